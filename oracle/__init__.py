@@ -1,0 +1,220 @@
+"""Plain CPU oracle of the event-based optical-flow hot path (arXiv 2112.10591).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_2112_10591_amd``) and never imports it.
+
+The arithmetic lives in ``ebof_oracle.c`` (plain C, double precision,
+single-threaded, compiled without FMA contraction); this module only loads it
+and marshals NumPy arrays.  Each wrapper names the passage of the paper that
+its C function follows.
+
+Parity status (what pins each function; the tests under ``tests/`` hold them):
+  edge_image        Sec. III-A       pinned: hand-built event lists, golden file
+  denoise / fill    Alg. 1 / Alg. 2  pinned: golden worked examples, identities
+  edt_separable     Sec. III-C       pinned: brute force (the definition)
+  surface           Eq. (1)-(3)      pinned: closed form values, saturation index
+  pyr_down          (flow pyramid)   pinned: scipy.ndimage mirror convolution
+  dis_flow          Sec. III-D       pinned: zero motion, linear-ramp sub-pixel
+                                     shifts, integer shifts, known translation
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ebof_oracle.c")
+_SO = os.path.join(_HERE, "_build", "libebof_oracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the system C compiler; return the .so path."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    os.makedirs(os.path.dirname(_SO), exist_ok=True)
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.oref_edge_image.argtypes = [i32, i32, P, P, P, i64, i64, i64, P]
+    lib.oref_edge_image.restype = i64
+    lib.oref_denoise.argtypes = [i32, i32, P, i32, P]
+    lib.oref_fill.argtypes = [i32, i32, P, i32, P]
+    lib.oref_edt_brute.argtypes = [i32, i32, P, P]
+    lib.oref_edt_brute_at.argtypes = [i32, i32, P, i32, i32]
+    lib.oref_edt_brute_at.restype = i32
+    lib.oref_edt_separable.argtypes = [i32, i32, P, P]
+    lib.oref_surface.argtypes = [i64, P, f64, P]
+    lib.oref_pyr_down.argtypes = [i32, i32, P, P]
+    lib.oref_dis_flow.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P]
+    lib.oref_dis_flow.restype = ctypes.c_int
+    lib.oref_patch_count.argtypes = [i32, i32, i32, i32]
+    lib.oref_patch_count.restype = i64
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Section III-A: window selection and the binary edge image
+# --------------------------------------------------------------------------
+def edge_image(W, H, x, y, t, t0, dt):
+    """Edge image of the events with t0 <= t < t0+dt (Sec. III-A); returns
+    (E uint8[H,W] of 0/1, number of events not binned)."""
+    x = np.ascontiguousarray(x, np.uint16)
+    y = np.ascontiguousarray(y, np.uint16)
+    t = np.ascontiguousarray(t, np.int64)
+    E = np.zeros((H, W), np.uint8)
+    dropped = _load().oref_edge_image(W, H, _ptr(x), _ptr(y), _ptr(t), len(x),
+                                      int(t0), int(dt), _ptr(E))
+    return E, int(dropped)
+
+
+def denoise(E, n_d):
+    """Algorithm 1 (denoising) with threshold N_d."""
+    E = np.ascontiguousarray(E, np.uint8)
+    H, W = E.shape
+    out = np.empty_like(E)
+    _load().oref_denoise(W, H, _ptr(E), int(n_d), _ptr(out))
+    return out
+
+
+def fill(Ed, n_f):
+    """Algorithm 2 (filling) with threshold N_f."""
+    Ed = np.ascontiguousarray(Ed, np.uint8)
+    H, W = Ed.shape
+    out = np.empty_like(Ed)
+    _load().oref_fill(W, H, _ptr(Ed), int(n_f), _ptr(out))
+    return out
+
+
+def denoise_fill(E, n_d, n_f):
+    """Denoising then filling, in that order (Sec. III-B)."""
+    return fill(denoise(E, n_d), n_f)
+
+
+# --------------------------------------------------------------------------
+# Section III-C: squared Euclidean distance to the closest edge pixel
+# --------------------------------------------------------------------------
+INT32_MAX = 2**31 - 1
+
+
+def edt_brute(E):
+    E = np.ascontiguousarray(E, np.uint8)
+    H, W = E.shape
+    D2 = np.empty((H, W), np.int32)
+    _load().oref_edt_brute(W, H, _ptr(E), _ptr(D2))
+    return D2
+
+
+def edt_brute_at(E, px, py):
+    E = np.ascontiguousarray(E, np.uint8)
+    H, W = E.shape
+    return int(_load().oref_edt_brute_at(W, H, _ptr(E), int(px), int(py)))
+
+
+def edt_separable(E):
+    E = np.ascontiguousarray(E, np.uint8)
+    H, W = E.shape
+    D2 = np.empty((H, W), np.int32)
+    _load().oref_edt_separable(W, H, _ptr(E), _ptr(D2))
+    return D2
+
+
+def surface(D2, alpha):
+    """Equation (1) on squared distances; float32 result."""
+    D2 = np.ascontiguousarray(D2, np.int32)
+    S = np.empty(D2.shape, np.float32)
+    _load().oref_surface(D2.size, _ptr(D2), float(alpha), _ptr(S))
+    return S
+
+
+def alpha_from_dsat(d_sat, eps=1.0 / 255.0):
+    """Equation (2): alpha = -d_sat / ln(eps); eq. (3) is eps = 1/255."""
+    return -float(d_sat) / float(np.log(eps))
+
+
+# --------------------------------------------------------------------------
+# Pyramid and flow
+# --------------------------------------------------------------------------
+def level_sizes(W, H, L):
+    sizes = []
+    for _ in range(L):
+        sizes.append((W, H))
+        W, H = (W + 1) // 2, (H + 1) // 2
+    return sizes
+
+
+def pyr_down(img):
+    img = np.ascontiguousarray(img, np.float32)
+    H, W = img.shape
+    out = np.empty(((H + 1) // 2, (W + 1) // 2), np.float32)
+    _load().oref_pyr_down(W, H, _ptr(img), _ptr(out))
+    return out
+
+
+def pyramid(S, L):
+    """Packed pyramid (level 0 first) as one float32 vector, plus the levels."""
+    levels = [np.ascontiguousarray(S, np.float32)]
+    for _ in range(L - 1):
+        levels.append(pyr_down(levels[-1]))
+    return np.concatenate([lv.ravel() for lv in levels]), levels
+
+
+def patch_count(W, H, ps=8, stride=4):
+    return int(_load().oref_patch_count(W, H, ps, stride))
+
+
+def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=1e-3,
+             want_patches=False):
+    """Dense inverse search flow from pyr0 (window k-1) to pyr1 (window k).
+    Returns float64 [2,H,W] (u, v), and per-level patch flows if asked."""
+    pyr0 = np.ascontiguousarray(pyr0, np.float32)
+    pyr1 = np.ascontiguousarray(pyr1, np.float32)
+    flow = np.empty((2, H, W), np.float64)
+    npatch = sum(patch_count(w, h, ps, stride) for w, h in level_sizes(W, H, L))
+    pu = np.empty((npatch, 2), np.float64) if want_patches else None
+    rc = _load().oref_dis_flow(W, H, L, _ptr(pyr0), _ptr(pyr1), ps, stride,
+                               iters, float(lam), _ptr(flow),
+                               _ptr(pu) if pu is not None else None)
+    if rc != 0:
+        raise ValueError("oref_dis_flow rejected its arguments")
+    if want_patches:
+        return flow, pu
+    return flow
+
+
+# --------------------------------------------------------------------------
+# The whole per-window path (events -> E_df -> D2 -> S -> pyramid)
+# --------------------------------------------------------------------------
+def window(W, H, x, y, t, t0, dt, n_d, n_f, alpha, L):
+    """Returns dict(E=raw edge image, Edf, D2, S, pyr (packed), dropped)."""
+    E, dropped = edge_image(W, H, x, y, t, t0, dt)
+    Edf = denoise_fill(E, n_d, n_f)
+    D2 = edt_separable(Edf)
+    S = surface(D2, alpha)
+    pyr, _ = pyramid(S, L)
+    return dict(E=E, Edf=Edf, D2=D2, S=S, pyr=pyr, dropped=dropped)

@@ -1,0 +1,506 @@
+/*
+ * ebof_oracle.c -- plain CPU oracle of the event-based optical-flow hot path
+ * of arXiv 2112.10591 (Brebion, Moreau, Davoine).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the GPU library.  Written for obviousness, not speed: every function
+ * follows the definition or the algorithm of the passage it cites, in double
+ * precision, single-threaded.
+ *
+ * Build: cc -O2 -ffp-contract=off -std=c99 -fPIC -shared ebof_oracle.c -lm
+ * (no FMA contraction, so every product and sum is rounded as written).
+ */
+#include "ebof_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Section III-A, accumulation: an edge image is a binary matrix telling    */
+/* whether a pixel produced at least one event during the window; polarity */
+/* plays no part.  Window reading: half-open [t0, t0 + dt).                 */
+/* ------------------------------------------------------------------------ */
+int64_t oref_edge_image(int32_t W, int32_t H, const uint16_t *x,
+                        const uint16_t *y, const int64_t *t, int64_t n,
+                        int64_t t0, int64_t dt, uint8_t *E)
+{
+    int64_t binned = 0;
+    memset(E, 0, (size_t)W * (size_t)H);
+    for (int64_t i = 0; i < n; i++) {
+        if (t[i] < t0 || t[i] >= t0 + dt)
+            continue;
+        if ((int32_t)x[i] >= W || (int32_t)y[i] >= H)
+            continue;
+        E[(size_t)y[i] * (size_t)W + x[i]] = 1;
+        binned++;
+    }
+    return n - binned;
+}
+
+/* 1 when (x, y) lies inside the image and is an edge pixel; pixels outside
+ * the image count as non-edges. */
+static int edge_at(const uint8_t *E, int32_t W, int32_t H, int32_t x,
+                   int32_t y)
+{
+    if (x < 0 || y < 0 || x >= W || y >= H)
+        return 0;
+    return E[(size_t)y * (size_t)W + x] != 0;
+}
+
+static int four_neighbours(const uint8_t *E, int32_t W, int32_t H, int32_t x,
+                           int32_t y)
+{
+    return edge_at(E, W, H, x - 1, y) + edge_at(E, W, H, x + 1, y) +
+           edge_at(E, W, H, x, y - 1) + edge_at(E, W, H, x, y + 1);
+}
+
+/* Algorithm 1: E_d starts as a copy of E; every edge pixel of E whose count
+ * of edge 4-neighbours (counted in E, never in E_d) is below N_d is removed. */
+void oref_denoise(int32_t W, int32_t H, const uint8_t *E, int32_t n_d,
+                  uint8_t *Ed)
+{
+    memcpy(Ed, E, (size_t)W * (size_t)H);
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            if (!edge_at(E, W, H, x, y))
+                continue;
+            if (four_neighbours(E, W, H, x, y) < n_d)
+                Ed[(size_t)y * W + x] = 0;
+        }
+}
+
+/* Algorithm 2: E_df starts as a copy of E_d; every non-edge pixel of E_d
+ * whose count of edge 4-neighbours (counted in E_d) is at least N_f becomes
+ * an edge. */
+void oref_fill(int32_t W, int32_t H, const uint8_t *Ed, int32_t n_f,
+               uint8_t *Edf)
+{
+    memcpy(Edf, Ed, (size_t)W * (size_t)H);
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            if (edge_at(Ed, W, H, x, y))
+                continue;
+            if (four_neighbours(Ed, W, H, x, y) >= n_f)
+                Edf[(size_t)y * W + x] = 1;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section III-C: d_Euc is the Euclidean distance to the closest edge pixel. */
+/* The oracle keeps its square, an integer.                                 */
+/* ------------------------------------------------------------------------ */
+int32_t oref_edt_brute_at(int32_t W, int32_t H, const uint8_t *E, int32_t px,
+                          int32_t py)
+{
+    int64_t best = INT32_MAX;
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            if (!E[(size_t)y * W + x])
+                continue;
+            int64_t dx = x - px, dy = y - py;
+            int64_t d = dx * dx + dy * dy;
+            if (d < best)
+                best = d;
+        }
+    return (int32_t)best;
+}
+
+void oref_edt_brute(int32_t W, int32_t H, const uint8_t *E, int32_t *D2)
+{
+    /* list the edge pixels once, then take the minimum for every pixel */
+    int64_t ne = 0;
+    for (int64_t i = 0; i < (int64_t)W * H; i++)
+        ne += E[i] != 0;
+    int32_t *ex = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne + 1));
+    int32_t *ey = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne + 1));
+    int64_t k = 0;
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++)
+            if (E[(size_t)y * W + x]) {
+                ex[k] = x;
+                ey[k] = y;
+                k++;
+            }
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            int64_t best = INT32_MAX;
+            for (int64_t i = 0; i < ne; i++) {
+                int64_t dx = ex[i] - x, dy = ey[i] - y;
+                int64_t d = dx * dx + dy * dy;
+                if (d < best)
+                    best = d;
+            }
+            D2[(size_t)y * W + x] = (int32_t)best;
+        }
+    free(ex);
+    free(ey);
+}
+
+static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0))
+        q -= 1;
+    return q;
+}
+
+/* Exact separable squared distance transform (the separable scheme of the
+ * distance-transform literature that Section III-C builds on):
+ *   phase 1, per column x: g(x, y) = min |y - y'| over edge pixels (x, y');
+ *   phase 2, per row y:    D2(x, y) = min_x' (x - x')^2 + g(x', y)^2,
+ * the second phase as the lower envelope of the parabolas
+ * F_x'(x) = (x - x')^2 + g(x', y)^2 over the columns x' that hold an edge.
+ * All integer arithmetic, so the result is exact. */
+void oref_edt_separable(int32_t W, int32_t H, const uint8_t *E, int32_t *D2)
+{
+    const int64_t INF = -1; /* marks "no edge in this column" */
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)W * (size_t)H);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * (size_t)W);
+    int64_t *site = (int64_t *)malloc(sizeof(int64_t) * (size_t)W);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)W);
+
+    /* phase 1: two sweeps per column */
+    for (int32_t x = 0; x < W; x++) {
+        int64_t last = INF;
+        for (int32_t y = 0; y < H; y++) {
+            if (E[(size_t)y * W + x])
+                last = y;
+            g[(size_t)y * W + x] = (last == INF) ? INF : (y - last);
+        }
+        last = INF;
+        for (int32_t y = H - 1; y >= 0; y--) {
+            if (E[(size_t)y * W + x])
+                last = y;
+            if (last != INF) {
+                int64_t d = last - y;
+                int64_t *gp = &g[(size_t)y * W + x];
+                if (*gp == INF || d < *gp)
+                    *gp = d;
+            }
+        }
+    }
+
+    /* phase 2: lower envelope per row */
+    for (int32_t y = 0; y < H; y++) {
+        int64_t q = -1; /* index of the last parabola in the envelope */
+        for (int32_t x = 0; x < W; x++) {
+            int64_t gv = g[(size_t)y * W + x];
+            f[x] = (gv == INF) ? INF : gv * gv;
+        }
+        for (int64_t u = 0; u < W; u++) {
+            if (f[u] == INF)
+                continue;
+            /* drop parabolas that u beats at the start of their segment */
+            while (q >= 0) {
+                int64_t s = site[q], at = start[q];
+                int64_t fs = (at - s) * (at - s) + f[s];
+                int64_t fu = (at - u) * (at - u) + f[u];
+                if (fs > fu)
+                    q--;
+                else
+                    break;
+            }
+            if (q < 0) {
+                q = 0;
+                site[0] = u;
+                start[0] = 0;
+            } else {
+                /* first integer x where parabola u is strictly below site[q]:
+                 * (x-u)^2+f(u) < (x-s)^2+f(s)  <=>  x > sep */
+                int64_t s = site[q];
+                int64_t sep = floor_div(u * u - s * s + f[u] - f[s], 2 * (u - s));
+                int64_t w = sep + 1;
+                if (w < W) {
+                    q++;
+                    site[q] = u;
+                    start[q] = w;
+                }
+            }
+        }
+        if (q < 0) { /* no edge pixel anywhere in the image */
+            for (int32_t x = 0; x < W; x++)
+                D2[(size_t)y * W + x] = INT32_MAX;
+            continue;
+        }
+        for (int64_t x = W - 1; x >= 0; x--) {
+            int64_t s = site[q];
+            int64_t d = (x - s) * (x - s) + f[s];
+            D2[(size_t)y * W + x] = (int32_t)d;
+            if (x == start[q])
+                q--;
+        }
+    }
+    free(g);
+    free(f);
+    free(site);
+    free(start);
+}
+
+/* Equation (1): d_exp = 1 - exp(-d_Euc / alpha). */
+void oref_surface(int64_t n, const int32_t *D2, double alpha, float *S)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double d = sqrt((double)D2[i]);
+        S[i] = (float)(1.0 - exp(-d / alpha));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian pyramid of a surface: binomial 5-tap blur then keep every second */
+/* pixel, reflect-101 border.                                               */
+/* ------------------------------------------------------------------------ */
+static int32_t reflect101(int32_t i, int32_t n)
+{
+    if (i < 0)
+        return -i;
+    if (i >= n)
+        return 2 * n - 2 - i;
+    return i;
+}
+
+void oref_pyr_down(int32_t W, int32_t H, const float *in, float *out)
+{
+    static const double k[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
+    int32_t Wo = (W + 1) / 2, Ho = (H + 1) / 2;
+    for (int32_t Y = 0; Y < Ho; Y++)
+        for (int32_t X = 0; X < Wo; X++) {
+            double acc = 0.0;
+            for (int32_t j = -2; j <= 2; j++)
+                for (int32_t i = -2; i <= 2; i++) {
+                    int32_t xx = reflect101(2 * X + i, W);
+                    int32_t yy = reflect101(2 * Y + j, H);
+                    acc += k[i + 2] * k[j + 2] * (double)in[(size_t)yy * W + xx];
+                }
+            out[(size_t)Y * Wo + X] = (float)(acc / 256.0);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frame-based flow between consecutive surfaces (Section III-D allows any   */
+/* frame-based method): dense inverse search.  Per level, coarse to fine:    */
+/* a regular grid of ps x ps patches at the given stride, each refined by    */
+/* inverse-compositional Lucas-Kanade (translation only), reset to its       */
+/* initial value when it moved more than ps, then densified into a per-pixel */
+/* flow by a weighted mean of the patches covering each pixel.              */
+/* ------------------------------------------------------------------------ */
+static double at_clamped(const float *I, int32_t W, int32_t H, int64_t x,
+                         int64_t y)
+{
+    if (x < 0)
+        x = 0;
+    if (x > W - 1)
+        x = W - 1;
+    if (y < 0)
+        y = 0;
+    if (y > H - 1)
+        y = H - 1;
+    return (double)I[(size_t)y * W + x];
+}
+
+/* bilinear interpolation at (sx, sy) with replicated borders: the four
+ * neighbouring sample indices are clamped into the image */
+static double bilinear(const float *I, int32_t W, int32_t H, double sx,
+                       double sy)
+{
+    double fx = floor(sx), fy = floor(sy);
+    double ax = sx - fx, ay = sy - fy;
+    /* indices beyond the border all clamp to the border, so the integer part
+     * can be limited before conversion without changing the result */
+    if (fx < -2.0)
+        fx = -2.0;
+    if (fx > W + 2.0)
+        fx = W + 2.0;
+    if (fy < -2.0)
+        fy = -2.0;
+    if (fy > H + 2.0)
+        fy = H + 2.0;
+    int64_t x0 = (int64_t)fx, y0 = (int64_t)fy;
+    double i00 = at_clamped(I, W, H, x0, y0);
+    double i10 = at_clamped(I, W, H, x0 + 1, y0);
+    double i01 = at_clamped(I, W, H, x0, y0 + 1);
+    double i11 = at_clamped(I, W, H, x0 + 1, y0 + 1);
+    return (1.0 - ay) * ((1.0 - ax) * i00 + ax * i10) +
+           ay * ((1.0 - ax) * i01 + ax * i11);
+}
+
+int64_t oref_patch_count(int32_t W, int32_t H, int32_t ps, int32_t stride)
+{
+    if (W < ps || H < ps || ps < 1 || stride < 1)
+        return 0;
+    int64_t nx = (W - ps + stride - 1) / stride + 1;
+    int64_t ny = (H - ps + stride - 1) / stride + 1;
+    return nx * ny;
+}
+
+/* origin of patch k along an axis of n pixels: k*stride, the last one
+ * clamped so that it ends on the border */
+static int32_t patch_origin(int32_t k, int32_t stride, int32_t n, int32_t ps)
+{
+    int32_t o = k * stride;
+    if (o > n - ps)
+        o = n - ps;
+    return o;
+}
+
+/* Densification: U(x) = sum_i w_i u_i / sum_i w_i over the patches i that
+ * contain x, w_i = 1 / max(1, 255 |I1(x + u_i) - I0(x)|).  The 255 puts the
+ * [0,1] surface on the 8-bit scale that the weight's unit threshold assumes. */
+static void densify(int32_t W, int32_t H, const float *I0, const float *I1,
+                    int32_t ps, int32_t stride, const double *pu,
+                    double *U /* 2*W*H */)
+{
+    int32_t nx = (W - ps + stride - 1) / stride + 1;
+    int32_t ny = (H - ps + stride - 1) / stride + 1;
+    size_t N = (size_t)W * H;
+    double *acc_w = (double *)calloc(N, sizeof(double));
+    double *acc_u = (double *)calloc(N, sizeof(double));
+    double *acc_v = (double *)calloc(N, sizeof(double));
+    for (int32_t ky = 0; ky < ny; ky++)
+        for (int32_t kx = 0; kx < nx; kx++) {
+            int32_t ox = patch_origin(kx, stride, W, ps);
+            int32_t oy = patch_origin(ky, stride, H, ps);
+            double u = pu[2 * ((size_t)ky * nx + kx)];
+            double v = pu[2 * ((size_t)ky * nx + kx) + 1];
+            for (int32_t j = 0; j < ps; j++)
+                for (int32_t i = 0; i < ps; i++) {
+                    int32_t x = ox + i, y = oy + j;
+                    double d = bilinear(I1, W, H, x + u, y + v) -
+                               (double)I0[(size_t)y * W + x];
+                    double s = 255.0 * fabs(d);
+                    double w = 1.0 / (s > 1.0 ? s : 1.0);
+                    size_t p = (size_t)y * W + x;
+                    acc_w[p] += w;
+                    acc_u[p] += w * u;
+                    acc_v[p] += w * v;
+                }
+        }
+    for (size_t p = 0; p < N; p++) {
+        U[p] = acc_u[p] / acc_w[p];
+        U[N + p] = acc_v[p] / acc_w[p];
+    }
+    free(acc_w);
+    free(acc_u);
+    free(acc_v);
+}
+
+int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                  const float *pyr1, int32_t ps, int32_t stride,
+                  int32_t iters, double lambda, double *flow,
+                  double *patch_uv)
+{
+    if (L < 1 || L > 16 || ps < 1 || stride < 1 || iters < 0)
+        return -1;
+    int32_t lw[16], lh[16];
+    size_t loff[16], poff[16];
+    size_t off = 0, pofs = 0;
+    int32_t w = W, h = H;
+    for (int32_t l = 0; l < L; l++) {
+        lw[l] = w;
+        lh[l] = h;
+        loff[l] = off;
+        poff[l] = pofs;
+        if (w < ps || h < ps)
+            return -1;
+        off += (size_t)w * h;
+        pofs += (size_t)oref_patch_count(w, h, ps, stride);
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+
+    double *Uc = NULL; /* dense flow of the coarser level, 2*Wc*Hc */
+    for (int32_t l = L - 1; l >= 0; l--) {
+        int32_t Wl = lw[l], Hl = lh[l];
+        const float *I0 = pyr0 + loff[l];
+        const float *I1 = pyr1 + loff[l];
+        int32_t nx = (Wl - ps + stride - 1) / stride + 1;
+        int32_t ny = (Hl - ps + stride - 1) / stride + 1;
+        double *pu = (double *)malloc(sizeof(double) * 2 * (size_t)nx * ny);
+        double *gx = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+        double *gy = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+        double *T = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+
+        for (int32_t ky = 0; ky < ny; ky++)
+            for (int32_t kx = 0; kx < nx; kx++) {
+                int32_t ox = patch_origin(kx, stride, Wl, ps);
+                int32_t oy = patch_origin(ky, stride, Hl, ps);
+
+                /* initial displacement: zero at the coarsest level, else
+                 * twice the coarser dense flow at the pixel nearest to the
+                 * patch centre */
+                double u0 = 0.0, v0 = 0.0;
+                if (l < L - 1) {
+                    int32_t Wc = lw[l + 1], Hc = lh[l + 1];
+                    int32_t cx = (ox + ps / 2) / 2, cy = (oy + ps / 2) / 2;
+                    if (cx > Wc - 1)
+                        cx = Wc - 1;
+                    if (cy > Hc - 1)
+                        cy = Hc - 1;
+                    u0 = 2.0 * Uc[(size_t)cy * Wc + cx];
+                    v0 = 2.0 * Uc[(size_t)Wc * Hc + (size_t)cy * Wc + cx];
+                }
+
+                /* template, its gradient (central differences, replicated
+                 * border) and the Gauss-Newton Hessian H = sum g g^T */
+                double hxx = 0.0, hxy = 0.0, hyy = 0.0;
+                for (int32_t j = 0; j < ps; j++)
+                    for (int32_t i = 0; i < ps; i++) {
+                        int32_t x = ox + i, y = oy + j;
+                        int32_t q = j * ps + i;
+                        T[q] = (double)I0[(size_t)y * Wl + x];
+                        gx[q] = 0.5 * (at_clamped(I0, Wl, Hl, x + 1, y) -
+                                       at_clamped(I0, Wl, Hl, x - 1, y));
+                        gy[q] = 0.5 * (at_clamped(I0, Wl, Hl, x, y + 1) -
+                                       at_clamped(I0, Wl, Hl, x, y - 1));
+                        hxx += gx[q] * gx[q];
+                        hxy += gx[q] * gy[q];
+                        hyy += gy[q] * gy[q];
+                    }
+                double a = hxx + lambda, c = hyy + lambda, bb = hxy;
+                double det = a * c - bb * bb;
+
+                /* inverse-compositional iterations, a fixed number of them */
+                double u = u0, v = v0;
+                for (int32_t it = 0; it < iters; it++) {
+                    double bx = 0.0, by = 0.0;
+                    for (int32_t j = 0; j < ps; j++)
+                        for (int32_t i = 0; i < ps; i++) {
+                            int32_t q = j * ps + i;
+                            double r = bilinear(I1, Wl, Hl, ox + i + u,
+                                                oy + j + v) - T[q];
+                            bx += gx[q] * r;
+                            by += gy[q] * r;
+                        }
+                    /* (H + lambda I) d = b, solved by the 2x2 inverse */
+                    double dx = (c * bx - bb * by) / det;
+                    double dy = (a * by - bb * bx) / det;
+                    u -= dx;
+                    v -= dy;
+                }
+                /* outlier reset: a patch that moved more than its size
+                 * returns to its initial displacement */
+                double mu = u - u0, mv = v - v0;
+                if (sqrt(mu * mu + mv * mv) > (double)ps) {
+                    u = u0;
+                    v = v0;
+                }
+                pu[2 * ((size_t)ky * nx + kx)] = u;
+                pu[2 * ((size_t)ky * nx + kx) + 1] = v;
+            }
+        if (patch_uv)
+            memcpy(patch_uv + 2 * poff[l], pu, sizeof(double) * 2 * (size_t)nx * ny);
+
+        double *Ul = (double *)malloc(sizeof(double) * 2 * (size_t)Wl * Hl);
+        densify(Wl, Hl, I0, I1, ps, stride, pu, Ul);
+        free(Uc);
+        Uc = Ul;
+        free(pu);
+        free(gx);
+        free(gy);
+        free(T);
+    }
+    memcpy(flow, Uc, sizeof(double) * 2 * (size_t)W * H);
+    free(Uc);
+    return 0;
+}

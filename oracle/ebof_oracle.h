@@ -1,0 +1,88 @@
+/*
+ * ebof_oracle.h -- plain CPU oracle of the event-based optical-flow hot path
+ * (Brebion, Moreau, Davoine, "Real-Time Optical Flow for Vehicular Perception
+ * with Low- and High-Resolution Event Cameras", arXiv 2112.10591).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header, table or helper with the GPU
+ * library and includes none of its files.
+ *
+ * Conventions shared with the GPU library only through the documented data
+ * layout (not through code):
+ *   - images are row-major, pitch = width, pixel (x, y) at index y*W + x;
+ *   - a pyramid of L levels stores level 0 first, then level 1, ... each
+ *     tightly packed; level l+1 has size ((W_l+1)/2, (H_l+1)/2);
+ *   - the squared distance of a pixel in an image with no edge pixel at all is
+ *     INT32_MAX;
+ *   - flows are two planes (u then v), u along +x (right), v along +y (down).
+ *
+ * Floating point: every intermediate is double precision.  Values that the
+ * method stores as FP32 (the distance surface and its pyramid levels) are
+ * rounded to float once, from the double result.
+ */
+#ifndef EBOF_ORACLE_H
+#define EBOF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Section III-A: binary edge image of the events with t0 <= t < t0 + dt.
+ * Polarity is not an input (the paper ignores it).  Events outside the
+ * window or outside the W x H sensor are not binned.  E gets W*H bytes of
+ * 0/1.  Returns the number of events not binned. */
+int64_t oref_edge_image(int32_t W, int32_t H, const uint16_t *x,
+                        const uint16_t *y, const int64_t *t, int64_t n,
+                        int64_t t0, int64_t dt, uint8_t *E);
+
+/* Algorithm 1 (denoising): an edge pixel with fewer than n_d edge pixels
+ * among its 4 direct neighbours in E stops being an edge.  Reads E only. */
+void oref_denoise(int32_t W, int32_t H, const uint8_t *E, int32_t n_d,
+                  uint8_t *Ed);
+
+/* Algorithm 2 (filling): a non-edge pixel with at least n_f edge pixels
+ * among its 4 direct neighbours in Ed becomes an edge.  Reads Ed only. */
+void oref_fill(int32_t W, int32_t H, const uint8_t *Ed, int32_t n_f,
+               uint8_t *Edf);
+
+/* Squared Euclidean distance to the closest edge pixel (the d_Euc of
+ * equation (1), squared), by its definition: a minimum over all edge pixels.
+ * O(W*H*#edges); for small images and for sampled pixels. */
+void oref_edt_brute(int32_t W, int32_t H, const uint8_t *E, int32_t *D2);
+int32_t oref_edt_brute_at(int32_t W, int32_t H, const uint8_t *E, int32_t px,
+                          int32_t py);
+
+/* The same quantity by the exact separable method (column distances, then a
+ * lower envelope of parabolas per row), the family of algorithms Section
+ * III-C names for its implementation. */
+void oref_edt_separable(int32_t W, int32_t H, const uint8_t *E, int32_t *D2);
+
+/* Equation (1): S = 1 - exp(-sqrt(D2) / alpha), rounded once to float. */
+void oref_surface(int64_t n, const int32_t *D2, double alpha, float *S);
+
+/* One pyramid reduction: out(X,Y) = sum_{i,j=-2..2} k_i k_j in(2X+i, 2Y+j),
+ * k = [1 4 6 4 1]/16, reflect-101 border.  out is ((W+1)/2) x ((H+1)/2). */
+void oref_pyr_down(int32_t W, int32_t H, const float *in, float *out);
+
+/* Dense inverse search flow from pyramid pyr0 (reference, window k-1) to
+ * pyramid pyr1 (window k), both L levels in the packed layout above.
+ * flow gets 2*W*H doubles (u plane, v plane) at level 0.  patch_uv, when not
+ * NULL, gets the final patch displacements of every level, level 0 first,
+ * patches row-major, (u, v) interleaved.  Returns 0, or -1 on bad arguments
+ * (a level smaller than the patch, ps < 1, stride < 1, iters < 0). */
+int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                  const float *pyr1, int32_t ps, int32_t stride,
+                  int32_t iters, double lambda, double *flow,
+                  double *patch_uv);
+
+/* Number of patches of one level: ceil((W-ps)/stride)+1 by the same in y. */
+int64_t oref_patch_count(int32_t W, int32_t H, int32_t ps, int32_t stride);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBOF_ORACLE_H */

@@ -1,0 +1,362 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests call the GPU library.  Each check is independent of the
+oracle's own code: hand-derived worked examples (tests/golden), brute force
+on tiny inputs, closed forms, invariants, and library routines for the steps
+that reduce to one (scipy's mirror-mode correlation for the pyramid).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_10591_amd import synth
+
+
+# --------------------------------------------------------------------------
+# golden-file readers
+# --------------------------------------------------------------------------
+def _grid(lines):
+    return np.array([[1 if c == "X" else 0 for c in ln] for ln in lines], np.uint8)
+
+
+def read_denoise_fill(path):
+    cases, cur, mode = [], None, None
+    for raw in open(path):
+        ln = raw.rstrip("\n")
+        if not ln or ln.startswith("#"):
+            continue
+        if ln.startswith("case "):
+            cur = dict(name=ln[5:], input=[], expect=[])
+            cases.append(cur)
+            mode = None
+        elif ln.startswith("params "):
+            cur["n_d"], cur["n_f"] = map(int, ln.split()[1:])
+        elif ln in ("input", "expect"):
+            mode = ln
+        else:
+            cur[mode].append(ln)
+    for c in cases:
+        c["input"] = _grid(c["input"])
+        c["expect"] = _grid(c["expect"])
+    return cases
+
+
+def read_edge_events(path):
+    d, mode, ev, exp = {}, None, [], []
+    for raw in open(path):
+        ln = raw.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        if ln.startswith("sensor"):
+            d["W"], d["H"] = map(int, ln.split()[1:])
+        elif ln.startswith("window"):
+            d["t0"], d["dt"] = map(int, ln.split()[1:])
+        elif ln.startswith("dropped"):
+            d["dropped"] = int(ln.split()[1])
+        elif ln in ("events", "expect"):
+            mode = ln
+        elif mode == "events":
+            ev.append(list(map(int, ln.split())))
+        else:
+            exp.append(ln)
+    ev = np.array(ev, np.int64)
+    d["x"], d["y"], d["t"], d["p"] = ev[:, 0], ev[:, 1], ev[:, 2], ev[:, 3]
+    d["expect"] = _grid(exp)
+    return d
+
+
+# --------------------------------------------------------------------------
+# Sec. III-A edge image
+# --------------------------------------------------------------------------
+def test_edge_image_golden(golden_dir):
+    g = read_edge_events(os.path.join(golden_dir, "edge_events.txt"))
+    E, dropped = oracle.edge_image(g["W"], g["H"], g["x"], g["y"], g["t"], g["t0"], g["dt"])
+    assert np.array_equal(E, g["expect"])
+    assert dropped == g["dropped"]
+
+
+def test_edge_image_order_and_duplicates_irrelevant():
+    rng = np.random.default_rng(0)
+    W, H, n = 37, 23, 500
+    x = rng.integers(0, W + 3, n)
+    y = rng.integers(0, H + 2, n)
+    t = rng.integers(0, 2000, n)
+    E1, d1 = oracle.edge_image(W, H, x, y, t, 500, 1000)
+    perm = rng.permutation(n)
+    E2, d2 = oracle.edge_image(W, H, np.r_[x[perm], x], np.r_[y[perm], y],
+                               np.r_[t[perm], t], 500, 1000)
+    assert np.array_equal(E1, E2) and d2 == 2 * d1
+    # brute-force set semantics
+    ref = np.zeros((H, W), np.uint8)
+    keep = (t >= 500) & (t < 1500) & (x < W) & (y < H)
+    ref[y[keep], x[keep]] = 1
+    assert np.array_equal(E1, ref)
+    assert d1 == n - keep.sum()
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 / Alg. 2
+# --------------------------------------------------------------------------
+def test_denoise_fill_golden(golden_dir):
+    cases = read_denoise_fill(os.path.join(golden_dir, "denoise_fill.txt"))
+    assert len(cases) >= 8
+    for c in cases:
+        got = oracle.denoise_fill(c["input"], c["n_d"], c["n_f"])
+        assert np.array_equal(got, c["expect"]), c["name"]
+
+
+def test_denoise_fill_disable_values():
+    """N_d = 0 disables denoising and N_f = 5 disables filling (Sec. III-B)."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        E = (rng.random((rng.integers(1, 30), rng.integers(1, 30))) < rng.random()).astype(np.uint8)
+        assert np.array_equal(oracle.denoise(E, 0), E)
+        assert np.array_equal(oracle.fill(E, 5), E)
+
+
+def test_denoise_fill_monotone():
+    """Denoising only removes, filling only adds."""
+    rng = np.random.default_rng(2)
+    for nd in range(5):
+        for nf in range(1, 6):
+            E = (rng.random((31, 17)) < 0.3).astype(np.uint8)
+            Ed = oracle.denoise(E, nd)
+            Edf = oracle.fill(Ed, nf)
+            assert np.all(Ed <= E) and np.all(Edf >= Ed)
+
+
+# --------------------------------------------------------------------------
+# Sec. III-C exact squared distance
+# --------------------------------------------------------------------------
+def test_edt_separable_matches_brute_force():
+    rng = np.random.default_rng(3)
+    for trial in range(300):
+        W, H = int(rng.integers(1, 25)), int(rng.integers(1, 25))
+        kind = trial % 5
+        if kind == 0:
+            E = np.zeros((H, W), np.uint8)
+        elif kind == 1:
+            E = np.zeros((H, W), np.uint8)
+            E[rng.integers(0, H), rng.integers(0, W)] = 1
+        elif kind == 2:
+            E = np.ones((H, W), np.uint8)
+        else:
+            E = (rng.random((H, W)) < rng.random() * 0.3).astype(np.uint8)
+        assert np.array_equal(oracle.edt_separable(E), oracle.edt_brute(E)), (W, H, kind)
+
+
+def test_edt_closed_forms():
+    W, H = 13, 9
+    E = np.zeros((H, W), np.uint8)
+    E[3, 5] = 1
+    yy, xx = np.mgrid[0:H, 0:W]
+    assert np.array_equal(oracle.edt_separable(E), (xx - 5) ** 2 + (yy - 3) ** 2)
+    assert np.all(oracle.edt_separable(np.zeros((H, W), np.uint8)) == oracle.INT32_MAX)
+    assert np.all(oracle.edt_separable(np.ones((H, W), np.uint8)) == 0)
+    # two edge pixels: the minimum of the two paraboloids
+    E[7, 0] = 1
+    ref = np.minimum((xx - 5) ** 2 + (yy - 3) ** 2, xx ** 2 + (yy - 7) ** 2)
+    assert np.array_equal(oracle.edt_separable(E), ref)
+
+
+def test_edt_brute_at_samples_large_image():
+    rng = np.random.default_rng(4)
+    E = (rng.random((260, 346)) < 0.01).astype(np.uint8)
+    D2 = oracle.edt_separable(E)
+    for _ in range(50):
+        x, y = int(rng.integers(0, 346)), int(rng.integers(0, 260))
+        assert D2[y, x] == oracle.edt_brute_at(E, x, y)
+
+
+# --------------------------------------------------------------------------
+# Eq. (1)-(3): the inverse exponential distance surface
+# --------------------------------------------------------------------------
+def test_alpha_from_dsat_matches_paper_constant():
+    """Eq. (3) prints alpha ~ d_sat / 5.541 (eps = 1/255), and Sec. IV-A uses
+    alpha = 1.08 for d_sat = 6 px."""
+    assert abs(oracle.alpha_from_dsat(1.0) * 5.541 - 1.0) < 1e-4
+    assert abs(oracle.alpha_from_dsat(6.0) - 1.08) < 5e-3
+
+
+def test_surface_closed_forms():
+    d2 = np.array([0, 1, 4, 36], np.int32)
+    # alpha = 1 and 2 are the two curves of Fig. 4: 1 - e^-x and 1 - e^-x/2
+    s1 = oracle.surface(d2, 1.0)
+    s2 = oracle.surface(d2, 2.0)
+    inv_e = 0.36787944117144233  # 1/e
+    assert s1[0] == 0.0 and s2[0] == 0.0          # zero on edge pixels
+    assert s1[1] == np.float32(1 - inv_e)         # d = 1, alpha = 1
+    assert s2[2] == np.float32(1 - inv_e)         # d = 2, alpha = 2
+    # Eq. (2): at d = d_sat the gap to 1 is eps = 1/255 exactly
+    a = oracle.alpha_from_dsat(6.0)
+    s = oracle.surface(np.array([36], np.int32), a)
+    assert abs((1.0 - float(s[0])) - 1.0 / 255.0) < 1e-7
+
+
+def test_surface_monotone_and_saturates():
+    alpha = float(np.float32(1.08))
+    d2 = np.arange(0, 2000, dtype=np.int32)
+    s = oracle.surface(d2, alpha)
+    assert np.all(np.diff(s) >= 0) and s[0] == 0.0
+    # first squared distance whose float32 value is exactly 1: 351 for 1.08
+    k = int(np.argmax(s == np.float32(1.0)))
+    assert k == 351 and np.all(s[k:] == 1.0) and s[k - 1] < 1.0
+    assert oracle.surface(np.array([oracle.INT32_MAX], np.int32), alpha)[0] == 1.0
+
+
+# --------------------------------------------------------------------------
+# pyramid: binomial 5-tap, reflect-101, decimate by two
+# --------------------------------------------------------------------------
+def test_pyr_down_matches_scipy_mirror_correlation():
+    ndi = pytest.importorskip("scipy.ndimage")
+    rng = np.random.default_rng(5)
+    k = np.array([1, 4, 6, 4, 1], np.float64) / 16.0
+    for H, W in [(9, 9), (10, 13), (33, 17), (64, 48), (65, 87)]:
+        img = rng.random((H, W)).astype(np.float32)
+        ref = ndi.correlate(img.astype(np.float64), np.outer(k, k), mode="mirror")[::2, ::2]
+        got = oracle.pyr_down(img)
+        assert got.shape == ((H + 1) // 2, (W + 1) // 2)
+        assert np.array_equal(got, ref.astype(np.float32))
+
+
+def test_pyr_down_invariants():
+    c = np.full((20, 31), 0.7, np.float32)
+    assert np.all(oracle.pyr_down(c) == np.float32(0.7))
+    yy, xx = np.mgrid[0:40, 0:50]
+    ramp = (0.01 * xx + 0.02 * yy).astype(np.float64)
+    out = oracle.pyr_down(ramp.astype(np.float32))
+    Y, X = np.mgrid[0:20, 0:25]
+    interior = (slice(1, 19), slice(1, 24))
+    assert np.allclose(out[interior], (0.01 * 2 * X + 0.02 * 2 * Y)[interior], atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# dense inverse search
+# --------------------------------------------------------------------------
+def _smooth_texture(H, W, seed):
+    ndi = pytest.importorskip("scipy.ndimage")
+    rng = np.random.default_rng(seed)
+    img = ndi.gaussian_filter(rng.random((H, W)), 2.0)
+    img = (img - img.min()) / (img.max() - img.min())
+    return img.astype(np.float32)
+
+
+def _pyr(img, L):
+    return oracle.pyramid(img, L)[0]
+
+
+def test_dis_zero_motion_is_exactly_zero():
+    img = _smooth_texture(70, 90, 6)
+    p = _pyr(img, 3)
+    f = oracle.dis_flow(p, p, 90, 70, 3)
+    assert np.all(f == 0.0)
+
+
+def test_dis_constant_images_keep_zero():
+    c = np.ones((40, 40), np.float32)
+    p = _pyr(c, 2)
+    assert np.all(oracle.dis_flow(p, p.copy(), 40, 40, 2) == 0.0)
+
+
+@pytest.mark.parametrize("d", [(2, -1), (-3, 1), (1, 3)])
+def test_dis_integer_shift_recovered(d):
+    H, W = 96, 128
+    img = _smooth_texture(H, W, 7)
+    ix = np.clip(np.arange(W) - d[0], 0, W - 1)
+    iy = np.clip(np.arange(H) - d[1], 0, H - 1)
+    img1 = img[iy][:, ix]
+    f = oracle.dis_flow(_pyr(img, 3), _pyr(img1, 3), W, H, 3)
+    inner = (slice(12, H - 12), slice(12, W - 12))
+    e = np.hypot(f[0][inner] - d[0], f[1][inner] - d[1])
+    assert np.median(e) < 1e-6 and np.mean(e < 0.05) > 0.98
+
+
+@pytest.mark.parametrize("d", [(0.3, 0.2), (-0.45, 0.7)])
+def test_dis_bilinear_image_subpixel_shift(d):
+    """Bilinear interpolation is exact on a bilinear image c0+c1x+c2y+c3xy,
+    whose gradient varies enough for a full-rank Hessian, so inverse search
+    recovers a sub-pixel shift of it (one level, away from the border)."""
+    H, W = 40, 48
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+
+    def img(x, y):  # a saddle: strong cross term, well-conditioned patches
+        return 1.0 + 0.01 * x + 0.008 * y + 0.01 * (x - 24) * (y - 20)
+
+    I0 = img(xx, yy).astype(np.float32)
+    I1 = img(xx - d[0], yy - d[1]).astype(np.float32)
+    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, want_patches=True)
+    nx = (W - 8 + 3) // 4 + 1
+    ny = (H - 8 + 3) // 4 + 1
+    pu = pu.reshape(ny, nx, 2)[1:-1, 1:-1]  # patches whose samples stay inside
+    # float32 storage of the image limits the attainable accuracy
+    assert np.max(np.abs(pu[..., 0] - d[0])) < 1e-5
+    assert np.max(np.abs(pu[..., 1] - d[1])) < 1e-5
+
+
+def test_dis_linear_ramp_recovers_normal_component():
+    """On a linear ramp the Hessian has rank one (aperture problem): only the
+    displacement along the gradient is determined, and it is recovered."""
+    H, W = 40, 48
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, d = 0.011, 0.007, (0.3, 0.2)
+    I0 = (0.1 + a * xx + b * yy).astype(np.float32)
+    I1 = (0.1 + a * (xx - d[0]) + b * (yy - d[1])).astype(np.float32)
+    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, want_patches=True)
+    nx = (W - 8 + 3) // 4 + 1
+    ny = (H - 8 + 3) // 4 + 1
+    pu = pu.reshape(ny, nx, 2)[1:-1, 1:-1]
+    normal = (a * (pu[..., 0] - d[0]) + b * (pu[..., 1] - d[1])) / math.hypot(a, b)
+    assert np.max(np.abs(normal)) < 1e-4
+
+
+def test_dis_single_patch_image_densifies_to_patch_flow():
+    """An 8x8 image is one patch; every pixel's densified flow is that
+    patch's displacement, whatever the weights."""
+    img = _smooth_texture(8, 8, 8)
+    img1 = np.roll(img, 1, axis=1)
+    f, pu = oracle.dis_flow(img.ravel(), img1.ravel(), 8, 8, 1, want_patches=True)
+    assert np.allclose(f[0], pu[0, 0], rtol=0, atol=1e-12)
+    assert np.allclose(f[1], pu[0, 1], rtol=0, atol=1e-12)
+
+
+def test_dis_rejects_levels_smaller_than_patch():
+    p = np.zeros(12 * 12 + 6 * 6, np.float32)
+    with pytest.raises(ValueError):
+        oracle.dis_flow(p, p, 12, 12, 2)
+
+
+def test_dis_known_translation_c1():
+    """Seeded C1 (346x260, 40 segments translating by (+2.5, -1.5) px per
+    window, 5 % noise): the median flow over the reference edge pixels more
+    than 16 px from the border lies within 0.05 px of the translation."""
+    s = synth.c1_stream(0)
+    W, H = s.W, s.H
+    r = []
+    for k in (0, 1):
+        w = s.window(k)
+        r.append(oracle.window(W, H, w["x"], w["y"], w["t"], w["t0"], synth.DT_US, 1, 4, 1.08, 3))
+    f = oracle.dis_flow(r[0]["pyr"], r[1]["pyr"], W, H, 3)
+    m = r[0]["Edf"][16:-16, 16:-16].astype(bool)
+    u = f[0][16:-16, 16:-16][m]
+    v = f[1][16:-16, 16:-16][m]
+    assert abs(np.median(u) - 2.5) <= 0.05
+    assert abs(np.median(v) + 1.5) <= 0.05
+
+
+# --------------------------------------------------------------------------
+# generator
+# --------------------------------------------------------------------------
+def test_generator_deterministic_and_order_free():
+    a = synth.c1_stream(0)
+    b = synth.c1_stream(0)
+    w1b = b.window(1)
+    w1a = a.window(1)
+    for key in ("x", "y", "t", "p"):
+        assert np.array_equal(w1a[key], w1b[key])
+    assert len(w1a["x"]) == 20_000
+    assert np.all(np.diff(w1a["t"]) >= 0)
+    assert w1a["t"].min() >= w1a["t0"] and w1a["t"].max() < w1a["t0"] + synth.DT_US
+    assert w1a["x"].max() < 346 and w1a["y"].max() < 260
