@@ -1,0 +1,252 @@
+/*
+ * ebof.h -- C ABI of the MI355X (gfx950) event-based optical-flow hot path.
+ *
+ * The method is the one of Brebion, Moreau and Davoine, "Real-Time Optical
+ * Flow for Vehicular Perception with Low- and High-Resolution Event Cameras"
+ * (arXiv 2112.10591): events of one time window become a binary edge image
+ * (Sec. III-A), which is denoised and filled (Sec. III-B, Alg. 1 and 2); the
+ * exact Euclidean distance to the closest edge pixel turns it into the
+ * inverse exponential distance surface (Sec. III-C, eq. 1-3); a frame-based
+ * dense flow then runs between consecutive surfaces and is restricted to the
+ * edge pixels (Sec. III-D).  The frame-based flow here is dense inverse
+ * search (coarse-to-fine patch inverse search with Lucas-Kanade refinement
+ * and patch densification), which Sec. III-D allows in place of the paper's
+ * own choice.
+ *
+ * Conventions
+ *   - Every pointer argument named *_dev or documented "device" is device
+ *     memory of the context's GPU, owned by the caller; the library never
+ *     frees it.  Stage calls are asynchronous on the caller's HIP stream
+ *     (passed as void*, NULL = the null stream): inputs must stay alive and
+ *     outputs untouched until that stream reaches the work.
+ *   - Images are row-major with pitch = width: pixel (x, y) is element
+ *     y*width + x.  x grows to the right, y downwards.
+ *   - A pyramid of L levels is one float array: level 0 (width x height)
+ *     first, then level 1 ((width+1)/2 x (height+1)/2), and so on, each
+ *     level tightly packed.  ebof_pyramid_floats() gives its length P.
+ *   - A flow is two float planes, u (along +x) then v (along +y), each
+ *     width*height, in pixels of level 0.
+ *   - Every call returns a status (EBOF_OK or a negative EBOF_E_*); nothing
+ *     throws across the ABI.  On failure ebof_last_error() describes it.
+ *   - All library-owned device memory comes from the caller's arena given to
+ *     ebof_create(); the library calls no device allocator after that,
+ *     except for pinned host staging of the serving calls.
+ */
+#ifndef EBOF_H
+#define EBOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define EBOF_OK 0
+#define EBOF_NO_FLOW 1      /* served window accepted, no previous window yet */
+#define EBOF_E_INVAL (-1)   /* bad argument or parameter                      */
+#define EBOF_E_NOMEM (-2)   /* the arena cannot hold what the call needs      */
+#define EBOF_E_AGAIN (-3)   /* not done yet / queue full: try again later     */
+#define EBOF_E_NOTFOUND (-4)/* unknown stream id or ticket                    */
+#define EBOF_E_DEVICE (-5)  /* a HIP call failed; the context is unusable     */
+#define EBOF_E_STATE (-6)   /* call not allowed in the current state          */
+
+/* ---- limits ------------------------------------------------------------ */
+#define EBOF_MAX_DIM 8192   /* width and height are at most this            */
+#define EBOF_MIN_DIM 8      /* and at least the patch size                  */
+#define EBOF_MAX_LEVELS 8
+#define EBOF_PATCH 8        /* the only supported patch size                */
+#define EBOF_MAX_BATCH 1024 /* windows per ebof_run_batch call              */
+
+/* ---- flags of ebof_params.flags ------------------------------------------ */
+#define EBOF_MASK_FLOW 1u   /* write 0 flow outside the mask (Sec. III-D)   */
+
+typedef struct ebof_ctx ebof_ctx; /* opaque, library-owned */
+
+/* Parameters of one sensor / stream.  Plain data; struct_size must be
+ * sizeof(ebof_params) (lets the struct grow). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t width, height; /* sensor size in pixels                        */
+    int64_t dt_us;         /* window length Delta-T (Sec. III-A)             */
+    int32_t n_d;           /* denoising threshold N_d, Alg. 1; 0 disables   */
+    int32_t n_f;           /* filling threshold N_f, Alg. 2; 5 disables     */
+    float alpha;           /* spreading parameter of eq. (1), > 0           */
+    int32_t levels;        /* pyramid levels L, 1..EBOF_MAX_LEVELS           */
+    int32_t patch;         /* patch size, must be EBOF_PATCH                 */
+    int32_t stride;        /* patch grid stride, 1..8                        */
+    int32_t iters;         /* inverse-search iterations per patch, 0..1024   */
+    float lambda_reg;      /* Tikhonov term added to the patch Hessian, > 0  */
+    uint32_t flags;        /* EBOF_MASK_FLOW                                 */
+} ebof_params;
+
+/* Defaults of Sec. IV-A for a sensor of the given size: N_d = 1, N_f = 4 up to
+ * 100k pixels (the 346x260 setting), N_d = 2, N_f = 3 above (1280x720);
+ * alpha = 1.08 (d_sat = 6 px, eq. 3); dt = 10 ms; levels = 3 up to 100k
+ * pixels, else 4 (each level at least 8 px); patch 8, stride 4, 16 iterations,
+ * lambda_reg 1e-3, no flags.  Returns EBOF_E_INVAL for a size out of range. */
+int ebof_params_default(int32_t width, int32_t height, ebof_params *out);
+
+/* EBOF_OK when the parameters are usable, else EBOF_E_INVAL.  Checks: sizes
+ * in [EBOF_MIN_DIM, EBOF_MAX_DIM], every pyramid level at least the patch
+ * size, n_d and n_f in [0, 5], alpha and lambda_reg finite and > 0, alpha
+ * small enough for a squared-distance lookup table of at most 2^22 entries,
+ * patch == 8, stride in [1, 8], iters in [0, 1024], dt_us > 0. */
+int ebof_validate(const ebof_params *p);
+
+/* Length P (in floats) of the pyramid of p, or -1 if p is invalid. */
+int64_t ebof_pyramid_floats(const ebof_params *p);
+
+/* Arena bytes the context needs for the scratch of one window of p (edge
+ * staging, column masks, column distances, patch flows), or -1. */
+int64_t ebof_window_scratch_bytes(const ebof_params *p);
+
+/* ---- context ------------------------------------------------------------- */
+/* Creates a context on HIP device `device`.  `arena` is caller-owned device
+ * memory of arena_bytes bytes (256-byte aligned) from which the library takes
+ * every device buffer it needs (lookup tables, scratch, per-stream state); it
+ * must outlive the context.  Returns EBOF_E_INVAL for a NULL/misaligned arena
+ * or a bad device. */
+int ebof_create(int device, void *arena, size_t arena_bytes, ebof_ctx **out);
+
+/* Waits for the context's own work, releases its host resources.  The arena
+ * is not touched. */
+int ebof_destroy(ebof_ctx *ctx);
+
+/* Description of the last failure of a call on ctx made by this thread
+ * (never NULL; "" when none). */
+const char *ebof_last_error(const ebof_ctx *ctx);
+
+/* ---- stage calls (one window, caller's stream) --------------------------
+ * The context's scratch for a given parameter set is shared by all stage
+ * calls with that set: order such calls on one stream. */
+
+/* Sec. III-A + III-B: bins the events with t0_us <= t < t0_us + dt_us into a
+ * binary edge image (polarity is not an input; events off the sensor or off
+ * the window are not binned), then applies Alg. 1 (N_d) and Alg. 2 (N_f) in
+ * that order.  x, y, t: n device values (SoA); n may be 0.  edge_out: device
+ * width*height bytes, receives the denoised and filled image E_df as 0/1.
+ * n_dropped_dev: NULL, or a device uint64 to which the number of events not
+ * binned is ADDED (the caller zeroes it). */
+int ebof_bin_events(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
+                    const uint16_t *y, const int64_t *t, int64_t n,
+                    int64_t t0_us, uint8_t *edge_out,
+                    uint64_t *n_dropped_dev, void *hip_stream);
+
+/* Sec. III-C, eq. (1): from a 0/1 edge image (device, width*height bytes),
+ * the exact squared Euclidean distance D2 to the closest edge pixel (int32;
+ * INT32_MAX everywhere when the image has no edge pixel), the surface
+ * S = 1 - exp(-sqrt(D2)/alpha) rounded once to float, and its Gaussian
+ * pyramid: each level is the 5x5 binomial ([1 4 6 4 1]/16 per axis,
+ * reflect-101 border) of the level above, sampled at even pixels.
+ * d2_out: NULL or device width*height int32.  pyr_out: device P floats;
+ * level 0 is S. */
+int ebof_edt_surface(ebof_ctx *ctx, const ebof_params *p,
+                     const uint8_t *edge, int32_t *d2_out, float *pyr_out,
+                     void *hip_stream);
+
+/* Sec. III-D: dense flow from the surface pyramid of window k-1 (pyr_prev,
+ * the reference) to that of window k (pyr_curr), both device, P floats, by
+ * dense inverse search: for levels L-1 .. 0, a grid of 8x8 patches at the
+ * given stride (origins k*stride, the last clamped to the border) each runs
+ * `iters` inverse-compositional Lucas-Kanade steps (bilinear sampling with
+ * replicated border, central-difference template gradient, Hessian plus
+ * lambda_reg*I), returns to its initial displacement when it moved more than
+ * the patch size, and the per-pixel flow is the mean of the covering patch
+ * displacements weighted by 1/max(1, 255*|I1(x+u)-I0(x)|).  A patch starts
+ * from twice the coarser level's flow at the pixel nearest its centre, from 0
+ * at the coarsest level.  flow_out: device 2*width*height floats.  mask: NULL,
+ * or device width*height bytes (the edge image of window k-1); with
+ * EBOF_MASK_FLOW set the flow is written as 0 where the mask is 0. */
+int ebof_flow(ebof_ctx *ctx, const ebof_params *p, const float *pyr_prev,
+              const float *pyr_curr, const uint8_t *mask, float *flow_out,
+              void *hip_stream);
+
+/* ---- batched form ---------------------------------------------------------
+ * One descriptor per window; every stage of every window of the batch runs
+ * in one kernel launch per stage (one per pyramid level for the pyramid and
+ * the flow).  Windows may have different parameters (sizes, levels). */
+typedef struct {
+    const ebof_params *params;
+    const uint16_t *x;      /* device, n events                           */
+    const uint16_t *y;
+    const int64_t *t;
+    int64_t n;
+    int64_t t0_us;
+    uint8_t *edge_out;      /* device W*H bytes: E_df of this window      */
+    int32_t *d2_out;        /* device W*H int32, or NULL                  */
+    float *pyr_out;         /* device P floats: this window's pyramid     */
+    const float *pyr_prev;  /* device P floats of window k-1, or NULL     */
+    const uint8_t *mask;    /* E_df of window k-1 for EBOF_MASK_FLOW      */
+    float *flow_out;        /* device 2*W*H floats, used if pyr_prev      */
+    uint64_t *n_dropped_dev;/* NULL or device counter (added to)          */
+} ebof_window;
+
+/* Runs n (1..EBOF_MAX_BATCH) windows on the caller's stream.  Window i's
+ * results are the same as the stage calls would give for it alone.  Scratch
+ * is per batch slot; consecutive batches must be ordered on one stream.  The
+ * first call for a given batch layout records a HIP graph that later calls
+ * with the same layout (number of windows, maximum level count, which windows
+ * compute flow) replay. */
+int ebof_run_batch(ebof_ctx *ctx, const ebof_window *w, int32_t n,
+                   void *hip_stream);
+
+/* ---- serving ----------------------------------------------------------------
+ * A served stream keeps its previous window's pyramid and edge image in the
+ * arena.  Windows are admitted while their arena bytes fit, batched as they
+ * arrive, and run on the context's own HIP stream; each submitted window
+ * yields the flow from the stream's previous window (EBOF_NO_FLOW for the
+ * first window after open). */
+int ebof_stream_open(ebof_ctx *ctx, const ebof_params *p, int32_t *stream_id);
+
+/* Closes a stream after its submitted windows complete. */
+int ebof_stream_close(ebof_ctx *ctx, int32_t stream_id);
+
+/* Queues one window of a stream.  Host event arrays (events_on_device = 0)
+ * are copied into pinned staging before the call returns; device arrays
+ * (events_on_device = 1) must stay alive until the ticket completes.
+ * flow_out_dev (2*W*H floats) and mask_out_dev (W*H bytes, the reference
+ * window's E_df) are device buffers written when the window completes; they
+ * must stay alive until ebof_poll reports completion.  Returns EBOF_E_AGAIN
+ * when the queue is full. */
+int ebof_submit(ebof_ctx *ctx, int32_t stream_id, const uint16_t *x,
+                const uint16_t *y, const int64_t *t, int64_t n, int64_t t0_us,
+                int events_on_device, float *flow_out_dev,
+                uint8_t *mask_out_dev, uint64_t *ticket);
+
+/* Non-blocking.  *status becomes EBOF_OK (flow written), EBOF_NO_FLOW (first
+ * window of the stream: outputs zeroed) or a negative error; the call returns
+ * EBOF_E_AGAIN while the window is pending, EBOF_E_NOTFOUND for an unknown or
+ * already-reported ticket, EBOF_OK once reported. */
+int ebof_poll(ebof_ctx *ctx, uint64_t ticket, int32_t *status);
+
+/* Blocks until every submitted window has completed. */
+int ebof_drain(ebof_ctx *ctx);
+
+/* ---- measurement -------------------------------------------------------------
+ * Kernel timing: when enabled, every launch of the selected kernels is
+ * bracketed by HIP events on the stream it is launched on; ebof_timing_read
+ * waits for them and returns the total milliseconds and the launch count
+ * accumulated since the last read (then resets). */
+#define EBOF_K_SCATTER 0
+#define EBOF_K_DENOISE_FILL 1
+#define EBOF_K_PACK_COLS 2
+#define EBOF_K_EDT_COLS 3
+#define EBOF_K_EDT_ROWS 4
+#define EBOF_K_PYR_DOWN 5
+#define EBOF_K_DIS_LEVEL 6
+#define EBOF_K_DENSIFY 7
+#define EBOF_K_COUNT 8
+int ebof_timing_enable(ebof_ctx *ctx, uint32_t kernel_mask);
+int ebof_timing_read(ebof_ctx *ctx, int32_t kernel_id, double *total_ms,
+                     int64_t *launches);
+
+/* Library version string. */
+const char *ebof_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBOF_H */

@@ -1,0 +1,370 @@
+"""Python binding of libebof (the C ABI declared in include/ebof.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.  Functions
+keep the C names; tensors are checked on the host (device, dtype, contiguity,
+size) before their pointers reach a kernel.  There is no fallback: if the
+library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libebof.so")
+
+EBOF_OK = 0
+EBOF_NO_FLOW = 1
+EBOF_E_INVAL = -1
+EBOF_E_NOMEM = -2
+EBOF_E_AGAIN = -3
+EBOF_E_NOTFOUND = -4
+EBOF_E_DEVICE = -5
+EBOF_E_STATE = -6
+EBOF_MASK_FLOW = 1
+EBOF_MAX_BATCH = 1024
+
+KERNELS = ["scatter", "denoise_fill", "pack_cols", "edt_cols", "edt_rows", "pyr_down",
+           "dis_level", "densify"]
+
+
+class EbofError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ebof error {code}: {msg}")
+        self.code = code
+
+
+class ebof_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("dt_us", ctypes.c_int64),
+        ("n_d", ctypes.c_int32),
+        ("n_f", ctypes.c_int32),
+        ("alpha", ctypes.c_float),
+        ("levels", ctypes.c_int32),
+        ("patch", ctypes.c_int32),
+        ("stride", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("lambda_reg", ctypes.c_float),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ebof_window(ctypes.Structure):
+    _fields_ = [
+        ("params", ctypes.POINTER(ebof_params)),
+        ("x", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("t", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("t0_us", ctypes.c_int64),
+        ("edge_out", ctypes.c_void_p),
+        ("d2_out", ctypes.c_void_p),
+        ("pyr_out", ctypes.c_void_p),
+        ("pyr_prev", ctypes.c_void_p),
+        ("mask", ctypes.c_void_p),
+        ("flow_out", ctypes.c_void_p),
+        ("n_dropped_dev", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libebof.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO_PATH):
+        raise RuntimeError(f"{SO_PATH} is missing: build it with paper_2112_10591_amd.build.build()")
+    lib = ctypes.CDLL(SO_PATH)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    pp = ctypes.POINTER(ebof_params)
+    sig = {
+        "ebof_params_default": ([i32, i32, pp], ctypes.c_int),
+        "ebof_validate": ([pp], ctypes.c_int),
+        "ebof_pyramid_floats": ([pp], i64),
+        "ebof_window_scratch_bytes": ([pp], i64),
+        "ebof_create": ([ctypes.c_int, P, ctypes.c_size_t, ctypes.POINTER(P)], ctypes.c_int),
+        "ebof_destroy": ([P], ctypes.c_int),
+        "ebof_last_error": ([P], ctypes.c_char_p),
+        "ebof_bin_events": ([P, pp, P, P, P, i64, i64, P, P, P], ctypes.c_int),
+        "ebof_edt_surface": ([P, pp, P, P, P, P], ctypes.c_int),
+        "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
+        "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
+        "ebof_stream_open": ([P, pp, ctypes.POINTER(i32)], ctypes.c_int),
+        "ebof_stream_close": ([P, i32], ctypes.c_int),
+        "ebof_submit": ([P, i32, P, P, P, i64, i64, ctypes.c_int, P, P,
+                         ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "ebof_poll": ([P, ctypes.c_uint64, ctypes.POINTER(i32)], ctypes.c_int),
+        "ebof_drain": ([P], ctypes.c_int),
+        "ebof_timing_enable": ([P, u32], ctypes.c_int),
+        "ebof_timing_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+                             ctypes.c_int),
+        "ebof_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
+            "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_flow", "ebof_run_batch",
+            "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
+            "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
+
+
+# --------------------------------------------------------------------------
+# host-only helpers (no device needed)
+# --------------------------------------------------------------------------
+def ebof_params_default(width, height, **overrides):
+    p = ebof_params()
+    rc = load().ebof_params_default(int(width), int(height), ctypes.byref(p))
+    if rc != EBOF_OK:
+        raise EbofError(rc, load().ebof_last_error(None).decode())
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def ebof_validate(p):
+    return load().ebof_validate(ctypes.byref(p))
+
+
+def ebof_pyramid_floats(p):
+    n = load().ebof_pyramid_floats(ctypes.byref(p))
+    if n < 0:
+        raise EbofError(EBOF_E_INVAL, load().ebof_last_error(None).decode())
+    return int(n)
+
+
+def ebof_window_scratch_bytes(p):
+    return int(load().ebof_window_scratch_bytes(ctypes.byref(p)))
+
+
+def level_sizes(p):
+    w, h, out = p.width, p.height, []
+    for _ in range(p.levels):
+        out.append((w, h))
+        w, h = (w + 1) // 2, (h + 1) // 2
+    return out
+
+
+# --------------------------------------------------------------------------
+# tensor checks
+# --------------------------------------------------------------------------
+def _dev(t, dtype, numel, name, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(ctx, rc, ok=(EBOF_OK,)):
+    if rc not in ok:
+        raise EbofError(rc, load().ebof_last_error(ctx).decode())
+    return rc
+
+
+# --------------------------------------------------------------------------
+# context and stage calls
+# --------------------------------------------------------------------------
+class ebof_ctx:
+    """Owns the arena tensor and the library context."""
+
+    def __init__(self, arena_bytes=1 << 30, device=0):
+        self.lib = load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        h = ctypes.c_void_p()
+        rc = self.lib.ebof_create(int(device), ctypes.c_void_p(self.arena.data_ptr()),
+                                  self.arena.numel(), ctypes.byref(h))
+        if rc != EBOF_OK:
+            raise EbofError(rc, self.lib.ebof_last_error(None).decode())
+        self.handle = h
+        self._keep = []
+
+    def close(self):
+        if self.handle is not None:
+            self.lib.ebof_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ebof_create(arena_bytes=1 << 30, device=0):
+    return ebof_ctx(arena_bytes, device)
+
+
+def ebof_destroy(ctx):
+    ctx.close()
+
+
+def ebof_last_error(ctx):
+    return load().ebof_last_error(ctx.handle).decode()
+
+
+def ebof_bin_events(ctx, p, x, y, t, t0_us, edge_out, n_dropped=None, stream=None):
+    n = int(x.numel())
+    px = _dev(x, torch.uint16, n, "x")
+    py = _dev(y, torch.uint16, n, "y")
+    pt = _dev(t, torch.int64, n, "t")
+    pe = _dev(edge_out, torch.uint8, p.width * p.height, "edge_out")
+    pd = _dev(n_dropped, torch.uint64, 1, "n_dropped", optional=True)
+    return _check(ctx.handle, ctx.lib.ebof_bin_events(ctx.handle, ctypes.byref(p), px, py, pt, n,
+                                                      int(t0_us), pe, pd, _stream(stream)))
+
+
+def ebof_edt_surface(ctx, p, edge, pyr_out, d2_out=None, stream=None):
+    N = p.width * p.height
+    pe = _dev(edge, torch.uint8, N, "edge")
+    pp = _dev(pyr_out, torch.float32, ebof_pyramid_floats(p), "pyr_out")
+    pd = _dev(d2_out, torch.int32, N, "d2_out", optional=True)
+    return _check(ctx.handle, ctx.lib.ebof_edt_surface(ctx.handle, ctypes.byref(p), pe, pd, pp,
+                                                       _stream(stream)))
+
+
+def ebof_flow(ctx, p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
+    P = ebof_pyramid_floats(p)
+    N = p.width * p.height
+    a = _dev(pyr_prev, torch.float32, P, "pyr_prev")
+    b = _dev(pyr_curr, torch.float32, P, "pyr_curr")
+    m = _dev(mask, torch.uint8, N, "mask", optional=True)
+    f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
+    return _check(ctx.handle, ctx.lib.ebof_flow(ctx.handle, ctypes.byref(p), a, b, m, f,
+                                                _stream(stream)))
+
+
+def ebof_run_batch(ctx, windows, stream=None):
+    """windows: list of dicts with keys params, x, y, t, t0_us, edge_out, pyr_out and
+    optionally d2_out, pyr_prev, mask, flow_out, n_dropped."""
+    n = len(windows)
+    if not 1 <= n <= EBOF_MAX_BATCH:
+        raise ValueError("batch size out of range")
+    arr = (ebof_window * n)()
+    keep = []
+    for i, w in enumerate(windows):
+        p = w["params"]
+        keep.append(p)
+        N = p.width * p.height
+        P = ebof_pyramid_floats(p)
+        ne = int(w["x"].numel())
+        a = arr[i]
+        a.params = ctypes.pointer(p)
+        a.x = _dev(w["x"], torch.uint16, ne, "x")
+        a.y = _dev(w["y"], torch.uint16, ne, "y")
+        a.t = _dev(w["t"], torch.int64, ne, "t")
+        a.n = ne
+        a.t0_us = int(w["t0_us"])
+        a.edge_out = _dev(w["edge_out"], torch.uint8, N, "edge_out")
+        a.d2_out = _dev(w.get("d2_out"), torch.int32, N, "d2_out", optional=True)
+        a.pyr_out = _dev(w["pyr_out"], torch.float32, P, "pyr_out")
+        a.pyr_prev = _dev(w.get("pyr_prev"), torch.float32, P, "pyr_prev", optional=True)
+        a.mask = _dev(w.get("mask"), torch.uint8, N, "mask", optional=True)
+        need_flow = w.get("pyr_prev") is not None
+        a.flow_out = _dev(w.get("flow_out"), torch.float32, 2 * N, "flow_out", optional=not need_flow)
+        a.n_dropped_dev = _dev(w.get("n_dropped"), torch.uint64, 1, "n_dropped", optional=True)
+    return _check(ctx.handle, ctx.lib.ebof_run_batch(ctx.handle, arr, n, _stream(stream)))
+
+
+def ebof_timing_enable(ctx, kernels):
+    mask = 0
+    for k in kernels:
+        mask |= 1 << KERNELS.index(k)
+    return _check(ctx.handle, ctx.lib.ebof_timing_enable(ctx.handle, mask))
+
+
+def ebof_timing_read(ctx, kernel):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(ctx.handle, ctx.lib.ebof_timing_read(ctx.handle, KERNELS.index(kernel), ctypes.byref(ms),
+                                                ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+def ebof_stream_open(ctx, p):
+    sid = ctypes.c_int32()
+    _check(ctx.handle, ctx.lib.ebof_stream_open(ctx.handle, ctypes.byref(p), ctypes.byref(sid)))
+    ctx._keep.append(p)
+    return sid.value
+
+
+def ebof_stream_close(ctx, sid):
+    return _check(ctx.handle, ctx.lib.ebof_stream_close(ctx.handle, int(sid)))
+
+
+def ebof_submit(ctx, sid, p, x, y, t, t0_us, flow_out, mask_out):
+    """Host (numpy) or device (tensor) events; device outputs.  Returns the
+    ticket, or None when the queue is full (EBOF_E_AGAIN)."""
+    import numpy as np
+    N = p.width * p.height
+    f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
+    m = _dev(mask_out, torch.uint8, N, "mask_out")
+    ticket = ctypes.c_uint64()
+    if isinstance(x, torch.Tensor):
+        n = int(x.numel())
+        args = (_dev(x, torch.uint16, n, "x"), _dev(y, torch.uint16, n, "y"),
+                _dev(t, torch.int64, n, "t"), n, int(t0_us), 1)
+    else:
+        x = np.ascontiguousarray(x, np.uint16)
+        y = np.ascontiguousarray(y, np.uint16)
+        t = np.ascontiguousarray(t, np.int64)
+        n = len(x)
+        if len(y) != n or len(t) != n:
+            raise ValueError("x, y, t lengths differ")
+        args = (ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(y.ctypes.data),
+                ctypes.c_void_p(t.ctypes.data), n, int(t0_us), 0)
+    rc = ctx.lib.ebof_submit(ctx.handle, int(sid), *args, f, m, ctypes.byref(ticket))
+    if rc == EBOF_E_AGAIN:
+        return None
+    _check(ctx.handle, rc)
+    return ticket.value
+
+
+def ebof_poll(ctx, ticket):
+    """Returns None while pending, else the window status (EBOF_OK / EBOF_NO_FLOW)."""
+    st = ctypes.c_int32()
+    rc = ctx.lib.ebof_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(st))
+    if rc == EBOF_E_AGAIN:
+        return None
+    _check(ctx.handle, rc)
+    return st.value
+
+
+def ebof_drain(ctx):
+    return _check(ctx.handle, ctx.lib.ebof_drain(ctx.handle))

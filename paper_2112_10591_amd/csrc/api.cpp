@@ -1,0 +1,762 @@
+// api.cpp -- the C ABI: parameters, context, stage calls, batched runs and
+// kernel timing.  Argument checking happens here; kernels assume valid
+// descriptors.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace ebof {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int check_hip(ebof_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return EBOF_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    if (ctx) ctx->failed = true;
+    return EBOF_E_DEVICE;
+}
+
+// ---------------------------------------------------------------- arena
+void Arena::init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    used_ = 0;
+    free_.clear();
+    inuse_.clear();
+    if (size) free_[0] = size;
+}
+
+void* Arena::alloc(size_t bytes, size_t align) {
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (align < 256) align = 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        const size_t off = it->first, sz = it->second;
+        const size_t aoff = (off + align - 1) / align * align;
+        if (aoff + bytes <= off + sz) {
+            free_.erase(it);
+            if (aoff > off) free_[off] = aoff - off;
+            if (off + sz > aoff + bytes) free_[aoff + bytes] = off + sz - (aoff + bytes);
+            inuse_[aoff] = bytes;
+            used_ += bytes;
+            return base_ + aoff;
+        }
+    }
+    return nullptr;
+}
+
+void Arena::free(void* p) {
+    if (!p) return;
+    size_t off = (size_t)((char*)p - base_);
+    auto it = inuse_.find(off);
+    if (it == inuse_.end()) return;
+    size_t sz = it->second;
+    inuse_.erase(it);
+    used_ -= sz;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + sz == nx->first) {
+        sz += nx->second;
+        nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+            pv->second += sz;
+            return;
+        }
+    }
+    free_[off] = sz;
+}
+
+size_t Arena::bytes_free() const { return size_ - used_; }
+
+// ---------------------------------------------------------------- params
+static int64_t lut_entries(float alpha, std::vector<float>* out) {
+    // squared distances whose surface value is below 1.0f in float
+    const double a = (double)alpha;
+    const int64_t cap = int64_t(1) << 22;
+    for (int64_t i = 0; i < cap; ++i) {
+        const float s = (float)(1.0 - std::exp(-std::sqrt((double)i) / a));
+        if (s == 1.0f) return i;
+        if (out) out->push_back(s);
+    }
+    return -1;
+}
+
+static int validate(const ebof_params* p) {
+    if (!p) {
+        set_error("params is NULL");
+        return EBOF_E_INVAL;
+    }
+    if (p->struct_size != sizeof(ebof_params)) {
+        set_error("params.struct_size is %u, expected %zu", p->struct_size, sizeof(ebof_params));
+        return EBOF_E_INVAL;
+    }
+    if (p->width < EBOF_MIN_DIM || p->width > EBOF_MAX_DIM || p->height < EBOF_MIN_DIM ||
+        p->height > EBOF_MAX_DIM) {
+        set_error("sensor size %dx%d outside [%d, %d]", p->width, p->height, EBOF_MIN_DIM, EBOF_MAX_DIM);
+        return EBOF_E_INVAL;
+    }
+    if (p->levels < 1 || p->levels > EBOF_MAX_LEVELS) {
+        set_error("levels %d outside [1, %d]", p->levels, EBOF_MAX_LEVELS);
+        return EBOF_E_INVAL;
+    }
+    int32_t w = p->width, h = p->height;
+    for (int l = 0; l < p->levels; ++l) {
+        if (w < EBOF_PATCH || h < EBOF_PATCH) {
+            set_error("pyramid level %d is %dx%d, smaller than the %d-pixel patch", l, w, h, EBOF_PATCH);
+            return EBOF_E_INVAL;
+        }
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    if (p->n_d < 0 || p->n_d > 5 || p->n_f < 0 || p->n_f > 5) {
+        set_error("n_d %d / n_f %d outside [0, 5]", p->n_d, p->n_f);
+        return EBOF_E_INVAL;
+    }
+    if (!(std::isfinite(p->alpha) && p->alpha > 0.f && p->alpha < 100.f)) {
+        set_error("alpha %g must be finite, > 0 and < 100", (double)p->alpha);
+        return EBOF_E_INVAL;
+    }
+    if (!(std::isfinite(p->lambda_reg) && p->lambda_reg > 0.f)) {
+        set_error("lambda_reg %g must be finite and > 0", (double)p->lambda_reg);
+        return EBOF_E_INVAL;
+    }
+    if (p->patch != EBOF_PATCH) {
+        set_error("patch %d: only %d is supported", p->patch, EBOF_PATCH);
+        return EBOF_E_INVAL;
+    }
+    if (p->stride < 1 || p->stride > EBOF_PATCH) {
+        set_error("stride %d outside [1, %d]", p->stride, EBOF_PATCH);
+        return EBOF_E_INVAL;
+    }
+    if (p->iters < 0 || p->iters > 1024) {
+        set_error("iters %d outside [0, 1024]", p->iters);
+        return EBOF_E_INVAL;
+    }
+    if (p->dt_us <= 0) {
+        set_error("dt_us %lld must be > 0", (long long)p->dt_us);
+        return EBOF_E_INVAL;
+    }
+    if (p->flags & ~EBOF_MASK_FLOW) {
+        set_error("unknown flags 0x%x", p->flags);
+        return EBOF_E_INVAL;
+    }
+    return EBOF_OK;
+}
+
+Geom make_geom(const ebof_params& p) {
+    Geom g{};
+    g.W = p.width;
+    g.H = p.height;
+    g.L = p.levels;
+    g.stride = p.stride;
+    int32_t w = p.width, h = p.height;
+    int64_t off = 0, poff = 0;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        LevelGeom& lv = g.lv[l];
+        if (l < p.levels) {
+            lv.w = w;
+            lv.h = h;
+            lv.pnx = (w - kPatch + p.stride - 1) / p.stride + 1;
+            lv.pny = (h - kPatch + p.stride - 1) / p.stride + 1;
+            lv.off = off;
+            lv.poff = poff;
+            off += (int64_t)w * h;
+            poff += (int64_t)lv.pnx * lv.pny;
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        } else {
+            lv = LevelGeom{0, 0, 0, 0, off, poff};
+        }
+    }
+    g.pyr_floats = off;
+    g.patches = poff;
+    return g;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static size_t scratch_bytes(const Geom& g) {
+    const size_t N = (size_t)g.W * g.H;
+    const size_t nch = (size_t)(g.H + kChunk - 1) / kChunk;
+    return align256(N) + align256(nch * g.W * 8) + align256(N * 2) + align256((size_t)g.patches * 8);
+}
+
+// ---------------------------------------------------------------- ctx helpers
+int lut_for(ebof_ctx* ctx, float alpha, Lut* out) {
+    for (const Lut& l : ctx->luts)
+        if (std::memcmp(&l.alpha, &alpha, sizeof(float)) == 0) {
+            *out = l;
+            return EBOF_OK;
+        }
+    std::vector<float> v;
+    const int64_t n = lut_entries(alpha, &v);
+    if (n < 0) {
+        set_error("alpha %g needs a lookup table over 2^22 entries", (double)alpha);
+        return EBOF_E_INVAL;
+    }
+    Lut l;
+    l.alpha = alpha;
+    l.n = (int32_t)n;
+    l.dev = (float*)ctx->arena.alloc(std::max<size_t>(4, v.size() * 4));
+    if (!l.dev) {
+        set_error("arena full (lookup table of %lld floats)", (long long)n);
+        return EBOF_E_NOMEM;
+    }
+    if (!v.empty()) {
+        int rc = check_hip(ctx, hipMemcpy(l.dev, v.data(), v.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(lut)");
+        if (rc) return rc;
+    }
+    ctx->luts.push_back(l);
+    *out = l;
+    return EBOF_OK;
+}
+
+int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t) {
+    const size_t N = (size_t)g.W * g.H;
+    const size_t nch = (size_t)(g.H + kChunk - 1) / kChunk;
+    Scratch t;
+    t.W = g.W;
+    t.H = g.H;
+    t.L = g.L;
+    t.stride = g.stride;
+    t.e_raw = (uint8_t*)ctx->arena.alloc(N);
+    t.colmask = (uint64_t*)ctx->arena.alloc(nch * g.W * 8);
+    t.g = (uint16_t*)ctx->arena.alloc(N * 2);
+    t.puv = (float2*)ctx->arena.alloc((size_t)g.patches * 8);
+    if (!t.e_raw || !t.colmask || !t.g || !t.puv) {
+        scratch_free(ctx, &t);
+        set_error("arena full: window scratch needs %zu bytes, %zu free", scratch_bytes(g),
+                  ctx->arena.bytes_free());
+        return EBOF_E_NOMEM;
+    }
+    t.stamp = 0;
+    t.needs_zero = true;
+    *s = t;
+    return EBOF_OK;
+}
+
+void scratch_free(ebof_ctx* ctx, Scratch* s) {
+    ctx->arena.free(s->e_raw);
+    ctx->arena.free(s->colmask);
+    ctx->arena.free(s->g);
+    ctx->arena.free(s->puv);
+    *s = Scratch();
+}
+
+void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratch& s, WinDesc* d) {
+    std::memset(d, 0, sizeof(*d));
+    d->W = p.width;
+    d->H = p.height;
+    d->L = p.levels;
+    d->n_d = p.n_d;
+    d->n_f = p.n_f;
+    d->stride = p.stride;
+    d->iters = p.iters;
+    d->flags = p.flags;
+    d->lambda = p.lambda_reg;
+    d->lut_n = lut.n;
+    d->lut = lut.dev;
+    d->e_raw = s.e_raw;
+    d->colmask = s.colmask;
+    d->g = s.g;
+    d->puv = s.puv;
+    for (int l = 0; l < kMaxLevels; ++l) d->lv[l] = g.lv[l];
+}
+
+static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int* rc) {
+    auto key = std::make_tuple(g.W, g.H, g.L, g.stride);
+    auto it = ctx->stage_scratch.find(key);
+    if (it != ctx->stage_scratch.end()) return &it->second;
+    Scratch s;
+    *rc = scratch_alloc(ctx, g, &s, st);
+    if (*rc) return nullptr;
+    return &(ctx->stage_scratch[key] = s);
+}
+
+// ---------------------------------------------------------------- timing
+template <class F>
+static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f) {
+    if (!(ctx->timing_mask & (1u << kid))) {
+        f();
+        return;
+    }
+    TimedPair tp;
+    for (hipEvent_t* e : {&tp.a, &tp.b}) {
+        if (!ctx->event_pool.empty()) {
+            *e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+        } else {
+            (void)hipEventCreate(e);
+        }
+    }
+    (void)hipEventRecord(tp.a, st);
+    f();
+    (void)hipEventRecord(tp.b, st);
+    ctx->timed[kid].push_back(tp);
+}
+
+static Launch one_launch(const WinDesc* d, int32_t total, hipStream_t st) {
+    Launch L;
+    L.one = d;
+    L.ba = BatchArgs{nullptr, nullptr, 0, 0};
+    L.batch = false;
+    L.total = total;
+    L.grid = std::max(1, total);
+    L.stream = st;
+    return L;
+}
+
+static int ctx_ok(ebof_ctx* ctx) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return EBOF_E_INVAL;
+    }
+    if (ctx->failed) {
+        set_error("context failed earlier (device error)");
+        return EBOF_E_DEVICE;
+    }
+    return EBOF_OK;
+}
+
+static int launch_status(ebof_ctx* ctx) { return check_hip(ctx, hipGetLastError(), "kernel launch"); }
+
+// ---------------------------------------------------------------- batched
+static std::string layout_key(const std::vector<WinDesc>& d, const std::vector<char>& flow) {
+    std::string k;
+    char buf[64];
+    for (size_t i = 0; i < d.size(); ++i) {
+        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d;", d[i].W, d[i].H, d[i].L, d[i].stride, (int)flow[i]);
+        k += buf;
+    }
+    return k;
+}
+
+int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t st, std::vector<Scratch>* slots,
+                   bool allow_graph) {
+    if (!w || n < 1 || n > EBOF_MAX_BATCH) {
+        set_error("batch of %d windows outside [1, %d]", n, EBOF_MAX_BATCH);
+        return EBOF_E_INVAL;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = validate(w[i].params);
+        if (rc) return rc;
+        if (w[i].n < 0 || (w[i].n > 0 && (!w[i].x || !w[i].y || !w[i].t)) || !w[i].edge_out || !w[i].pyr_out ||
+            (w[i].pyr_prev && !w[i].flow_out)) {
+            set_error("window %d: missing buffer or negative event count", i);
+            return EBOF_E_INVAL;
+        }
+        if (w[i].t0_us > INT64_MAX - w[i].params->dt_us) {
+            set_error("window %d: t0 + dt overflows", i);
+            return EBOF_E_INVAL;
+        }
+    }
+    if (!ctx->batch_table_dev) {
+        ctx->batch_table_bytes =
+            align256(sizeof(WinDesc) * EBOF_MAX_BATCH) + sizeof(int32_t) * kNumStages * (EBOF_MAX_BATCH + 1);
+        ctx->batch_table_dev = (char*)ctx->arena.alloc(ctx->batch_table_bytes);
+        if (!ctx->batch_table_dev) {
+            set_error("arena full (batch table)");
+            return EBOF_E_NOMEM;
+        }
+        ctx->pinned.resize(4);
+        for (auto& pb : ctx->pinned) {
+            int rc = check_hip(ctx, hipHostMalloc((void**)&pb.host, ctx->batch_table_bytes, hipHostMallocDefault),
+                               "hipHostMalloc");
+            if (rc) return rc;
+            rc = check_hip(ctx, hipEventCreateWithFlags(&pb.done, hipEventDisableTiming), "hipEventCreate");
+            if (rc) return rc;
+        }
+    }
+    if ((int32_t)slots->size() < n) slots->resize(n);
+    std::vector<WinDesc> descs(n);
+    std::vector<char> flow(n), zero(n);
+    int32_t lmax = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        const ebof_params& p = *w[i].params;
+        const Geom g = make_geom(p);
+        Lut lut;
+        int rc = lut_for(ctx, p.alpha, &lut);
+        if (rc) return rc;
+        Scratch& s = (*slots)[i];
+        if (s.W != g.W || s.H != g.H || s.L != g.L || s.stride != g.stride) {
+            scratch_free(ctx, &s);
+            rc = scratch_alloc(ctx, g, &s, st);
+            if (rc) return rc;
+        }
+        WinDesc& d = descs[i];
+        fill_desc(p, g, lut, s, &d);
+        d.ex = w[i].x;
+        d.ey = w[i].y;
+        d.et = w[i].t;
+        d.n_ev = w[i].n;
+        d.t0 = w[i].t0_us;
+        d.t1 = w[i].t0_us + p.dt_us;
+        d.stamp = s.next_stamp();
+        zero[i] = s.needs_zero;
+        s.needs_zero = false;
+        d.e_df = w[i].edge_out;
+        d.d2 = w[i].d2_out;
+        d.pyr = w[i].pyr_out;
+        d.pyr_prev = w[i].pyr_prev;
+        d.mask = w[i].mask;
+        d.flow = w[i].flow_out;
+        d.n_dropped = (unsigned long long*)w[i].n_dropped_dev;
+        flow[i] = w[i].pyr_prev != nullptr;
+        lmax = std::max(lmax, p.levels);
+    }
+    // per-stage prefix sums
+    const size_t tab_bytes = align256(sizeof(WinDesc) * EBOF_MAX_BATCH);
+    std::vector<int32_t> prefix((size_t)kNumStages * (n + 1));
+    int32_t totals[kNumStages];
+    for (int s = 0; s < kNumStages; ++s) {
+        int64_t run = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            prefix[(size_t)s * (n + 1) + i] = (int32_t)run;
+            run += stage_items(descs[i], s, flow[i], zero[i]);
+        }
+        if (run > INT32_MAX) {
+            set_error("batch too large: stage %d has %lld work items", s, (long long)run);
+            return EBOF_E_INVAL;
+        }
+        prefix[(size_t)s * (n + 1) + n] = (int32_t)run;
+        totals[s] = (int32_t)run;
+    }
+    // upload descriptor table + prefix sums through a pinned staging buffer
+    auto& pb = ctx->pinned[ctx->pinned_next];
+    ctx->pinned_next = (ctx->pinned_next + 1) % (int)ctx->pinned.size();
+    if (pb.used) {
+        int rc = check_hip(ctx, hipEventSynchronize(pb.done), "hipEventSynchronize");
+        if (rc) return rc;
+    }
+    std::memcpy(pb.host, descs.data(), sizeof(WinDesc) * n);
+    std::memcpy(pb.host + tab_bytes, prefix.data(), prefix.size() * sizeof(int32_t));
+    int rc = check_hip(ctx, hipMemcpyAsync(ctx->batch_table_dev, pb.host, sizeof(WinDesc) * n, hipMemcpyHostToDevice, st),
+                       "hipMemcpyAsync(table)");
+    if (rc) return rc;
+    rc = check_hip(ctx,
+                   hipMemcpyAsync(ctx->batch_table_dev + tab_bytes, pb.host + tab_bytes,
+                                  prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+                   "hipMemcpyAsync(prefix)");
+    if (rc) return rc;
+    rc = check_hip(ctx, hipEventRecord(pb.done, st), "hipEventRecord");
+    if (rc) return rc;
+    pb.used = true;
+
+    const WinDesc* tab = (const WinDesc*)ctx->batch_table_dev;
+    const int32_t* pre = (const int32_t*)(ctx->batch_table_dev + tab_bytes);
+    const bool graph_mode = allow_graph && ctx->use_graphs && ctx->timing_mask == 0;
+    constexpr int32_t kCapScatter = 2048, kCapZero = 512, kCap = 1 << 20;
+    auto mk = [&](int s, int32_t cap_graph) {
+        Launch L;
+        L.one = &descs[0];
+        L.ba = BatchArgs{tab, pre + (size_t)s * (n + 1), n, 0};
+        L.batch = true;
+        L.total = totals[s];
+        L.grid = graph_mode ? std::max(1, std::min(cap_graph, kCap)) : std::max(1, std::min(totals[s], kCap));
+        if (graph_mode && cap_graph == 0) L.grid = std::max(1, totals[s]);
+        L.stream = st;
+        return L;
+    };
+    auto run_all = [&](bool all) {
+        if (all || totals[kStZero]) timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_zero(mk(kStZero, kCapZero)); });
+        if (all || totals[kStScatter])
+            timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(mk(kStScatter, kCapScatter)); });
+        timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_denoise_fill(mk(kStDenoise, 0), true); });
+        timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(mk(kStCols, 0)); });
+        timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(mk(kStRows, 0)); });
+        for (int l = 1; l < lmax; ++l)
+            if (totals[kStPyr + l - 1])
+                timed(ctx, EBOF_K_PYR_DOWN, st, [&] { launch_pyr_down(mk(kStPyr + l - 1, 0), l); });
+        for (int l = lmax - 1; l >= 0; --l)
+            if (totals[kStDis + l])
+                timed(ctx, EBOF_K_DIS_LEVEL, st, [&] { launch_dis_level(mk(kStDis + l, 0), l); });
+        if (totals[kStDensify]) timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(mk(kStDensify, 0)); });
+    };
+    if (!graph_mode) {
+        run_all(false);
+        return launch_status(ctx);
+    }
+    const std::string key = layout_key(descs, flow);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipStream_t cs = st;
+        hipStreamCaptureStatus cst;
+        rc = check_hip(ctx, hipStreamIsCapturing(cs, &cst), "hipStreamIsCapturing");
+        if (rc) return rc;
+        if (cst != hipStreamCaptureStatusNone || cs == nullptr) {
+            // the caller's stream cannot be captured here: launch directly
+            run_all(false);
+            return launch_status(ctx);
+        }
+        hipGraph_t graph;
+        rc = check_hip(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (rc) return rc;
+        run_all(true);
+        rc = check_hip(ctx, hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
+        if (rc) return rc;
+        ebof_ctx::GraphEntry ge;
+        rc = check_hip(ctx, hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        it = ctx->graphs.emplace(key, ge).first;
+    }
+    return check_hip(ctx, hipGraphLaunch(it->second.exec, st), "hipGraphLaunch");
+}
+
+}  // namespace ebof
+
+using namespace ebof;
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* ebof_version(void) { return "ebof 0.1 gfx950"; }
+
+int ebof_params_default(int32_t width, int32_t height, ebof_params* out) {
+    if (!out) {
+        set_error("out is NULL");
+        return EBOF_E_INVAL;
+    }
+    ebof_params p;
+    std::memset(&p, 0, sizeof p);
+    p.struct_size = sizeof(ebof_params);
+    p.width = width;
+    p.height = height;
+    p.dt_us = 10000;
+    const bool low = (int64_t)width * height <= 100000;
+    p.n_d = low ? 1 : 2;
+    p.n_f = low ? 4 : 3;
+    p.alpha = 1.08f;
+    p.levels = low ? 3 : 4;
+    p.patch = EBOF_PATCH;
+    p.stride = 4;
+    p.iters = 16;
+    p.lambda_reg = 1e-3f;
+    p.flags = 0;
+    // fewer levels for small sensors so that every level holds a patch
+    while (p.levels > 1) {
+        int32_t w = width, h = height;
+        bool ok = true;
+        for (int l = 0; l < p.levels; ++l) {
+            if (w < EBOF_PATCH || h < EBOF_PATCH) ok = false;
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        }
+        if (ok) break;
+        --p.levels;
+    }
+    int rc = validate(&p);
+    if (rc) return rc;
+    *out = p;
+    return EBOF_OK;
+}
+
+int ebof_validate(const ebof_params* p) { return validate(p); }
+
+int64_t ebof_pyramid_floats(const ebof_params* p) {
+    if (validate(p)) return -1;
+    return make_geom(*p).pyr_floats;
+}
+
+int64_t ebof_window_scratch_bytes(const ebof_params* p) {
+    if (validate(p)) return -1;
+    return (int64_t)scratch_bytes(make_geom(*p));
+}
+
+int ebof_create(int device, void* arena, size_t arena_bytes, ebof_ctx** out) {
+    if (!out || !arena || arena_bytes < 4096 || ((uintptr_t)arena & 255)) {
+        set_error("ebof_create: need out, a 256-byte aligned arena and arena_bytes >= 4096");
+        return EBOF_E_INVAL;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        set_error("ebof_create: device %d not available (%d devices)", device, count);
+        return EBOF_E_INVAL;
+    }
+    if (check_hip(nullptr, hipSetDevice(device), "hipSetDevice")) return EBOF_E_DEVICE;
+    ebof_ctx* c = new ebof_ctx();
+    c->device = device;
+    c->arena.init((char*)arena, arena_bytes);
+    *out = c;
+    set_error("");
+    return EBOF_OK;
+}
+
+int ebof_destroy(ebof_ctx* ctx) {
+    if (!ctx) return EBOF_OK;
+    serve_shutdown(ctx);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    for (auto& pb : ctx->pinned) {
+        if (pb.host) (void)hipHostFree(pb.host);
+        if (pb.done) (void)hipEventDestroy(pb.done);
+    }
+    for (auto& v : ctx->timed)
+        for (auto& tp : v) {
+            (void)hipEventDestroy(tp.a);
+            (void)hipEventDestroy(tp.b);
+        }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return EBOF_OK;
+}
+
+const char* ebof_last_error(const ebof_ctx*) { return g_err; }
+
+int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
+                    int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if ((rc = validate(p))) return rc;
+    if (n < 0 || (n > 0 && (!x || !y || !t)) || !edge_out) {
+        set_error("ebof_bin_events: NULL buffer or negative n");
+        return EBOF_E_INVAL;
+    }
+    if ((n + kEventsPerItem - 1) / kEventsPerItem > INT32_MAX) {
+        set_error("ebof_bin_events: too many events");
+        return EBOF_E_INVAL;
+    }
+    if (t0_us > INT64_MAX - p->dt_us) {
+        set_error("ebof_bin_events: t0 + dt overflows");
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom g = make_geom(*p);
+    Scratch* s = stage_scratch(ctx, g, st, &rc);
+    if (!s) return rc;
+    Lut lut{p->alpha, 0, nullptr};
+    WinDesc d;
+    fill_desc(*p, g, lut, *s, &d);
+    d.ex = x;
+    d.ey = y;
+    d.et = t;
+    d.n_ev = n;
+    d.t0 = t0_us;
+    d.t1 = t0_us + p->dt_us;
+    d.stamp = s->next_stamp();
+    d.e_df = edge_out;
+    d.n_dropped = (unsigned long long*)n_dropped_dev;
+    if (s->needs_zero) {
+        launch_zero(one_launch(&d, stage_items(d, kStZero, false, true), st));
+        s->needs_zero = false;
+    }
+    if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false), st)); });
+    timed(ctx, EBOF_K_DENOISE_FILL, st,
+          [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false), st), false); });
+    return launch_status(ctx);
+}
+
+int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, int32_t* d2_out, float* pyr_out,
+                     void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if ((rc = validate(p))) return rc;
+    if (!edge || !pyr_out) {
+        set_error("ebof_edt_surface: NULL edge or pyr_out");
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom g = make_geom(*p);
+    Scratch* s = stage_scratch(ctx, g, st, &rc);
+    if (!s) return rc;
+    Lut lut;
+    if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+    WinDesc d;
+    fill_desc(*p, g, lut, *s, &d);
+    d.e_df = const_cast<uint8_t*>(edge);  // read only by these kernels
+    d.d2 = d2_out;
+    d.pyr = pyr_out;
+    timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false), st)); });
+    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false), st)); });
+    timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false), st)); });
+    for (int l = 1; l < p->levels; ++l)
+        timed(ctx, EBOF_K_PYR_DOWN, st,
+              [&] { launch_pyr_down(one_launch(&d, stage_items(d, kStPyr + l - 1, false, false), st), l); });
+    return launch_status(ctx);
+}
+
+int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const float* pyr_curr, const uint8_t* mask,
+              float* flow_out, void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if ((rc = validate(p))) return rc;
+    if (!pyr_prev || !pyr_curr || !flow_out) {
+        set_error("ebof_flow: NULL pyramid or flow_out");
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom g = make_geom(*p);
+    Scratch* s = stage_scratch(ctx, g, st, &rc);
+    if (!s) return rc;
+    Lut lut{p->alpha, 0, nullptr};
+    WinDesc d;
+    fill_desc(*p, g, lut, *s, &d);
+    d.pyr = const_cast<float*>(pyr_curr);  // read only by these kernels
+    d.pyr_prev = pyr_prev;
+    d.mask = mask;
+    d.flow = flow_out;
+    for (int l = p->levels - 1; l >= 0; --l)
+        timed(ctx, EBOF_K_DIS_LEVEL, st,
+              [&] { launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false), st), l); });
+    timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false), st)); });
+    return launch_status(ctx);
+}
+
+int ebof_run_batch(ebof_ctx* ctx, const ebof_window* w, int32_t n, void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return run_batch_impl(ctx, w, n, (hipStream_t)hip_stream, &ctx->batch_slots, true);
+}
+
+int ebof_timing_enable(ebof_ctx* ctx, uint32_t kernel_mask) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    ctx->timing_mask = kernel_mask & ((1u << EBOF_K_COUNT) - 1);
+    return EBOF_OK;
+}
+
+int ebof_timing_read(ebof_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t* launches) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if (kernel_id < 0 || kernel_id >= EBOF_K_COUNT || !total_ms || !launches) {
+        set_error("ebof_timing_read: bad kernel id or NULL output");
+        return EBOF_E_INVAL;
+    }
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& tp : ctx->timed[kernel_id]) {
+        rc = check_hip(ctx, hipEventSynchronize(tp.b), "hipEventSynchronize");
+        if (rc) return rc;
+        float ms = 0.f;
+        rc = check_hip(ctx, hipEventElapsedTime(&ms, tp.a, tp.b), "hipEventElapsedTime");
+        if (rc) return rc;
+        tot += ms;
+        ++cnt;
+        ctx->event_pool.push_back(tp.a);
+        ctx->event_pool.push_back(tp.b);
+    }
+    ctx->timed[kernel_id].clear();
+    *total_ms = tot;
+    *launches = cnt;
+    return EBOF_OK;
+}
+
+}  // extern "C"

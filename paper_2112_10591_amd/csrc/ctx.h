@@ -1,0 +1,129 @@
+// ctx.h -- host-side context of the library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ebof_dev.h"
+
+namespace ebof {
+
+void set_error(const char* fmt, ...);
+
+// First-fit sub-allocator over the caller's arena (host bookkeeping only).
+class Arena {
+   public:
+    void init(char* base, size_t size);
+    void* alloc(size_t bytes, size_t align = 256);
+    void free(void* p);
+    size_t bytes_free() const;
+    size_t bytes_used() const { return used_; }
+    bool contains(const void* p) const { return (const char*)p >= base_ && (const char*)p < base_ + size_; }
+
+   private:
+    char* base_ = nullptr;
+    size_t size_ = 0, used_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> size
+    std::map<size_t, size_t> inuse_;  // offset -> size
+};
+
+// Geometry of one parameter set.
+struct Geom {
+    int32_t W, H, L, stride;
+    LevelGeom lv[kMaxLevels];
+    int64_t pyr_floats;
+    int64_t patches;
+};
+Geom make_geom(const ebof_params& p);
+
+// Scratch of one window (staging image, column masks, column distances,
+// patch displacements) in the arena.
+struct Scratch {
+    int32_t W = 0, H = 0, L = 0, stride = 0;
+    uint8_t* e_raw = nullptr;
+    uint64_t* colmask = nullptr;
+    uint16_t* g = nullptr;
+    float2* puv = nullptr;
+    uint32_t stamp = 0;
+    bool needs_zero = true;
+    // next stamp; sets needs_zero when the counter wraps
+    uint32_t next_stamp() {
+        if (++stamp > 255) {
+            stamp = 1;
+            needs_zero = true;
+        }
+        return stamp;
+    }
+};
+
+struct Lut {
+    float alpha;
+    int32_t n;
+    float* dev;
+};
+
+struct TimedPair {
+    hipEvent_t a, b;
+};
+
+struct ServeState;  // serving runtime (serve.cpp)
+
+}  // namespace ebof
+
+struct ebof_ctx {
+    int device = 0;
+    ebof::Arena arena;
+    bool failed = false;
+    std::mutex mu;  // guards arena, luts, scratch maps against the server thread
+
+    std::vector<ebof::Lut> luts;
+    std::map<std::tuple<int, int, int, int>, ebof::Scratch> stage_scratch;
+
+    // batched form
+    std::vector<ebof::Scratch> batch_slots;
+    char* batch_table_dev = nullptr;  // arena, sized for EBOF_MAX_BATCH
+    size_t batch_table_bytes = 0;
+    struct Pinned {
+        char* host = nullptr;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    std::vector<Pinned> pinned;  // staging ring for batch tables
+    int pinned_next = 0;
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        int pinned_slot = -1;
+    };
+    std::map<std::string, GraphEntry> graphs;
+    bool use_graphs = true;
+
+    // timing
+    uint32_t timing_mask = 0;
+    std::vector<ebof::TimedPair> timed[EBOF_K_COUNT];
+    std::vector<hipEvent_t> event_pool;
+
+    ebof::ServeState* serve = nullptr;  // owned; released by serve_shutdown
+};
+
+namespace ebof {
+// helpers shared by api.cpp and serve.cpp
+int lut_for(ebof_ctx* ctx, float alpha, Lut* out);
+int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t stream);
+void scratch_free(ebof_ctx* ctx, Scratch* s);
+void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratch& s, WinDesc* d);
+int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t stream,
+                   std::vector<Scratch>* slots, bool allow_graph);
+int check_hip(ebof_ctx* ctx, hipError_t e, const char* what);
+void serve_shutdown(ebof_ctx* ctx);
+}  // namespace ebof

@@ -1,0 +1,114 @@
+// ebof_dev.h -- descriptors shared by the HIP kernels and the host side of
+// the library.  One WinDesc describes one window of one stream: its
+// parameters, its input events and every buffer its stages read or write.
+// A kernel launch either carries a single WinDesc by value (the stage calls)
+// or reads a device table of them (the batched form), in which case each
+// launch covers every window of the batch and a block finds its window by a
+// binary search over the stage's prefix sum of per-window work items.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ebof.h"
+
+namespace ebof {
+
+constexpr int kMaxLevels = EBOF_MAX_LEVELS;
+constexpr int kPatch = EBOF_PATCH;
+constexpr uint16_t kGInf = 0xFFFF;  // "no edge pixel in this column"
+constexpr int kBlock = 256;         // threads per block of every kernel
+
+// work-item granularity of each stage
+constexpr int kEventsPerItem = 1024;  // scatter: events per block
+constexpr int kTile = 64;             // denoise/fill: 64x64 pixels per block
+constexpr int kChunk = 64;            // column-mask chunk: 64 rows per word
+constexpr int kPyrTileW = 64;         // pyramid: 64x16 output pixels per block
+constexpr int kPyrTileH = 16;
+constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
+constexpr int kDensTileH = 4;         // densify: 64x4 pixels per block
+constexpr int kZeroBytesPerItem = 4096;
+
+struct LevelGeom {
+    int32_t w, h;      // level size
+    int32_t pnx, pny;  // patch grid
+    int64_t off;       // first float of the level in a pyramid
+    int64_t poff;      // first patch of the level in the patch-flow array
+};
+
+struct WinDesc {
+    int32_t W, H, L;
+    int32_t n_d, n_f;
+    int32_t stride, iters;
+    uint32_t flags;
+    float lambda;
+    int32_t lut_n;      // squared distances below lut_n read lut[], others 1.0f
+    const float* lut;
+    // events of the window, SoA, and the half-open window [t0, t1)
+    const uint16_t* ex;
+    const uint16_t* ey;
+    const int64_t* et;
+    int64_t n_ev, t0, t1;
+    uint32_t stamp;     // value marking this window's pixels in e_raw
+    uint32_t pad0;
+    // buffers
+    uint8_t* e_raw;     // W*H staging of the scattered events (stamps)
+    uint8_t* e_df;      // W*H denoised and filled edge image (0/1)
+    uint64_t* colmask;  // ceil(H/64) x W column bit masks of e_df
+    uint16_t* g;        // W*H distance to the nearest edge in the column
+    int32_t* d2;        // W*H squared distance, or null
+    float* pyr;         // this window's pyramid (level 0 = surface)
+    const float* pyr_prev;  // reference pyramid for the flow, or null
+    const uint8_t* mask;    // reference edge image for EBOF_MASK_FLOW, or null
+    float* flow;            // 2*W*H output flow
+    float2* puv;            // patch displacements, all levels
+    unsigned long long* n_dropped;  // optional counter
+    LevelGeom lv[kMaxLevels];
+};
+
+// Stages of the batched pipeline; each has a prefix sum of work items.
+enum Stage : int32_t {
+    kStZero = 0,
+    kStScatter = 1,
+    kStDenoise = 2,
+    kStPack = 3,
+    kStCols = 4,
+    kStRows = 5,
+    kStPyr = 6,                      // + (l - 1), levels 1 .. 7
+    kStDis = kStPyr + kMaxLevels - 1,  // + l, levels 0 .. 7
+    kStDensify = kStDis + kMaxLevels,
+    kNumStages = kStDensify + 1
+};
+
+// Batched launch arguments (device table form).
+struct BatchArgs {
+    const WinDesc* tab;     // nwin descriptors
+    const int32_t* prefix;  // nwin + 1 running sums of this stage's items
+    int32_t nwin;
+    int32_t pad;
+};
+
+// Host-side launch description.
+struct Launch {
+    const WinDesc* one;  // single window (host copy, passed by value)
+    BatchArgs ba;        // used when batch is true
+    bool batch;
+    int32_t total;       // items (single-window form)
+    int32_t grid;        // blocks
+    hipStream_t stream;
+};
+
+// Work items of one stage for one window (0 when the stage does not apply).
+int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero);
+
+void launch_zero(const Launch& L);
+void launch_scatter(const Launch& L);
+void launch_denoise_fill(const Launch& L, bool pack);
+void launch_pack_cols(const Launch& L);
+void launch_edt_cols(const Launch& L);
+void launch_edt_rows(const Launch& L);
+void launch_pyr_down(const Launch& L, int level);
+void launch_dis_level(const Launch& L, int level);
+void launch_densify(const Launch& L);
+
+}  // namespace ebof
