@@ -85,7 +85,7 @@ typedef struct {
  * 100k pixels (the 346x260 setting), N_d = 2, N_f = 3 above (1280x720);
  * alpha = 1.08 (d_sat = 6 px, eq. 3); dt = 10 ms; levels = 3 up to 100k
  * pixels, else 4 (each level at least 8 px); patch 8, stride 4, 16 iterations,
- * lambda_reg 1e-3, no flags.  Returns EBOF_E_INVAL for a size out of range. */
+ * lambda_reg 0.3, no flags.  Returns EBOF_E_INVAL for a size out of range. */
 int ebof_params_default(int32_t width, int32_t height, ebof_params *out);
 
 /* EBOF_OK when the parameters are usable, else EBOF_E_INVAL.  Checks: sizes

@@ -188,7 +188,7 @@ def patch_count(W, H, ps=8, stride=4):
     return int(_load().oref_patch_count(W, H, ps, stride))
 
 
-def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=1e-3,
+def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=0.3,
              want_patches=False):
     """Dense inverse search flow from pyr0 (window k-1) to pyr1 (window k).
     Returns float64 [2,H,W] (u, v), and per-level patch flows if asked."""

@@ -191,7 +191,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 static size_t scratch_bytes(const Geom& g) {
     const size_t N = (size_t)g.W * g.H;
     const size_t nch = (size_t)(g.H + kChunk - 1) / kChunk;
-    return align256(N) + align256(nch * g.W * 8) + align256(N * 2) + align256((size_t)g.patches * 8);
+    return align256(N) + align256(nch * g.W * 8) + align256(N * 2) + align256((size_t)g.patches * 16);
 }
 
 // ---------------------------------------------------------------- ctx helpers
@@ -235,7 +235,7 @@ int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t) {
     t.e_raw = (uint8_t*)ctx->arena.alloc(N);
     t.colmask = (uint64_t*)ctx->arena.alloc(nch * g.W * 8);
     t.g = (uint16_t*)ctx->arena.alloc(N * 2);
-    t.puv = (float2*)ctx->arena.alloc((size_t)g.patches * 8);
+    t.puv = (double2*)ctx->arena.alloc((size_t)g.patches * 16);
     if (!t.e_raw || !t.colmask || !t.g || !t.puv) {
         scratch_free(ctx, &t);
         set_error("arena full: window scratch needs %zu bytes, %zu free", scratch_bytes(g),
@@ -477,9 +477,10 @@ int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t s
         timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_denoise_fill(mk(kStDenoise, 0), true); });
         timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(mk(kStCols, 0)); });
         timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(mk(kStRows, 0)); });
-        for (int l = 1; l < lmax; ++l)
-            if (totals[kStPyr + l - 1])
-                timed(ctx, EBOF_K_PYR_DOWN, st, [&] { launch_pyr_down(mk(kStPyr + l - 1, 0), l); });
+        for (int from = 0; from < lmax - 1; from += kPyrChain)
+            if (totals[kStPyr + from / kPyrChain])
+                timed(ctx, EBOF_K_PYR_DOWN, st,
+                      [&] { launch_pyr_chain(mk(kStPyr + from / kPyrChain, 0), from); });
         for (int l = lmax - 1; l >= 0; --l)
             if (totals[kStDis + l])
                 timed(ctx, EBOF_K_DIS_LEVEL, st, [&] { launch_dis_level(mk(kStDis + l, 0), l); });
@@ -544,7 +545,7 @@ int ebof_params_default(int32_t width, int32_t height, ebof_params* out) {
     p.patch = EBOF_PATCH;
     p.stride = 4;
     p.iters = 16;
-    p.lambda_reg = 1e-3f;
+    p.lambda_reg = 0.3f;
     p.flags = 0;
     // fewer levels for small sensors so that every level holds a patch
     while (p.levels > 1) {
@@ -685,9 +686,10 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
     timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false), st)); });
     timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false), st)); });
     timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false), st)); });
-    for (int l = 1; l < p->levels; ++l)
-        timed(ctx, EBOF_K_PYR_DOWN, st,
-              [&] { launch_pyr_down(one_launch(&d, stage_items(d, kStPyr + l - 1, false, false), st), l); });
+    for (int from = 0; from < p->levels - 1; from += kPyrChain)
+        timed(ctx, EBOF_K_PYR_DOWN, st, [&] {
+            launch_pyr_chain(one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false), st), from);
+        });
     return launch_status(ctx);
 }
 

@@ -54,7 +54,7 @@ struct Scratch {
     uint8_t* e_raw = nullptr;
     uint64_t* colmask = nullptr;
     uint16_t* g = nullptr;
-    float2* puv = nullptr;
+    double2* puv = nullptr;
     uint32_t stamp = 0;
     bool needs_zero = true;
     // next stamp; sets needs_zero when the counter wraps

@@ -20,11 +20,10 @@ constexpr uint16_t kGInf = 0xFFFF;  // "no edge pixel in this column"
 constexpr int kBlock = 256;         // threads per block of every kernel
 
 // work-item granularity of each stage
-constexpr int kEventsPerItem = 1024;  // scatter: events per block
+constexpr int kEventsPerItem = 512;   // scatter: events per block
 constexpr int kTile = 64;             // denoise/fill: 64x64 pixels per block
 constexpr int kChunk = 64;            // column-mask chunk: 64 rows per word
-constexpr int kPyrTileW = 64;         // pyramid: 64x16 output pixels per block
-constexpr int kPyrTileH = 16;
+constexpr int kPyrChain = 3;          // pyramid: levels built per launch
 constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
 constexpr int kDensTileH = 4;         // densify: 64x4 pixels per block
 constexpr int kZeroBytesPerItem = 4096;
@@ -61,7 +60,7 @@ struct WinDesc {
     const float* pyr_prev;  // reference pyramid for the flow, or null
     const uint8_t* mask;    // reference edge image for EBOF_MASK_FLOW, or null
     float* flow;            // 2*W*H output flow
-    float2* puv;            // patch displacements, all levels
+    double2* puv;           // patch displacements (u, v), all levels
     unsigned long long* n_dropped;  // optional counter
     LevelGeom lv[kMaxLevels];
 };
@@ -74,7 +73,7 @@ enum Stage : int32_t {
     kStPack = 3,
     kStCols = 4,
     kStRows = 5,
-    kStPyr = 6,                      // + (l - 1), levels 1 .. 7
+    kStPyr = 6,                      // + chain index (levels 1-3, 4-6, 7)
     kStDis = kStPyr + kMaxLevels - 1,  // + l, levels 0 .. 7
     kStDensify = kStDis + kMaxLevels,
     kNumStages = kStDensify + 1
@@ -107,7 +106,7 @@ void launch_denoise_fill(const Launch& L, bool pack);
 void launch_pack_cols(const Launch& L);
 void launch_edt_cols(const Launch& L);
 void launch_edt_rows(const Launch& L);
-void launch_pyr_down(const Launch& L, int level);
+void launch_pyr_chain(const Launch& L, int from);
 void launch_dis_level(const Launch& L, int level);
 void launch_densify(const Launch& L);
 

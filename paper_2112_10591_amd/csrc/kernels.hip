@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ebof_dev.h"
 
 namespace ebof {
@@ -43,42 +45,6 @@ __device__ __forceinline__ int32_t item_total(const BatchArgs& ba, int32_t total
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// 8-lane all-reduce (sum) within aligned groups of 8 lanes, by DPP:
-// swap neighbours, swap pairs, then mirror the two quads of the half-row.
-// Each step adds two values in an order that commutes, so all 8 lanes end
-// with bit-identical sums.
-template <int CTRL>
-__device__ __forceinline__ float dppf(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                                 0xF, 0xF, false));
-}
-__device__ __forceinline__ float red8(float v) {
-    v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dppf<0x141>(v);  // row_half_mirror
-    return v;
-}
-
-// Bilinear sample with replicated border (the four neighbour indices clamped
-// into the image).  Offsets beyond the image all clamp to the border, so the
-// position is limited first to keep the float-to-int conversion defined.
-__device__ __forceinline__ float bilinear(const float* __restrict__ I, int W, int H, float sx,
-                                          float sy) {
-    const float lim = (float)(W + H + 16);
-    sx = fminf(fmaxf(sx, -lim), lim);
-    sy = fminf(fmaxf(sy, -lim), lim);
-    const float fx = floorf(sx), fy = floorf(sy);
-    const float ax = sx - fx, ay = sy - fy;
-    const int x0 = (int)fx, y0 = (int)fy;
-    const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
-    const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
-    const float a = I[(size_t)ya * W + xa], b = I[(size_t)ya * W + xb];
-    const float c = I[(size_t)yb * W + xa], d = I[(size_t)yb * W + xb];
-    const float top = a + ax * (b - a);
-    const float bot = c + ax * (d - c);
-    return top + ay * (bot - top);
-}
 
 // Patches of one axis that contain pixel p: the regular ones (origin k*s,
 // k <= np-2, never clamped) with k*s <= p <= k*s+7, plus the last patch
@@ -237,74 +203,92 @@ __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, cons
 
 // --------------------------------------------------------------------------
 // Column bit masks of an edge image (for edge images not produced by
-// k_denoise_fill).  Item = 64 columns x 4 chunks; thread = (column, chunk).
+// k_denoise_fill).  Item = one 64x64 tile; thread = (column, 16-row segment);
+// the four 16-bit pieces of a column are joined in LDS.
 // --------------------------------------------------------------------------
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_pack_cols(const WinDesc one, const BatchArgs ba,
                                                       int32_t total_arg) {
+    __shared__ uint16_t sBits[4][64];
     const int32_t total = item_total<B>(ba, total_arg);
+    const int c = threadIdx.x & 63, seg = threadIdx.x >> 6;
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
-        const int bands = (W + 63) / 64, nch = (H + kChunk - 1) / kChunk;
-        const int bx = local % bands, cg = local / bands;
-        const int x = bx * 64 + (threadIdx.x & 63);
-        const int ck = cg * 4 + (threadIdx.x >> 6);
-        if (x < W && ck < nch) {
-            const int rows = min(kChunk, H - ck * kChunk);
-            const uint8_t* col = d->e_df + (size_t)ck * kChunk * W + x;
-            uint64_t m = 0;
-            for (int r = 0; r < rows; ++r) m |= (uint64_t)(col[(size_t)r * W] != 0) << r;
-            d->colmask[(size_t)ck * W + x] = m;
+        const int bands = (W + 63) / 64;
+        const int bx = local % bands, ck = local / bands;
+        const int x = bx * 64 + c;
+        const int y0 = ck * kChunk + seg * 16;
+        uint32_t bits = 0;
+        if (x < W) {
+            const uint8_t* col = d->e_df + (size_t)y0 * W + x;
+            if (y0 + 16 <= H) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) bits |= (uint32_t)(col[(size_t)r * W] != 0) << r;
+            } else {
+                for (int r = 0; y0 + r < H; ++r) bits |= (uint32_t)(col[(size_t)r * W] != 0) << r;
+            }
         }
+        sBits[seg][c] = (uint16_t)bits;
+        __syncthreads();
+        if (seg == 0 && x < W)
+            d->colmask[(size_t)ck * W + x] = (uint64_t)sBits[0][c] | ((uint64_t)sBits[1][c] << 16) |
+                                             ((uint64_t)sBits[2][c] << 32) | ((uint64_t)sBits[3][c] << 48);
+        __syncthreads();
     }
 }
 
 // --------------------------------------------------------------------------
 // Exact distance transform, column pass: g(x, y) = min |y - y'| over the edge
-// pixels (x, y') of column x, or kGInf when the column has none.  Thread =
-// (column, 64-row chunk): the nearest edges above and below the chunk come
-// from the neighbouring chunks' masks, those inside it from bit scans.
+// pixels (x, y') of column x, or kGInf when the column has none.  Item = one
+// 64x64 tile; thread = (column, 16-row segment).  The nearest edges above and
+// below the tile's chunk come from the neighbouring chunks' masks, those
+// inside it from bit scans of the chunk's mask.
 // --------------------------------------------------------------------------
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const BatchArgs ba,
                                                      int32_t total_arg) {
     const int32_t total = item_total<B>(ba, total_arg);
+    const int c = threadIdx.x & 63, seg = threadIdx.x >> 6;
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
         const int bands = (W + 63) / 64, nch = (H + kChunk - 1) / kChunk;
-        const int bx = local % bands, cg = local / bands;
-        const int x = bx * 64 + (threadIdx.x & 63);
-        const int ck = cg * 4 + (threadIdx.x >> 6);
-        if (x < W && ck < nch) {
-            const uint64_t* cm = d->colmask + x;
-            const uint64_t m = cm[(size_t)ck * W];
-            int prev = -1;  // last edge row above the chunk
-            for (int c2 = ck - 1; c2 >= 0; --c2) {
-                const uint64_t mm = cm[(size_t)c2 * W];
-                if (mm) {
-                    prev = c2 * kChunk + 63 - __clzll(mm);
-                    break;
-                }
+        const int bx = local % bands, ck = local / bands;
+        const int x = bx * 64 + c;
+        if (x >= W) continue;
+        const uint64_t* cm = d->colmask + x;
+        const uint64_t m = cm[(size_t)ck * W];
+        int above = -1;  // last edge row above the chunk
+        for (int c2 = ck - 1; c2 >= 0; --c2) {
+            const uint64_t mm = cm[(size_t)c2 * W];
+            if (mm) {
+                above = c2 * kChunk + 63 - __clzll(mm);
+                break;
             }
-            int next = -1;  // first edge row below the chunk
-            for (int c2 = ck + 1; c2 < nch; ++c2) {
-                const uint64_t mm = cm[(size_t)c2 * W];
-                if (mm) {
-                    next = c2 * kChunk + __ffsll((unsigned long long)mm) - 1;
-                    break;
-                }
+        }
+        int below = -1;  // first edge row below the chunk
+        for (int c2 = ck + 1; c2 < nch; ++c2) {
+            const uint64_t mm = cm[(size_t)c2 * W];
+            if (mm) {
+                below = c2 * kChunk + __ffsll((unsigned long long)mm) - 1;
+                break;
             }
-            const int rows = min(kChunk, H - ck * kChunk);
-            uint16_t* gcol = d->g + (size_t)ck * kChunk * W + x;
-            for (int r = 0; r < rows; ++r) {
-                const int y = ck * kChunk + r;
-                const uint64_t rest = m >> r;
-                if (rest & 1ull) prev = y;
-                const int nxt = rest ? y + __ffsll((unsigned long long)rest) - 1 : next;
+        }
+        const int r0 = seg * 16;
+        const int rows = min(16, H - ck * kChunk - r0);
+        uint16_t* gcol = d->g + (size_t)(ck * kChunk + r0) * W + x;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < rows) {
+                const int rr = r0 + r;  // row within the chunk
+                const int y = ck * kChunk + rr;
+                const uint64_t lo = rr == 63 ? m : (m & ((2ull << rr) - 1));  // bits <= rr
+                const uint64_t hi = m >> rr;                                   // bits >= rr
+                const int prev = lo ? ck * kChunk + 63 - __clzll(lo) : above;
+                const int nxt = hi ? y + __ffsll((unsigned long long)hi) - 1 : below;
                 int gv = 0x7fffffff;
                 if (prev >= 0) gv = y - prev;
                 if (nxt >= 0) gv = min(gv, nxt - y);
@@ -320,7 +304,9 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
 // D2(x) = min_r r^2 + g(x +- r)^2, stopping once r^2 reaches the best value
 // found (no later column can beat it), which gives the exact minimum.  The
 // surface is looked up from the squared distance: lut[D2] below lut_n,
-// exactly 1.0f from there on.
+// exactly 1.0f from there on.  When D2 is not exported the search also stops
+// at r^2 >= lut_n: a minimum of lut_n or more gives 1.0f whatever it is, and
+// a smaller one is always found before that radius.
 // --------------------------------------------------------------------------
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const BatchArgs ba,
@@ -344,13 +330,14 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         const float* __restrict__ lut = d->lut;
         int32_t* d2row = d->d2 ? d->d2 + (size_t)y * W : nullptr;
         float* srow = d->pyr + (size_t)y * W;
+        const uint32_t cap = d2row ? 0xffffffffu : (uint32_t)lut_n;
         for (int x = threadIdx.x; x < W; x += kBlock) {
             uint32_t best = 0x7fffffffu;
             if (any) {
                 best = sG2[x];
                 for (int r = 1;; ++r) {
                     const uint32_t r2 = (uint32_t)r * (uint32_t)r;
-                    if (r2 >= best) break;
+                    if (r2 >= best || r2 >= cap) break;
                     const bool lft = x - r >= 0, rgt = x + r < W;
                     if (!lft && !rgt) break;
                     if (lft) best = min(best, r2 + sG2[x - r]);
@@ -359,14 +346,14 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
             }
             const int32_t d2v = best >= 0x7fffffffu ? 0x7fffffff : (int32_t)best;
             if (d2row) d2row[x] = d2v;
-            srow[x] = d2v < lut_n ? lut[d2v] : 1.0f;
+            srow[x] = best < (uint32_t)lut_n ? lut[best] : 1.0f;
         }
         __syncthreads();
     }
 }
 
 // --------------------------------------------------------------------------
-// Pyramid reduction level l-1 -> l: 5x5 binomial (separable [1 4 6 4 1]),
+// Pyramid: level l+1 = 5x5 binomial (separable [1 4 6 4 1]) of level l,
 // reflect-101 border, even samples.  Sums are formed in double: the products
 // of float samples by the small integer taps and their sums are exact there,
 // so the single rounding to float at the end gives the correctly rounded
@@ -378,59 +365,181 @@ __device__ __forceinline__ int reflect101(int i, int n) {
     return clampi(i, 0, n - 1);  // only reached for samples no output uses
 }
 
+// One launch builds up to three levels below level `from`.  A block owns an
+// 8x8 tile of the deepest level it builds; it stages the region of level
+// `from` that the tile depends on (85x85 for three levels) and computes each
+// intermediate level over the region the next one needs, writing only its own
+// part of every level.  Regions: R(deepest) = 8, R(k-1) = 2 R(k) + 3, origin
+// o(k-1) = 2 o(k) - 2.
+
+__device__ __forceinline__ void rc_init(int n, int& r, int& cc, int& dr, int& dc) {
+    r = threadIdx.x / n;
+    cc = threadIdx.x - r * n;
+    dr = kBlock / n;
+    dc = kBlock - dr * n;
+}
+__device__ __forceinline__ void rc_step(int n, int& r, int& cc, int dr, int dc) {
+    cc += dc;
+    r += dr;
+    if (cc >= n) {
+        cc -= n;
+        ++r;
+    }
+}
+
 template <bool B>
-__global__ __launch_bounds__(kBlock) void k_pyr_down(const WinDesc one, const BatchArgs ba,
-                                                     int32_t total_arg, int level) {
-    constexpr int RH = 2 * kPyrTileH + 4, RW = 2 * kPyrTileW + 4;
-    __shared__ float sIn[RH][RW];
-    __shared__ double sH[RH][kPyrTileW];
+__global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const BatchArgs ba, int32_t total_arg,
+                                                      int from) {
+    // one array, three regions (85x85 | 41x41 | 19x19); offsets rather than
+    // pointers keep every access in the LDS address space
+    __shared__ float sP[85 * 85 + 41 * 41 + 19 * 19];
     const int32_t total = item_total<B>(ba, total_arg);
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
-        const LevelGeom gs = d->lv[level - 1], gd = d->lv[level];
-        const float* __restrict__ src = d->pyr + gs.off;
-        float* dst = d->pyr + gd.off;
-        const int tiles_x = (gd.w + kPyrTileW - 1) / kPyrTileW;
-        const int X0 = (local % tiles_x) * kPyrTileW, Y0 = (local / tiles_x) * kPyrTileH;
-        for (int i = threadIdx.x; i < RH * RW; i += kBlock) {
-            const int r = i / RW, c = i % RW;
-            const int sy = reflect101(2 * Y0 - 2 + r, gs.h), sx = reflect101(2 * X0 - 2 + c, gs.w);
-            sIn[r][c] = src[(size_t)sy * gs.w + sx];
+        const int nlev = min(kPyrChain, d->L - 1 - from);
+        const LevelGeom gd = d->lv[from + nlev];
+        const int tiles_x = (gd.w + 7) / 8;
+        const int tx = local % tiles_x, ty = local / tiles_x;
+        int R[kPyrChain + 1], ox[kPyrChain + 1], oy[kPyrChain + 1];
+        int buf[kPyrChain + 1];
+        R[nlev] = 8;
+        ox[nlev] = 8 * tx;
+        oy[nlev] = 8 * ty;
+        for (int k = nlev - 1; k >= 0; --k) {
+            R[k] = 2 * R[k + 1] + 3;
+            ox[k] = 2 * ox[k + 1] - 2;
+            oy[k] = 2 * oy[k + 1] - 2;
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < RH * kPyrTileW; i += kBlock) {
-            const int r = i / kPyrTileW, X = i % kPyrTileW;
-            const float* p = &sIn[r][2 * X];
-            sH[r][X] = (double)p[0] + 4.0 * (double)p[1] + 6.0 * (double)p[2] + 4.0 * (double)p[3] +
-                       (double)p[4];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < kPyrTileH * kPyrTileW; i += kBlock) {
-            const int Y = i / kPyrTileW, X = i % kPyrTileW;
-            if (X0 + X < gd.w && Y0 + Y < gd.h) {
-                const double v = sH[2 * Y][X] + 4.0 * sH[2 * Y + 1][X] + 6.0 * sH[2 * Y + 2][X] +
-                                 4.0 * sH[2 * Y + 3][X] + sH[2 * Y + 4][X];
-                dst[(size_t)(Y0 + Y) * gd.w + X0 + X] = (float)(v * (1.0 / 256.0));
+        for (int k = 0; k <= nlev; ++k)
+            buf[k] = (nlev - k == 1) ? 85 * 85 + 41 * 41 : (nlev - k == 2) ? 85 * 85 : 0;
+        {
+            const LevelGeom g0 = d->lv[from];
+            const float* __restrict__ src = d->pyr + g0.off;
+            const int n = R[0];
+            int r, cc, dr, dc;
+            rc_init(n, r, cc, dr, dc);
+            for (; r < n; rc_step(n, r, cc, dr, dc)) {
+                const int X = ox[0] + cc, Y = oy[0] + r;
+                sP[buf[0] + r * n + cc] = (X >= 0 && X < g0.w && Y >= 0 && Y < g0.h) ? src[(size_t)Y * g0.w + X] : 0.f;
             }
         }
         __syncthreads();
+        for (int k = 1; k <= nlev; ++k) {
+            const LevelGeom gs = d->lv[from + k - 1], gt = d->lv[from + k];
+            const int in = buf[k - 1], outb = buf[k];
+            const int Rin = R[k - 1], oxi = ox[k - 1], oyi = oy[k - 1];
+            const int n = R[k];
+            const int span = 8 << (nlev - k);
+            const int cx0 = span * tx, cy0 = span * ty;
+            float* dst = d->pyr + gt.off;
+            int r, cc, dr, dc;
+            rc_init(n, r, cc, dr, dc);
+            for (; r < n; rc_step(n, r, cc, dr, dc)) {
+                const int X = ox[k] + cc, Y = oy[k] + r;
+                if (X < 0 || X >= gt.w || Y < 0 || Y >= gt.h) {
+                    if (k < nlev) sP[outb + r * n + cc] = 0.f;
+                    continue;
+                }
+                int xs[5], ys[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t) {
+                    xs[t] = reflect101(2 * X + t - 2, gs.w) - oxi;
+                    ys[t] = reflect101(2 * Y + t - 2, gs.h) - oyi;
+                }
+                double acc = 0.0;
+                constexpr double kw[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const int row = in + ys[j] * Rin;
+                    const double h = (double)sP[row + xs[0]] + 4.0 * (double)sP[row + xs[1]] +
+                                     6.0 * (double)sP[row + xs[2]] + 4.0 * (double)sP[row + xs[3]] +
+                                     (double)sP[row + xs[4]];
+                    acc += kw[j] * h;
+                }
+                const float v = (float)(acc * (1.0 / 256.0));
+                if (k < nlev) sP[outb + r * n + cc] = v;
+                if (X >= cx0 && X < cx0 + span && Y >= cy0 && Y < cy0 + span) dst[(size_t)Y * gt.w + X] = v;
+            }
+            __syncthreads();
+        }
     }
 }
 
 // --------------------------------------------------------------------------
-// Dense inverse search, one level.  A wave holds 8 patches; the 8 lanes of a
-// patch each own one column of it (8 template pixels, their gradients).  Per
-// iteration a lane reads the 9 rows of two adjacent columns of I1 around its
-// column (all pixels of a patch share the sub-pixel offset), interpolates
-// bilinearly, and the residual products are summed over the patch's 8 lanes.
-// The initial displacement of a patch is twice the coarser level's densified
-// flow at the pixel nearest the patch centre, computed here from the coarser
-// patch displacements (only at that pixel).
+// Dense inverse search.  The iteration runs in double precision: the
+// Gauss-Newton steps of weakly textured patches and the outlier reset are
+// sensitive enough that single-precision rounding changes a visible fraction
+// of the flow, while vector FP64 runs at the rate of (non-packed) FP32 here.
 // --------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double red8d(double v) {
+    v += dppd<0xB1>(v);
+    v += dppd<0x4E>(v);
+    v += dppd<0x141>(v);
+    return v;
+}
+
+// bilinear sample (replicated border) of a float image, in double
+__device__ __forceinline__ double bilinear_d(const float* __restrict__ I, int W, int H, double sx, double sy) {
+    const double lim = (double)(W + H + 16);
+    sx = fmin(fmax(sx, -lim), lim);
+    sy = fmin(fmax(sy, -lim), lim);
+    const double fx = floor(sx), fy = floor(sy);
+    const double ax = sx - fx, ay = sy - fy;
+    const int x0 = (int)fx, y0 = (int)fy;
+    const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+    const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+    const double a = I[(size_t)ya * W + xa], b = I[(size_t)ya * W + xb];
+    const double c = I[(size_t)yb * W + xa], d = I[(size_t)yb * W + xb];
+    const double top = a + ax * (b - a);
+    const double bot = c + ax * (d - c);
+    return top + ay * (bot - top);
+}
+
+// densification weight 1 / max(1, 255 |d|)
+__device__ __forceinline__ double dens_weight(double dv) { return 1.0 / fmax(1.0, 255.0 * fabs(dv)); }
+
+constexpr int kDisRW = 192;   // LDS search region, columns
+constexpr int kDisRH = 40;    // LDS search region, rows
+constexpr int kDisMargin = kPatch + 2;  // around the initial windows: covers any patch
+                                        // that stays within the reset distance
+
+// Copies an h x w window of img with top-left (x0, y0), indices clamped into
+// the image (replicated border), into LDS (pitch w).
+__device__ __forceinline__ void stage_clamped(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
+                                              int x0, int y0, int w, int h) {
+    int r = threadIdx.x / w, cc = threadIdx.x - r * w;
+    const int dr = kBlock / w, dc = kBlock - dr * w;
+    while (r < h) {
+        const int gy = clampi(y0 + r, 0, H - 1), gx = clampi(x0 + cc, 0, W - 1);
+        dst[r * w + cc] = img[(size_t)gy * W + gx];
+        cc += dc;
+        r += dr;
+        if (cc >= w) {
+            cc -= w;
+            ++r;
+        }
+    }
+}
+
+// One level.  Work item = 32 consecutive patches of one patch row (4 waves x
+// 8 patches); the 8 lanes of a patch each own one patch column.  The
+// reference strip (rows oy-1 .. oy+8) is staged in LDS for the template and
+// its gradient; then the region of I1 covering every patch's search window
+// at its initial displacement (plus a margin) is staged, and the iterations
+// read it there (a patch whose window leaves the region reads global memory;
+// both give the same clamped samples).
 template <bool B>
-__global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba,
-                                                      int32_t total_arg, int level) {
+__global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
+                                                      int level) {
+    __shared__ float sR[kDisRW * kDisRH];
+    __shared__ int sBox[4];
     const int32_t total = item_total<B>(ba, total_arg);
     const int lane = threadIdx.x & 63;
     const int slot = (threadIdx.x >> 6) * 8 + (lane >> 3);
@@ -440,109 +549,160 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const WinDesc* d = locate<B>(one, ba, item, local);
         const LevelGeom g = d->lv[level];
         const int Wl = g.w, Hl = g.h, pnx = g.pnx;
-        const int npatch = g.pnx * g.pny;
+        const int nseg = (pnx + kPatchesPerItem - 1) / kPatchesPerItem;
+        const int ky = local / nseg, seg = local - (local / nseg) * nseg;
         const int s = d->stride;
-        const float lam = d->lambda;
+        const double lam = (double)d->lambda;
         const float* __restrict__ I0 = d->pyr_prev + g.off;
         const float* __restrict__ I1 = d->pyr + g.off;
-        const int pi = local * kPatchesPerItem + slot;
-        const bool valid = pi < npatch;
-        const int pic = valid ? pi : npatch - 1;
-        const int kx = pic % pnx, ky = pic / pnx;
-        const int ox = min(kx * s, Wl - kPatch), oy = min(ky * s, Hl - kPatch);
+        const int kx0 = seg * kPatchesPerItem;
+        const int kx_last = min(kx0 + kPatchesPerItem, pnx) - 1;
+        const int kx = kx0 + slot;
+        const bool valid = kx < pnx;
+        const int kxc = valid ? kx : kx_last;
+        const int ox = min(kxc * s, Wl - kPatch), oy = min(ky * s, Hl - kPatch);
         const int x = ox + c;
-        const int xm = max(x - 1, 0), xp = min(x + 1, Wl - 1);
 
-        float T[kPatch], gxs[kPatch], gys[kPatch];
-        float hxx = 0.f, hxy = 0.f, hyy = 0.f;
+        // ---- template and gradient from the staged reference strip
+        const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
+        const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
+        stage_clamped(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2);
+        __syncthreads();
+        double T[kPatch], gxs[kPatch], gys[kPatch];
+        double hxx = 0.0, hxy = 0.0, hyy = 0.0;
+        {
+            const float* col = sR + sw + (x - sx0);
 #pragma unroll
-        for (int j = 0; j < kPatch; ++j) {
-            const int y = oy + j;
-            const int ym = max(y - 1, 0), yp = min(y + 1, Hl - 1);
-            const float* row = I0 + (size_t)y * Wl;
-            T[j] = row[x];
-            gxs[j] = 0.5f * (row[xp] - row[xm]);
-            gys[j] = 0.5f * (I0[(size_t)yp * Wl + x] - I0[(size_t)ym * Wl + x]);
-            hxx += gxs[j] * gxs[j];
-            hxy += gxs[j] * gys[j];
-            hyy += gys[j] * gys[j];
+            for (int j = 0; j < kPatch; ++j) {
+                const float* q = col + j * sw;
+                T[j] = q[0];
+                gxs[j] = 0.5 * ((double)q[1] - (double)q[-1]);
+                gys[j] = 0.5 * ((double)q[sw] - (double)q[-sw]);
+                hxx += gxs[j] * gxs[j];
+                hxy += gxs[j] * gys[j];
+                hyy += gys[j] * gys[j];
+            }
         }
-        hxx = red8(hxx);
-        hxy = red8(hxy);
-        hyy = red8(hyy);
-        const float a = hxx + lam, cc = hyy + lam;
-        const float det = a * cc - hxy * hxy;
-        const float ia = cc / det, ib = -hxy / det, ic = a / det;
+        hxx = red8d(hxx);
+        hxy = red8d(hxy);
+        hyy = red8d(hyy);
+        const double ha = hxx + lam, hc = hyy + lam;
+        const double det = ha * hc - hxy * hxy;
+        const double ia = hc / det, ib = -hxy / det, ic = ha / det;
 
-        float u0x = 0.f, u0y = 0.f;
+        // ---- initial displacement: twice the coarser dense flow at the
+        // pixel nearest the patch centre (densified there from the coarser
+        // level's patch displacements)
+        double u0x = 0.0, u0y = 0.0;
         if (level < d->L - 1) {
             const LevelGeom gc = d->lv[level + 1];
             const float* __restrict__ C0 = d->pyr_prev + gc.off;
             const float* __restrict__ C1 = d->pyr + gc.off;
-            const float2* __restrict__ cu = d->puv + gc.poff;
+            const double2* __restrict__ cu = d->puv + gc.poff;
             const int px = min((ox + kPatch / 2) >> 1, gc.w - 1);
             const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
             const Cover cx = cover_of(px, gc.w, gc.pnx, s), cy = cover_of(py, gc.h, gc.pny, s);
-            const float i0 = C0[(size_t)py * gc.w + px];
-            float sw = 0.f, su = 0.f, sv = 0.f;
+            const double i0 = C0[(size_t)py * gc.w + px];
+            double sw_ = 0.0, su = 0.0, sv = 0.0;
             for (int q = c; q < cx.n * cy.n; q += 8) {
                 const int qx = cover_index(cx, q % cx.n), qy = cover_index(cy, q / cx.n);
-                const float2 u = cu[(size_t)qy * gc.pnx + qx];
-                const float dv = bilinear(C1, gc.w, gc.h, (float)px + u.x, (float)py + u.y) - i0;
-                const float w = 1.0f / fmaxf(1.0f, 255.0f * fabsf(dv));
-                sw += w;
+                const double2 u = cu[(size_t)qy * gc.pnx + qx];
+                const double w = dens_weight(bilinear_d(C1, gc.w, gc.h, px + u.x, py + u.y) - i0);
+                sw_ += w;
                 su += w * u.x;
                 sv += w * u.y;
             }
-            sw = red8(sw);
-            su = red8(su);
-            sv = red8(sv);
-            u0x = 2.0f * (su / sw);
-            u0y = 2.0f * (sv / sw);
+            sw_ = red8d(sw_);
+            su = red8d(su);
+            sv = red8d(sv);
+            u0x = 2.0 * (su / sw_);
+            u0y = 2.0 * (sv / sw_);
         }
 
-        float ux = u0x, uy = u0y;
-        const float lim = (float)(Wl + Hl + 16);
+        // ---- stage the search region of I1
+        const double lim = (double)(Wl + Hl + 16);
+        if (threadIdx.x == 0) {
+            sBox[0] = INT32_MAX;
+            sBox[1] = INT32_MIN;
+            sBox[2] = INT32_MAX;
+            sBox[3] = INT32_MIN;
+        }
+        __syncthreads();  // also ends the reads of the reference strip
+        if (valid && c == 0) {
+            const int wx = ox + (int)floor(fmin(fmax(u0x, -lim), lim));
+            const int wy = oy + (int)floor(fmin(fmax(u0y, -lim), lim));
+            atomicMin(&sBox[0], wx);
+            atomicMax(&sBox[1], wx);
+            atomicMin(&sBox[2], wy);
+            atomicMax(&sBox[3], wy);
+        }
+        __syncthreads();
+        const int RX0 = sBox[0] - kDisMargin, RY0 = sBox[2] - kDisMargin;
+        const int RW = min(sBox[1] + kPatch + 1 + kDisMargin - RX0, kDisRW);
+        const int RH = min(sBox[3] + kPatch + 1 + kDisMargin - RY0, kDisRH);
+        stage_clamped(sR, I1, Wl, Hl, RX0, RY0, RW, RH);
+        __syncthreads();
+
+        // ---- inverse-compositional iterations
+        double ux = u0x, uy = u0y;
         const int iters = d->iters;
         for (int it = 0; it < iters; ++it) {
-            const float sx = fminf(fmaxf(ux, -lim), lim), sy = fminf(fmaxf(uy, -lim), lim);
-            const float fx = floorf(sx), fy = floorf(sy);
-            const float ax = sx - fx, ay = sy - fy;
+            const double sxu = fmin(fmax(ux, -lim), lim), syu = fmin(fmax(uy, -lim), lim);
+            const double fx = floor(sxu), fy = floor(syu);
+            const double ax = sxu - fx, ay = syu - fy;
             const int ix = (int)fx, iy = (int)fy;
-            const int xa = clampi(x + ix, 0, Wl - 1), xb = clampi(x + ix + 1, 0, Wl - 1);
-            float bx = 0.f, by = 0.f, hprev = 0.f;
+            const int rx = x + ix - RX0, ry = oy + iy - RY0;
+            double bx = 0.0, by = 0.0, hprev = 0.0;
+            if (rx >= 0 && rx + 1 < RW && ry >= 0 && ry + kPatch < RH) {
+                const float* q = sR + ry * RW + rx;
 #pragma unroll
-            for (int j = 0; j <= kPatch; ++j) {
-                const int yy = clampi(oy + j + iy, 0, Hl - 1);
-                const float* row = I1 + (size_t)yy * Wl;
-                const float A = row[xa], Bv = row[xb];
-                const float h = A + ax * (Bv - A);
-                if (j > 0) {
-                    const float w = hprev + ay * (h - hprev);
-                    const float r = w - T[j - 1];
-                    bx += gxs[j - 1] * r;
-                    by += gys[j - 1] * r;
+                for (int j = 0; j <= kPatch; ++j) {
+                    const double A = q[j * RW], Bv = q[j * RW + 1];
+                    const double h = A + ax * (Bv - A);
+                    if (j > 0) {
+                        const double r = (hprev + ay * (h - hprev)) - T[j - 1];
+                        bx += gxs[j - 1] * r;
+                        by += gys[j - 1] * r;
+                    }
+                    hprev = h;
                 }
-                hprev = h;
+            } else {
+                const int xa = clampi(x + ix, 0, Wl - 1), xb = clampi(x + ix + 1, 0, Wl - 1);
+#pragma unroll
+                for (int j = 0; j <= kPatch; ++j) {
+                    const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
+                    const double A = row[xa], Bv = row[xb];
+                    const double h = A + ax * (Bv - A);
+                    if (j > 0) {
+                        const double r = (hprev + ay * (h - hprev)) - T[j - 1];
+                        bx += gxs[j - 1] * r;
+                        by += gys[j - 1] * r;
+                    }
+                    hprev = h;
+                }
             }
-            bx = red8(bx);
-            by = red8(by);
+            bx = red8d(bx);
+            by = red8d(by);
             ux -= ia * bx + ib * by;
             uy -= ib * bx + ic * by;
         }
-        const float mx = ux - u0x, my = uy - u0y;
-        if (mx * mx + my * my > (float)(kPatch * kPatch)) {
+        // outlier reset: back to the initial displacement when the patch
+        // moved more than its size
+        const double mx = ux - u0x, my = uy - u0y;
+        if (sqrt(mx * mx + my * my) > (double)kPatch) {
             ux = u0x;
             uy = u0y;
         }
-        if (valid && c == 0) d->puv[g.poff + pi] = make_float2(ux, uy);
+        if (valid && c == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(ux, uy);
+        __syncthreads();  // the next item restages sR
     }
 }
 
 // --------------------------------------------------------------------------
 // Densification at level 0: the flow of a pixel is the mean of the covering
-// patches' displacements weighted by 1 / max(1, 255 |I1(x+u) - I0(x)|);
-// optionally zero outside the reference window's edge pixels.
+// patches' displacements weighted by 1 / max(1, 255 |I1(x+u) - I0(x)|)
+// (double precision); optionally zero outside the reference window's edge
+// pixels.
 // --------------------------------------------------------------------------
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const BatchArgs ba, int32_t total_arg) {
@@ -559,23 +719,22 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const int s = d->stride;
         const float* __restrict__ I0 = d->pyr_prev;
         const float* __restrict__ I1 = d->pyr;
-        const float2* __restrict__ pu = d->puv + g.poff;
+        const double2* __restrict__ pu = d->puv + g.poff;
         const Cover cx = cover_of(x, W, g.pnx, s), cy = cover_of(y, H, g.pny, s);
-        const float i0 = I0[(size_t)y * W + x];
-        float sw = 0.f, su = 0.f, sv = 0.f;
+        const double i0 = I0[(size_t)y * W + x];
+        double sw = 0.0, su = 0.0, sv = 0.0;
         for (int qy = 0; qy < cy.n; ++qy) {
             const int ky = cover_index(cy, qy);
             for (int qx = 0; qx < cx.n; ++qx) {
                 const int kx = cover_index(cx, qx);
-                const float2 u = pu[(size_t)ky * g.pnx + kx];
-                const float dv = bilinear(I1, W, H, (float)x + u.x, (float)y + u.y) - i0;
-                const float w = 1.0f / fmaxf(1.0f, 255.0f * fabsf(dv));
+                const double2 u = pu[(size_t)ky * g.pnx + kx];
+                const double w = dens_weight(bilinear_d(I1, W, H, x + u.x, y + u.y) - i0);
                 sw += w;
                 su += w * u.x;
                 sv += w * u.y;
             }
         }
-        float fu = su / sw, fv = sv / sw;
+        float fu = (float)(su / sw), fv = (float)(sv / sw);
         if ((d->flags & EBOF_MASK_FLOW) && d->mask && !d->mask[(size_t)y * W + x]) fu = fv = 0.f;
         d->flow[(size_t)y * W + x] = fu;
         d->flow[(size_t)W * H + (size_t)y * W + x] = fv;
@@ -617,7 +776,7 @@ void launch_denoise_fill(const Launch& L, bool pack) {
 void launch_pack_cols(const Launch& L) { EBOF_LAUNCH(k_pack_cols, L); }
 void launch_edt_cols(const Launch& L) { EBOF_LAUNCH(k_edt_cols, L); }
 void launch_edt_rows(const Launch& L) { EBOF_LAUNCH(k_edt_rows, L); }
-void launch_pyr_down(const Launch& L, int level) { EBOF_LAUNCH(k_pyr_down, L, level); }
+void launch_pyr_chain(const Launch& L, int from) { EBOF_LAUNCH(k_pyr_chain, L, from); }
 void launch_dis_level(const Launch& L, int level) { EBOF_LAUNCH(k_dis_level, L, level); }
 void launch_densify(const Launch& L) { EBOF_LAUNCH(k_densify, L); }
 
@@ -630,19 +789,19 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero) {
     if (stage == kStZero) return zero ? (int32_t)((N + kZeroBytesPerItem - 1) / kZeroBytesPerItem) : 0;
     if (stage == kStScatter) return (int32_t)((d.n_ev + kEventsPerItem - 1) / kEventsPerItem);
     if (stage == kStDenoise) return ((d.W + kTile - 1) / kTile) * ((d.H + kTile - 1) / kTile);
-    if (stage == kStPack || stage == kStCols) return bands * ((nch + 3) / 4);
+    if (stage == kStPack || stage == kStCols) return bands * nch;
     if (stage == kStRows) return d.H;
     if (stage >= kStPyr && stage < kStPyr + kMaxLevels - 1) {
-        const int l = stage - kStPyr + 1;
-        if (l >= d.L) return 0;
-        const LevelGeom& g = d.lv[l];
-        return ((g.w + kPyrTileW - 1) / kPyrTileW) * ((g.h + kPyrTileH - 1) / kPyrTileH);
+        const int from = (stage - kStPyr) * kPyrChain;
+        if (from >= d.L - 1) return 0;
+        const LevelGeom& g = d.lv[from + std::min(kPyrChain, d.L - 1 - from)];
+        return ((g.w + 7) / 8) * ((g.h + 7) / 8);
     }
     if (stage >= kStDis && stage < kStDis + kMaxLevels) {
         const int l = stage - kStDis;
         if (!has_flow || l >= d.L) return 0;
         const LevelGeom& g = d.lv[l];
-        return (g.pnx * g.pny + kPatchesPerItem - 1) / kPatchesPerItem;
+        return g.pny * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
     }
     if (stage == kStDensify) return has_flow ? ((d.W + 63) / 64) * ((d.H + kDensTileH - 1) / kDensTileH) : 0;
     return 0;

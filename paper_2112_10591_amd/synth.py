@@ -96,8 +96,23 @@ class Stream:
         rng = _rng(self.config_id, self.stream_id, k + 1, 0)
         n = int(self.n_events(k))
         n_sig = int(round((1.0 - self.noise) * n))
-        lens = [np.linalg.norm(g.segs[:, 1] - g.segs[:, 0], axis=1) for g in self.groups]
+        # Only segments whose pose-k / pose-(k+1) bounding box meets the sensor
+        # can produce an accepted event; sampling among them (by length) and
+        # rejecting points off the sensor gives the same accepted distribution
+        # as sampling among all of them.
+        vis = []
+        for g in self.groups:
+            a, b = g.pose_fn(k), g.pose_fn(k + 1)
+            ends = [g.segs[:, e] @ m[:, :2].T + m[:, 2] for m in (a, b) for e in (0, 1)]
+            ex = np.stack([q[:, 0] for q in ends], 1)
+            ey = np.stack([q[:, 1] for q in ends], 1)
+            keep = ((ex.max(1) >= -1) & (ex.min(1) <= self.W) &
+                    (ey.max(1) >= -1) & (ey.min(1) <= self.H))
+            vis.append(np.nonzero(keep)[0])
+        lens = [np.linalg.norm(g.segs[v, 1] - g.segs[v, 0], axis=1) for g, v in zip(self.groups, vis)]
         glen = np.array([l.sum() for l in lens])
+        if glen.sum() <= 0:
+            n_sig = 0
         xs, ys, ts = [], [], []
         need = n_sig
         while need > 0:
@@ -111,7 +126,7 @@ class Stream:
                 if sel.size == 0:
                     continue
                 p = lens[g_idx] / lens[g_idx].sum()
-                si = rng.choice(len(g.segs), size=sel.size, p=p)
+                si = vis[g_idx][rng.choice(len(vis[g_idx]), size=sel.size, p=p)]
                 s = rng.random(sel.size)[:, None]
                 pts = g.segs[si, 0] * (1 - s) + g.segs[si, 1] * s  # scene coords
                 a = g.pose_fn(k)
@@ -136,8 +151,10 @@ class Stream:
         ts.append(rng.integers(0, DT_US, n_noise).astype(np.int64))
         x = np.concatenate(xs)
         y = np.concatenate(ys)
-        t = np.concatenate(ts) + self.t0(k)
-        order = np.argsort(t, kind="stable")
+        rel = np.concatenate(ts)
+        # window-relative times fit in 16 bits: NumPy's stable sort is a radix sort there
+        order = np.argsort(rel.astype(np.uint16) if DT_US <= 65535 else rel, kind="stable")
+        t = rel + self.t0(k)
         p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
         ev = dict(x=np.ascontiguousarray(x[order]), y=np.ascontiguousarray(y[order]),
                   t=np.ascontiguousarray(t[order]), p=p, t0=self.t0(k))
@@ -147,13 +164,13 @@ class Stream:
 
     # ------------------------------------------------------------------
     def gt_flow(self, k):
-        """Motion field at pixel centres between window k-1 and window k
-        (image pose k-1 -> pose k) of the first group (the background);
+        """Motion field at pixel centres from window k-1 to window k of the
+        first group (the background): the map between the mid-window poses,
+        x -> A(k+1/2) A(k-1/2)^-1 x - x, with A(k+1/2) = (pose k + pose k+1)/2.
         float64 [2,H,W]."""
         g = self.groups[0]
-        a = g.pose_fn(k - 1)
-        b = g.pose_fn(k)
-        # x_img(k) = B A^-1 x_img(k-1)
+        a = 0.5 * (g.pose_fn(k - 1) + g.pose_fn(k))
+        b = 0.5 * (g.pose_fn(k) + g.pose_fn(k + 1))
         ainv_lin = np.linalg.inv(a[:, :2])
         m_lin = b[:, :2] @ ainv_lin
         m_t = b[:, 2] - m_lin @ a[:, 2]
@@ -175,23 +192,30 @@ def translation_pose(v):
 
 
 class AffineWalk:
-    """Cumulative random affine motion about the image centre; increment k is
-    rotation U[-rot,rot] deg, zoom U[-zoom,zoom], translation U[-tr,tr]^2 px."""
+    """Global affine motion about the image centre, composed window after
+    window.  The increment of window k has rotation rot*sin(.) degrees, zoom
+    zoom*sin(.) and translation tr*sin(.) px per axis, each sine with its own
+    stream-seeded amplitude (50-100 % of the maximum), period (40-120 windows)
+    and phase: the motion stays within the per-window bounds, changes
+    smoothly from one window to the next, and its cumulative drift stays
+    bounded over long sequences."""
 
     def __init__(self, W, H, config_id, stream_id, rot=2.0, zoom=0.03, tr=12.0,
                  start=None):
         self.c = np.array([W / 2.0, H / 2.0])
-        self.args = (config_id, stream_id)
-        self.rot, self.zoom, self.tr = rot, zoom, tr
+        rng = _rng(config_id, stream_id, 0, 7)
+        amp = rng.uniform(0.5, 1.0, 4) * np.array([rot, zoom, tr, tr])
+        self.amp = amp
+        self.period = rng.uniform(40.0, 120.0, 4)
+        self.phase = rng.uniform(0.0, 2 * math.pi, 4)
         self.poses = [IDENTITY if start is None else start]
 
     def increment(self, k):
-        rng = _rng(*self.args, k + 1, 1)
-        th = math.radians(rng.uniform(-self.rot, self.rot))
-        z = 1.0 + rng.uniform(-self.zoom, self.zoom)
-        t = rng.uniform(-self.tr, self.tr, 2)
+        v = self.amp * np.sin(2 * math.pi * k / self.period + self.phase)
+        th = math.radians(v[0])
+        z = 1.0 + v[1]
         lin = z * np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
-        trans = self.c - lin @ self.c + t
+        trans = self.c - lin @ self.c + v[2:]
         return _affine(lin, trans)
 
     def __call__(self, k):
@@ -315,3 +339,31 @@ def c5_stream(stream_id=0):
         poly = _polygon(c, rng.uniform(40, 200), int(rng.integers(3, 9)), rng)
         groups.append(Group(poly, translation_pose(rng.uniform(-20, 20, 2))))
     return Stream(W, H, 5, stream_id, groups, lambda k: 2_000_000, 0.30)
+
+
+# ----------------------------------------------------------------------
+# parallel generation (call before the GPU is initialised: uses fork)
+# ----------------------------------------------------------------------
+_FACTORIES = {"c1": c1_stream, "c2": c2_stream, "c4": c4_camera, "c5": c5_stream,
+              "c3": lambda i: c3_streams()[i]}
+
+
+def _gen_one(args):
+    name, sid, k = args
+    ev = _FACTORIES[name](sid).window(k)
+    return ev["x"], ev["y"], ev["t"], ev["t0"]
+
+
+def generate(name, sid, ks, workers=8):
+    """Windows ks of stream `sid` of workload `name` ("c1".."c5"), as a list
+    of dicts x, y, t, t0 (polarity dropped), generated by `workers`
+    processes."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = [(name, sid, k) for k in ks]
+    if workers <= 1 or len(jobs) < 4:
+        res = [_gen_one(j) for j in jobs]
+    else:
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+            res = list(ex.map(_gen_one, jobs, chunksize=max(1, len(jobs) // (4 * workers))))
+    return [dict(x=x, y=y, t=t, t0=t0) for x, y, t, t0 in res]

@@ -261,14 +261,28 @@ def test_dis_constant_images_keep_zero():
     assert np.all(oracle.dis_flow(p, p.copy(), 40, 40, 2) == 0.0)
 
 
+def _shifted_event_surfaces(W, H, d, seed, density=0.03, L=3):
+    """Pyramids of two windows whose events are the same sparse random pixels,
+    the second shifted by the integer displacement d (no denoise/fill)."""
+    rng = np.random.default_rng(seed)
+    n = int(density * W * H)
+    x = rng.integers(0, W, n)
+    y = rng.integers(0, H, n)
+    x1, y1 = x + d[0], y + d[1]
+    keep = (x1 >= 0) & (x1 < W) & (y1 >= 0) & (y1 < H)
+    t = np.zeros(n, np.int64)
+    a = oracle.window(W, H, x, y, t, 0, 10, 0, 5, float(np.float32(1.08)), L)
+    b = oracle.window(W, H, x1[keep], y1[keep], t[keep], 0, 10, 0, 5, float(np.float32(1.08)), L)
+    return a, b
+
+
 @pytest.mark.parametrize("d", [(2, -1), (-3, 1), (1, 3)])
 def test_dis_integer_shift_recovered(d):
+    """Events shifted by an integer displacement: away from the border the
+    surfaces are exact translates, and the flow recovers the shift."""
     H, W = 96, 128
-    img = _smooth_texture(H, W, 7)
-    ix = np.clip(np.arange(W) - d[0], 0, W - 1)
-    iy = np.clip(np.arange(H) - d[1], 0, H - 1)
-    img1 = img[iy][:, ix]
-    f = oracle.dis_flow(_pyr(img, 3), _pyr(img1, 3), W, H, 3)
+    a, b = _shifted_event_surfaces(W, H, d, 7)
+    f = oracle.dis_flow(a["pyr"], b["pyr"], W, H, 3)
     inner = (slice(12, H - 12), slice(12, W - 12))
     e = np.hypot(f[0][inner] - d[0], f[1][inner] - d[1])
     assert np.median(e) < 1e-6 and np.mean(e < 0.05) > 0.98
@@ -287,7 +301,9 @@ def test_dis_bilinear_image_subpixel_shift(d):
 
     I0 = img(xx, yy).astype(np.float32)
     I1 = img(xx - d[0], yy - d[1]).astype(np.float32)
-    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, want_patches=True)
+    # a light Tikhonov term, so that 16 iterations converge on the weakly
+    # curved patches near the saddle point
+    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, lam=1e-3, want_patches=True)
     nx = (W - 8 + 3) // 4 + 1
     ny = (H - 8 + 3) // 4 + 1
     pu = pu.reshape(ny, nx, 2)[1:-1, 1:-1]  # patches whose samples stay inside
@@ -304,12 +320,36 @@ def test_dis_linear_ramp_recovers_normal_component():
     a, b, d = 0.011, 0.007, (0.3, 0.2)
     I0 = (0.1 + a * xx + b * yy).astype(np.float32)
     I1 = (0.1 + a * (xx - d[0]) + b * (yy - d[1])).astype(np.float32)
-    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, want_patches=True)
+    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, lam=1e-3, want_patches=True)
     nx = (W - 8 + 3) // 4 + 1
     ny = (H - 8 + 3) // 4 + 1
     pu = pu.reshape(ny, nx, 2)[1:-1, 1:-1]
     normal = (a * (pu[..., 0] - d[0]) + b * (pu[..., 1] - d[1])) / math.hypot(a, b)
     assert np.max(np.abs(normal)) < 1e-4
+
+
+@pytest.mark.parametrize("lam,iters", [(0.3, 16), (0.05, 4), (1.0, 7)])
+def test_dis_damping_closed_form(lam, iters):
+    """On a linear ramp with gradient g every patch pixel has the same
+    gradient, H = 64 g g^T, and the residual is linear in the displacement:
+    each step multiplies the error along g by lam / (lam + 64 |g|^2).  From a
+    zero start the normal error after k steps is -(lam/(lam+64|g|^2))^k d.n."""
+    H, W = 40, 48
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, d = 0.011, 0.007, (0.3, 0.2)
+    I0 = (0.1 + a * xx + b * yy).astype(np.float32)
+    I1 = (0.1 + a * (xx - d[0]) + b * (yy - d[1])).astype(np.float32)
+    f, pu = oracle.dis_flow(I0.ravel(), I1.ravel(), W, H, 1, lam=lam, iters=iters, want_patches=True)
+    nx = (W - 8 + 3) // 4 + 1
+    ny = (H - 8 + 3) // 4 + 1
+    pu = pu.reshape(ny, nx, 2)[1:-1, 1:-1]
+    gn = math.hypot(a, b)
+    normal = (a * (pu[..., 0] - d[0]) + b * (pu[..., 1] - d[1])) / gn
+    expect = -((lam / (lam + 64 * gn * gn)) ** iters) * (a * d[0] + b * d[1]) / gn
+    assert np.max(np.abs(normal - expect)) < 1e-4
+    # no step along the level lines (the gradient-orthogonal direction)
+    tang = (-b * pu[..., 0] + a * pu[..., 1]) / gn
+    assert np.max(np.abs(tang)) < 1e-6
 
 
 def test_dis_single_patch_image_densifies_to_patch_flow():
