@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=6, help="oracle flows in the CPU sample")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--serving-pool", type=int, default=12, help="pre-generated windows per camera")
     ap.add_argument("--workers", type=int, default=8)
     return ap.parse_args()
 
@@ -85,8 +86,15 @@ def main():
     c3 = []
     if not args.no_batched:
         bsteps = args.batched_steps + 4
-        for sid in range(16):
-            c3.append(synth.generate("c3", sid, range(bsteps), workers=args.workers))
+        flat = synth.generate_jobs([("c3", sid, k) for sid in range(16) for k in range(bsteps)], args.workers)
+        c3 = [flat[sid * bsteps:(sid + 1) * bsteps] for sid in range(16)]
+    c4, c5 = [], []
+    if not args.no_serving:
+        pool = args.serving_pool
+        flat = synth.generate_jobs([("c4", cam, k) for cam in range(64) for k in range(pool)] +
+                                   [("c5", 0, 0), ("c5", 0, 1)], args.workers)
+        c4 = [flat[cam * pool:(cam + 1) * pool] for cam in range(64)]
+        c5 = flat[64 * pool:]
     log(f"generated inputs in {time.time() - t_gen:.1f}s")
 
     # ---------------- CPU oracle on a bounded sample (before the GPU) -------
@@ -260,8 +268,12 @@ def main():
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
         out["batched"] = bench_batched(L, ctx, c3, args.batched_steps, dev, stream)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if c4:
+        out["serving"] = bench_serving(L, c4, args.serving_seconds, dev)
+        out["serving"]["speedup_vs_plain"] = out["serving"]["saturation"]["frames_per_s"] / fps
+        out["stress"] = bench_burst(L, c4, c5, dev)
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(L, ctx, c3, steps, dev, stream):
@@ -332,6 +344,191 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
            "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "graph": True}
     log(f"batched: {res['frames_per_s']:.1f} frames/s ({res['ms_per_batch']:.3f} ms per 16-window batch)")
+    return res
+
+
+def _serving_setup(L, dev, pools, flags):
+    """Open one stream per camera, upload its window pool, allocate output
+    rings.  Returns (ctx, cams)."""
+    import torch
+    ctx = L.ebof_create(arena_bytes=12 << 30)
+    cams = []
+    for c, pool in enumerate(pools):
+        W, H = int(pool[0]["W"]), int(pool[0]["H"])
+        p = L.ebof_params_default(W, H, flags=flags)
+        if pool[0].get("levels"):
+            p.levels = pool[0]["levels"]
+        sid = L.ebof_stream_open(ctx, p)
+        evs = [dict(x=torch.from_numpy(w["x"]).to(dev), y=torch.from_numpy(w["y"]).to(dev),
+                    t=torch.from_numpy(w["t"]).to(dev), t0=int(w["t0"])) for w in pool]
+        outs = [(torch.empty(2 * W * H, dtype=torch.float32, device=dev),
+                 torch.empty(W * H, dtype=torch.uint8, device=dev)) for _ in range(6)]
+        cams.append(dict(p=p, sid=sid, evs=evs, outs=outs, busy=[None] * len(outs), k=0, W=W, H=H))
+    torch.cuda.synchronize()
+    return ctx, cams
+
+
+def _palindrome(k, n):
+    period = 2 * (n - 1)
+    j = k % period
+    return j if j < n else period - j
+
+
+def _submit(L, ctx, cam, pend):
+    """Submit the camera's next pooled window into a free output slot."""
+    import ctypes
+    slot = cam["k"] % len(cam["outs"])
+    while cam["busy"][slot] is not None:  # output slot still in flight
+        _reap(L, ctx, pend, block=True)
+    ev = cam["evs"][_palindrome(cam["k"], len(cam["evs"]))]
+    f, m = cam["outs"][slot]
+    tk = ctypes.c_uint64()
+    vp = ctypes.c_void_p
+    while True:
+        rc = ctx.lib.ebof_submit(ctx.handle, cam["sid"], vp(ev["x"].data_ptr()), vp(ev["y"].data_ptr()),
+                                 vp(ev["t"].data_ptr()), int(ev["x"].numel()), ev["t0"], 1,
+                                 vp(f.data_ptr()), vp(m.data_ptr()), ctypes.byref(tk))
+        if rc == L.EBOF_OK:
+            break
+        if rc != L.EBOF_E_AGAIN:
+            raise RuntimeError(ctx.lib.ebof_last_error(ctx.handle).decode())
+        _reap(L, ctx, pend, block=True)
+    cam["busy"][slot] = tk.value
+    cam["k"] += 1
+    pend.append((tk.value, cam, slot))
+
+
+def _reap(L, ctx, pend, block=False, lat=None):
+    """Poll outstanding tickets (oldest first); record latencies."""
+    import ctypes
+    st, ln = ctypes.c_int32(), ctypes.c_int64()
+    done = 0
+    while pend:
+        tk, cam, slot = pend[0]
+        rc = ctx.lib.ebof_poll(ctx.handle, ctypes.c_uint64(tk), ctypes.byref(st), ctypes.byref(ln))
+        if rc == L.EBOF_E_AGAIN:
+            if block and done == 0:
+                time.sleep(20e-6)
+                continue
+            break
+        if rc != L.EBOF_OK or st.value < 0:
+            raise RuntimeError(f"served window failed: {rc} {st.value}")
+        pend.popleft()
+        cam["busy"][slot] = None
+        if lat is not None:
+            lat.append((ln.value * 1e-6, cam["W"], st.value))
+        done += 1
+    return done
+
+
+def _pools_c4(c4):
+    pools = []
+    for c, wins in enumerate(c4):
+        W, H = [(346, 260), (640, 480), (1280, 720)][c % 3]
+        pools.append([dict(w, W=W, H=H) for w in wins])
+    return pools
+
+
+def _lat_stats(lat, hd_only=False):
+    v = np.array([l for l, W, st in lat if st == 0 and (not hd_only or W == 1280)])
+    if v.size == 0:
+        return None
+    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)), "n": int(v.size)}
+
+
+def bench_serving(L, c4, seconds, dev):
+    """64 cameras (346x260 / 640x480 / 1280x720 by camera index mod 3), each
+    submitting windows with exponential inter-arrival times of mean 10 ms.
+    Then a saturation run: every camera keeps windows queued, no pacing."""
+    from collections import deque
+    import torch
+    ctx, cams = _serving_setup(L, dev, _pools_c4(c4), L.EBOF_MASK_FLOW | L.EBOF_CHAIN_ALWAYS)
+    rng = np.random.default_rng(44)
+    arrivals = []
+    for c in range(len(cams)):
+        t = np.cumsum(rng.exponential(0.010, int(seconds * 100 * 1.5) + 10))
+        arrivals += [(x, c) for x in t[t < seconds]]
+    arrivals.sort()
+    pend, lat = deque(), []
+    # prime every stream (first window gives no flow)
+    for cam in cams:
+        _submit(L, ctx, cam, pend)
+    while pend:
+        _reap(L, ctx, pend, block=True)
+    t0 = time.perf_counter()
+    for ta, c in arrivals:
+        while time.perf_counter() - t0 < ta:
+            _reap(L, ctx, pend, lat=lat)
+        _submit(L, ctx, cams[c], pend)
+    while pend:
+        _reap(L, ctx, pend, block=True, lat=lat)
+    t_poisson = time.perf_counter() - t0
+    n_poisson = len(arrivals)
+    # saturation: keep every camera's output slots full for `seconds`/2
+    sat_lat = []
+    t1 = time.perf_counter()
+    n_sat = 0
+    c = 0
+    while time.perf_counter() - t1 < max(2.0, seconds / 2):
+        _submit(L, ctx, cams[c % len(cams)], pend)
+        c += 1
+        n_sat += 1
+        _reap(L, ctx, pend, lat=sat_lat)
+    while pend:
+        _reap(L, ctx, pend, block=True, lat=sat_lat)
+    t_sat = time.perf_counter() - t1
+    hd_sat = sum(1 for _, W, st in sat_lat if W == 1280)
+    res = {"cameras": len(cams), "arrivals": "Poisson, mean 100 Hz per camera", "seconds": seconds,
+           "offered_frames_per_s": n_poisson / seconds, "frames_per_s": n_poisson / t_poisson,
+           "latency_ms": _lat_stats(lat), "latency_ms_hd": _lat_stats(lat, hd_only=True),
+           "saturation": {"frames_per_s": n_sat / t_sat, "hd_frames_per_s": hd_sat / t_sat,
+                          "latency_ms": _lat_stats(sat_lat), "latency_ms_hd": _lat_stats(sat_lat, True)},
+           "pool_windows_per_camera": len(cams[0]["evs"]),
+           "note": "events pre-generated and resident on the device, replayed palindromically"}
+    log(f"serving: offered {res['offered_frames_per_s']:.0f}/s, p50/p99 {res['latency_ms']['p50']:.2f}/"
+        f"{res['latency_ms']['p99']:.2f} ms; saturation {res['saturation']['frames_per_s']:.0f} frames/s")
+    for cam in cams:
+        L.ebof_stream_close(ctx, cam["sid"])
+    torch.cuda.synchronize()
+    ctx.close()
+    return res
+
+
+def bench_burst(L, c4, c5, dev):
+    """256 streams (86 at 1280x720 with 2M-event windows and a 5-level
+    pyramid, 85 at 640x480, 85 at 346x260) submit one window each at once."""
+    from collections import deque
+    import torch
+    pools = []
+    for i in range(256):
+        r = i % 3
+        if r == 2:
+            pools.append([dict(w, W=1280, H=720, levels=5) for w in c5])
+        else:
+            cam = c4[r + 3 * (i % 20)]
+            W, H = [(346, 260), (640, 480)][r]
+            pools.append([dict(w, W=W, H=H) for w in cam[:2]])
+    ctx, cams = _serving_setup(L, dev, pools, L.EBOF_MASK_FLOW | L.EBOF_CHAIN_ALWAYS)
+    pend, lat = deque(), []
+    for cam in cams:  # prime
+        _submit(L, ctx, cam, pend)
+    while pend:
+        _reap(L, ctx, pend, block=True)
+    t0 = time.perf_counter()
+    for cam in cams:
+        _submit(L, ctx, cam, pend)
+    t_sub = time.perf_counter() - t0
+    while pend:
+        _reap(L, ctx, pend, block=True, lat=lat)
+    dt = time.perf_counter() - t0
+    res = {"streams": 256, "mix": "86 x 1280x720 (2M events, L5) + 85 x 640x480 + 85 x 346x260",
+           "submit_ms": 1e3 * t_sub, "drain_ms": 1e3 * dt, "frames_per_s": 256 / dt,
+           "latency_ms": _lat_stats(lat), "latency_ms_hd": _lat_stats(lat, hd_only=True)}
+    log(f"burst: 256 windows drained in {1e3 * dt:.1f} ms (submitted in {1e3 * t_sub:.2f} ms)")
+    for cam in cams:
+        L.ebof_stream_close(ctx, cam["sid"])
+    torch.cuda.synchronize()
+    ctx.close()
     return res
 
 

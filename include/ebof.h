@@ -61,6 +61,10 @@ extern "C" {
 
 /* ---- flags of ebof_params.flags ------------------------------------------ */
 #define EBOF_MASK_FLOW 1u   /* write 0 flow outside the mask (Sec. III-D)   */
+#define EBOF_CHAIN_ALWAYS 2u /* served stream: a window always pairs with the
+                                stream's previous window, whatever its t0 (by
+                                default a t0 other than previous t0 + dt_us
+                                starts the stream over, EBOF_NO_FLOW)       */
 
 typedef struct ebof_ctx ebof_ctx; /* opaque, library-owned */
 
@@ -78,7 +82,7 @@ typedef struct {
     int32_t stride;        /* patch grid stride, 1..8                        */
     int32_t iters;         /* inverse-search iterations per patch, 0..1024   */
     float lambda_reg;      /* Tikhonov term added to the patch Hessian, > 0  */
-    uint32_t flags;        /* EBOF_MASK_FLOW                                 */
+    uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS             */
 } ebof_params;
 
 /* Defaults of Sec. IV-A for a sensor of the given size: N_d = 1, N_f = 4 up to
@@ -216,10 +220,12 @@ int ebof_submit(ebof_ctx *ctx, int32_t stream_id, const uint16_t *x,
                 uint8_t *mask_out_dev, uint64_t *ticket);
 
 /* Non-blocking.  *status becomes EBOF_OK (flow written), EBOF_NO_FLOW (first
- * window of the stream: outputs zeroed) or a negative error; the call returns
- * EBOF_E_AGAIN while the window is pending, EBOF_E_NOTFOUND for an unknown or
- * already-reported ticket, EBOF_OK once reported. */
-int ebof_poll(ebof_ctx *ctx, uint64_t ticket, int32_t *status);
+ * window of the stream, or first after a gap in time: outputs zeroed) or a
+ * negative error; the call returns EBOF_E_AGAIN while the window is pending,
+ * EBOF_E_NOTFOUND for an unknown or already-reported ticket, EBOF_OK once
+ * reported.  latency_ns: NULL, or receives the time from ebof_submit to the
+ * completion of the window's batch (host steady clock). */
+int ebof_poll(ebof_ctx *ctx, uint64_t ticket, int32_t *status, int64_t *latency_ns);
 
 /* Blocks until every submitted window has completed. */
 int ebof_drain(ebof_ctx *ctx);

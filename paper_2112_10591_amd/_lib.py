@@ -25,6 +25,7 @@ EBOF_E_NOTFOUND = -4
 EBOF_E_DEVICE = -5
 EBOF_E_STATE = -6
 EBOF_MASK_FLOW = 1
+EBOF_CHAIN_ALWAYS = 2
 EBOF_MAX_BATCH = 1024
 
 KERNELS = ["scatter", "denoise_fill", "pack_cols", "edt_cols", "edt_rows", "pyr_down",
@@ -105,7 +106,7 @@ def load():
         "ebof_stream_close": ([P, i32], ctypes.c_int),
         "ebof_submit": ([P, i32, P, P, P, i64, i64, ctypes.c_int, P, P,
                          ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
-        "ebof_poll": ([P, ctypes.c_uint64, ctypes.POINTER(i32)], ctypes.c_int),
+        "ebof_poll": ([P, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
         "ebof_drain": ([P], ctypes.c_int),
         "ebof_timing_enable": ([P, u32], ctypes.c_int),
         "ebof_timing_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
@@ -356,14 +357,16 @@ def ebof_submit(ctx, sid, p, x, y, t, t0_us, flow_out, mask_out):
     return ticket.value
 
 
-def ebof_poll(ctx, ticket):
-    """Returns None while pending, else the window status (EBOF_OK / EBOF_NO_FLOW)."""
+def ebof_poll(ctx, ticket, with_latency=False):
+    """Returns None while pending, else the window status (EBOF_OK /
+    EBOF_NO_FLOW), or (status, latency in seconds) with with_latency."""
     st = ctypes.c_int32()
-    rc = ctx.lib.ebof_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(st))
+    lat = ctypes.c_int64()
+    rc = ctx.lib.ebof_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(st), ctypes.byref(lat))
     if rc == EBOF_E_AGAIN:
         return None
     _check(ctx.handle, rc)
-    return st.value
+    return (st.value, lat.value * 1e-9) if with_latency else st.value
 
 
 def ebof_drain(ctx):

@@ -149,7 +149,7 @@ static int validate(const ebof_params* p) {
         set_error("dt_us %lld must be > 0", (long long)p->dt_us);
         return EBOF_E_INVAL;
     }
-    if (p->flags & ~EBOF_MASK_FLOW) {
+    if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS)) {
         set_error("unknown flags 0x%x", p->flags);
         return EBOF_E_INVAL;
     }
@@ -311,7 +311,7 @@ static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f) {
 static Launch one_launch(const WinDesc* d, int32_t total, hipStream_t st) {
     Launch L;
     L.one = d;
-    L.ba = BatchArgs{nullptr, nullptr, 0, 0};
+    L.ba = BatchArgs{nullptr, nullptr, nullptr, 0, 0};
     L.batch = false;
     L.total = total;
     L.grid = std::max(1, total);
@@ -338,14 +338,53 @@ static std::string layout_key(const std::vector<WinDesc>& d, const std::vector<c
     std::string k;
     char buf[64];
     for (size_t i = 0; i < d.size(); ++i) {
-        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d;", d[i].W, d[i].H, d[i].L, d[i].stride, (int)flow[i]);
+        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d;", d[i].W, d[i].H, d[i].L, d[i].stride, (int)flow[i],
+                 (int)d[i].zero_out);
         k += buf;
     }
     return k;
 }
 
-int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t st, std::vector<Scratch>* slots,
-                   bool allow_graph) {
+static size_t prefix_bytes(int32_t n) { return sizeof(int32_t) * (size_t)kNumStages * (n + 1); }
+static size_t table_desc_offset() { return align256(kTableHeader + prefix_bytes(EBOF_MAX_BATCH)); }
+
+void runner_release(BatchRunner& br) {
+    for (auto& kv : br.graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    br.graphs.clear();
+    for (auto& pb : br.pinned) {
+        if (pb.host) (void)hipHostFree(pb.host);
+        if (pb.done) (void)hipEventDestroy(pb.done);
+    }
+    br.pinned.clear();
+}
+
+static int runner_init(ebof_ctx* ctx, BatchRunner& br) {
+    if (br.table_dev) return EBOF_OK;
+    br.table_bytes = table_desc_offset() + sizeof(WinDesc) * EBOF_MAX_BATCH;
+    br.table_dev = (char*)ctx->arena.alloc(br.table_bytes);
+    if (!br.table_dev) {
+        set_error("arena full (batch table of %zu bytes)", br.table_bytes);
+        return EBOF_E_NOMEM;
+    }
+    br.pinned.resize(4);
+    for (auto& pb : br.pinned) {
+        int rc = check_hip(ctx, hipHostMalloc((void**)&pb.host, br.table_bytes, hipHostMallocDefault), "hipHostMalloc");
+        if (rc) return rc;
+        rc = check_hip(ctx, hipEventCreateWithFlags(&pb.done, hipEventDisableTiming), "hipEventCreate");
+        if (rc) return rc;
+    }
+    return EBOF_OK;
+}
+
+// Runs n windows, one launch per stage.  scr[i] is window i's scratch (its
+// geometry must match the window's parameters).  graph_mode: kGraphNone
+// launches directly; kGraphLayout captures one graph per batch layout with
+// exact grids; kGraphUniversal captures one graph per maximum level count
+// with fixed persistent grids, valid for any batch (every count is read from
+// the uploaded table).
+int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const WinExtra* extra, int32_t n,
+                   hipStream_t st, Scratch* const* scr, int graph_mode) {
     if (!w || n < 1 || n > EBOF_MAX_BATCH) {
         set_error("batch of %d windows outside [1, %d]", n, EBOF_MAX_BATCH);
         return EBOF_E_INVAL;
@@ -353,8 +392,9 @@ int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t s
     for (int32_t i = 0; i < n; ++i) {
         int rc = validate(w[i].params);
         if (rc) return rc;
+        const bool zero_out = extra && extra[i].zero_out;
         if (w[i].n < 0 || (w[i].n > 0 && (!w[i].x || !w[i].y || !w[i].t)) || !w[i].edge_out || !w[i].pyr_out ||
-            (w[i].pyr_prev && !w[i].flow_out)) {
+            ((w[i].pyr_prev || zero_out) && !w[i].flow_out)) {
             set_error("window %d: missing buffer or negative event count", i);
             return EBOF_E_INVAL;
         }
@@ -362,25 +402,15 @@ int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t s
             set_error("window %d: t0 + dt overflows", i);
             return EBOF_E_INVAL;
         }
-    }
-    if (!ctx->batch_table_dev) {
-        ctx->batch_table_bytes =
-            align256(sizeof(WinDesc) * EBOF_MAX_BATCH) + sizeof(int32_t) * kNumStages * (EBOF_MAX_BATCH + 1);
-        ctx->batch_table_dev = (char*)ctx->arena.alloc(ctx->batch_table_bytes);
-        if (!ctx->batch_table_dev) {
-            set_error("arena full (batch table)");
-            return EBOF_E_NOMEM;
-        }
-        ctx->pinned.resize(4);
-        for (auto& pb : ctx->pinned) {
-            int rc = check_hip(ctx, hipHostMalloc((void**)&pb.host, ctx->batch_table_bytes, hipHostMallocDefault),
-                               "hipHostMalloc");
-            if (rc) return rc;
-            rc = check_hip(ctx, hipEventCreateWithFlags(&pb.done, hipEventDisableTiming), "hipEventCreate");
-            if (rc) return rc;
+        const Scratch& s = *scr[i];
+        if (s.W != w[i].params->width || s.H != w[i].params->height || s.L != w[i].params->levels ||
+            s.stride != w[i].params->stride) {
+            set_error("window %d: scratch geometry does not match its parameters", i);
+            return EBOF_E_INVAL;
         }
     }
-    if ((int32_t)slots->size() < n) slots->resize(n);
+    int rc = runner_init(ctx, br);
+    if (rc) return rc;
     std::vector<WinDesc> descs(n);
     std::vector<char> flow(n), zero(n);
     int32_t lmax = 1;
@@ -388,14 +418,8 @@ int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t s
         const ebof_params& p = *w[i].params;
         const Geom g = make_geom(p);
         Lut lut;
-        int rc = lut_for(ctx, p.alpha, &lut);
-        if (rc) return rc;
-        Scratch& s = (*slots)[i];
-        if (s.W != g.W || s.H != g.H || s.L != g.L || s.stride != g.stride) {
-            scratch_free(ctx, &s);
-            rc = scratch_alloc(ctx, g, &s, st);
-            if (rc) return rc;
-        }
+        if ((rc = lut_for(ctx, p.alpha, &lut))) return rc;
+        Scratch& s = *scr[i];
         WinDesc& d = descs[i];
         fill_desc(p, g, lut, s, &d);
         d.ex = w[i].x;
@@ -414,108 +438,122 @@ int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t s
         d.mask = w[i].mask;
         d.flow = w[i].flow_out;
         d.n_dropped = (unsigned long long*)w[i].n_dropped_dev;
+        if (extra) {
+            d.mask_out = extra[i].mask_out;
+            d.zero_out = (!w[i].pyr_prev && extra[i].zero_out) ? 1u : 0u;
+        }
         flow[i] = w[i].pyr_prev != nullptr;
         lmax = std::max(lmax, p.levels);
     }
-    // per-stage prefix sums
-    const size_t tab_bytes = align256(sizeof(WinDesc) * EBOF_MAX_BATCH);
+    // prefix sums, window-major: prefix[i * kNumStages + s]
     std::vector<int32_t> prefix((size_t)kNumStages * (n + 1));
     int32_t totals[kNumStages];
     for (int s = 0; s < kNumStages; ++s) {
         int64_t run = 0;
         for (int32_t i = 0; i < n; ++i) {
-            prefix[(size_t)s * (n + 1) + i] = (int32_t)run;
+            prefix[(size_t)i * kNumStages + s] = (int32_t)run;
             run += stage_items(descs[i], s, flow[i], zero[i]);
         }
         if (run > INT32_MAX) {
             set_error("batch too large: stage %d has %lld work items", s, (long long)run);
             return EBOF_E_INVAL;
         }
-        prefix[(size_t)s * (n + 1) + n] = (int32_t)run;
+        prefix[(size_t)n * kNumStages + s] = (int32_t)run;
         totals[s] = (int32_t)run;
     }
-    // upload descriptor table + prefix sums through a pinned staging buffer
-    auto& pb = ctx->pinned[ctx->pinned_next];
-    ctx->pinned_next = (ctx->pinned_next + 1) % (int)ctx->pinned.size();
-    if (pb.used) {
-        int rc = check_hip(ctx, hipEventSynchronize(pb.done), "hipEventSynchronize");
-        if (rc) return rc;
-    }
-    std::memcpy(pb.host, descs.data(), sizeof(WinDesc) * n);
-    std::memcpy(pb.host + tab_bytes, prefix.data(), prefix.size() * sizeof(int32_t));
-    int rc = check_hip(ctx, hipMemcpyAsync(ctx->batch_table_dev, pb.host, sizeof(WinDesc) * n, hipMemcpyHostToDevice, st),
-                       "hipMemcpyAsync(table)");
-    if (rc) return rc;
-    rc = check_hip(ctx,
-                   hipMemcpyAsync(ctx->batch_table_dev + tab_bytes, pb.host + tab_bytes,
-                                  prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
-                   "hipMemcpyAsync(prefix)");
-    if (rc) return rc;
-    rc = check_hip(ctx, hipEventRecord(pb.done, st), "hipEventRecord");
-    if (rc) return rc;
+    // upload through a pinned staging buffer: [nwin | prefix sums] and the descriptors
+    auto& pb = br.pinned[br.pinned_next];
+    br.pinned_next = (br.pinned_next + 1) % (int)br.pinned.size();
+    if (pb.used && (rc = check_hip(ctx, hipEventSynchronize(pb.done), "hipEventSynchronize"))) return rc;
+    const size_t doff = table_desc_offset();
+    std::memcpy(pb.host, &n, sizeof(int32_t));
+    std::memcpy(pb.host + kTableHeader, prefix.data(), prefix_bytes(n));
+    std::memcpy(pb.host + doff, descs.data(), sizeof(WinDesc) * n);
+    if ((rc = check_hip(ctx,
+                        hipMemcpyAsync(br.table_dev, pb.host, kTableHeader + prefix_bytes(n), hipMemcpyHostToDevice,
+                                       st),
+                        "hipMemcpyAsync(prefix)")))
+        return rc;
+    if ((rc = check_hip(ctx,
+                        hipMemcpyAsync(br.table_dev + doff, pb.host + doff, sizeof(WinDesc) * n,
+                                       hipMemcpyHostToDevice, st),
+                        "hipMemcpyAsync(table)")))
+        return rc;
+    if ((rc = check_hip(ctx, hipEventRecord(pb.done, st), "hipEventRecord"))) return rc;
     pb.used = true;
 
-    const WinDesc* tab = (const WinDesc*)ctx->batch_table_dev;
-    const int32_t* pre = (const int32_t*)(ctx->batch_table_dev + tab_bytes);
-    const bool graph_mode = allow_graph && ctx->use_graphs && ctx->timing_mask == 0;
-    constexpr int32_t kCapScatter = 2048, kCapZero = 512, kCap = 1 << 20;
-    auto mk = [&](int s, int32_t cap_graph) {
+    const WinDesc* tab = (const WinDesc*)(br.table_dev + doff);
+    const int32_t* pre = (const int32_t*)(br.table_dev + kTableHeader);
+    const int32_t* nw = (const int32_t*)br.table_dev;
+    const int mode = (ctx->timing_mask == 0 && ctx->use_graphs) ? graph_mode : kGraphNone;
+    const bool universal = mode == kGraphUniversal;
+    auto mk = [&](int s, int32_t cap) {
         Launch L;
         L.one = &descs[0];
-        L.ba = BatchArgs{tab, pre + (size_t)s * (n + 1), n, 0};
+        L.ba = BatchArgs{tab, pre, nw, s, 0};
         L.batch = true;
         L.total = totals[s];
-        L.grid = graph_mode ? std::max(1, std::min(cap_graph, kCap)) : std::max(1, std::min(totals[s], kCap));
-        if (graph_mode && cap_graph == 0) L.grid = std::max(1, totals[s]);
+        if (universal)
+            L.grid = cap;
+        else if (mode == kGraphLayout && (s == kStZero || s == kStScatter))
+            L.grid = cap;  // these counts vary between batches of one layout
+        else
+            L.grid = std::max(1, std::min(totals[s], 1 << 20));
         L.stream = st;
         return L;
     };
     auto run_all = [&](bool all) {
-        if (all || totals[kStZero]) timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_zero(mk(kStZero, kCapZero)); });
-        if (all || totals[kStScatter])
-            timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(mk(kStScatter, kCapScatter)); });
-        timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_denoise_fill(mk(kStDenoise, 0), true); });
-        timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(mk(kStCols, 0)); });
-        timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(mk(kStRows, 0)); });
+        if (all || totals[kStZero]) launch_zero(mk(kStZero, 512));
+        if (all || totals[kStScatter]) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(mk(kStScatter, 2048)); });
+        if (all || totals[kStDenoise])
+            timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_denoise_fill(mk(kStDenoise, 2048), true); });
+        if (all || totals[kStCols]) timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(mk(kStCols, 2048)); });
+        if (all || totals[kStRows]) timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(mk(kStRows, 2048)); });
         for (int from = 0; from < lmax - 1; from += kPyrChain)
-            if (totals[kStPyr + from / kPyrChain])
+            if (all || totals[kStPyr + from / kPyrChain])
                 timed(ctx, EBOF_K_PYR_DOWN, st,
-                      [&] { launch_pyr_chain(mk(kStPyr + from / kPyrChain, 0), from); });
+                      [&] { launch_pyr_chain(mk(kStPyr + from / kPyrChain, 1024), from); });
         for (int l = lmax - 1; l >= 0; --l)
-            if (totals[kStDis + l])
-                timed(ctx, EBOF_K_DIS_LEVEL, st, [&] { launch_dis_level(mk(kStDis + l, 0), l); });
-        if (totals[kStDensify]) timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(mk(kStDensify, 0)); });
+            if (all || totals[kStDis + l])
+                timed(ctx, EBOF_K_DIS_LEVEL, st, [&] { launch_dis_level(mk(kStDis + l, 2048), l); });
+        if (all || totals[kStDensify])
+            timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(mk(kStDensify, 2048)); });
     };
-    if (!graph_mode) {
+    if (mode == kGraphNone) {
         run_all(false);
         return launch_status(ctx);
     }
-    const std::string key = layout_key(descs, flow);
-    auto it = ctx->graphs.find(key);
-    if (it == ctx->graphs.end()) {
-        hipStream_t cs = st;
+    std::string key;
+    if (universal) {
+        key = "U" + std::to_string(lmax);
+    } else {
+        key = layout_key(descs, flow);
+    }
+    auto it = br.graphs.find(key);
+    if (it == br.graphs.end()) {
         hipStreamCaptureStatus cst;
-        rc = check_hip(ctx, hipStreamIsCapturing(cs, &cst), "hipStreamIsCapturing");
-        if (rc) return rc;
-        if (cst != hipStreamCaptureStatusNone || cs == nullptr) {
-            // the caller's stream cannot be captured here: launch directly
+        if ((rc = check_hip(ctx, hipStreamIsCapturing(st, &cst), "hipStreamIsCapturing"))) return rc;
+        if (cst != hipStreamCaptureStatusNone || st == nullptr) {
+            // the stream cannot be captured here: launch directly
             run_all(false);
             return launch_status(ctx);
         }
         hipGraph_t graph;
-        rc = check_hip(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        if (rc) return rc;
-        run_all(true);
-        rc = check_hip(ctx, hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
-        if (rc) return rc;
-        ebof_ctx::GraphEntry ge;
-        rc = check_hip(ctx, hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if ((rc = check_hip(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
+                            "hipStreamBeginCapture")))
+            return rc;
+        run_all(universal || mode == kGraphLayout);
+        if ((rc = check_hip(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture"))) return rc;
+        hipGraphExec_t exec = nullptr;
+        rc = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
         (void)hipGraphDestroy(graph);
         if (rc) return rc;
-        it = ctx->graphs.emplace(key, ge).first;
+        it = br.graphs.emplace(key, exec).first;
     }
-    return check_hip(ctx, hipGraphLaunch(it->second.exec, st), "hipGraphLaunch");
+    return check_hip(ctx, hipGraphLaunch(it->second, st), "hipGraphLaunch");
 }
+
+int validate_params(const ebof_params* p) { return validate(p); }
 
 }  // namespace ebof
 
@@ -600,12 +638,7 @@ int ebof_destroy(ebof_ctx* ctx) {
     if (!ctx) return EBOF_OK;
     serve_shutdown(ctx);
     (void)hipDeviceSynchronize();
-    for (auto& kv : ctx->graphs)
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    for (auto& pb : ctx->pinned) {
-        if (pb.host) (void)hipHostFree(pb.host);
-        if (pb.done) (void)hipEventDestroy(pb.done);
-    }
+    runner_release(ctx->batch);
     for (auto& v : ctx->timed)
         for (auto& tp : v) {
             (void)hipEventDestroy(tp.a);
@@ -724,8 +757,26 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
 int ebof_run_batch(ebof_ctx* ctx, const ebof_window* w, int32_t n, void* hip_stream) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;
+    if (!w || n < 1 || n > EBOF_MAX_BATCH) {
+        set_error("batch of %d windows outside [1, %d]", n, EBOF_MAX_BATCH);
+        return EBOF_E_INVAL;
+    }
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_batch_impl(ctx, w, n, (hipStream_t)hip_stream, &ctx->batch_slots, true);
+    hipStream_t st = (hipStream_t)hip_stream;
+    // scratch per batch position, reallocated when the geometry changes
+    if ((int32_t)ctx->batch_slots.size() < n) ctx->batch_slots.resize(n);
+    std::vector<Scratch*> scr(n);
+    for (int32_t i = 0; i < n; ++i) {
+        if ((rc = validate(w[i].params))) return rc;
+        const Geom g = make_geom(*w[i].params);
+        Scratch& s = ctx->batch_slots[i];
+        if (s.W != g.W || s.H != g.H || s.L != g.L || s.stride != g.stride) {
+            scratch_free(ctx, &s);
+            if ((rc = scratch_alloc(ctx, g, &s, st))) return rc;
+        }
+        scr[i] = &s;
+    }
+    return run_batch_impl(ctx, ctx->batch, w, nullptr, n, st, scr.data(), kGraphLayout);
 }
 
 int ebof_timing_enable(ebof_ctx* ctx, uint32_t kernel_mask) {

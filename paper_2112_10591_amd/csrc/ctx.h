@@ -77,6 +77,29 @@ struct TimedPair {
     hipEvent_t a, b;
 };
 
+// Device descriptor table + pinned staging ring + captured graphs of one
+// batched launcher (the public batch call and the server each own one).
+struct BatchRunner {
+    char* table_dev = nullptr;
+    size_t table_bytes = 0;
+    struct Pinned {
+        char* host = nullptr;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    std::vector<Pinned> pinned;
+    int pinned_next = 0;
+    std::map<std::string, hipGraphExec_t> graphs;
+};
+
+// Extra per-window outputs of the served form.
+struct WinExtra {
+    uint8_t* mask_out = nullptr;
+    bool zero_out = false;
+};
+
+enum GraphMode { kGraphNone = 0, kGraphLayout = 1, kGraphUniversal = 2 };
+
 struct ServeState;  // serving runtime (serve.cpp)
 
 }  // namespace ebof
@@ -92,20 +115,7 @@ struct ebof_ctx {
 
     // batched form
     std::vector<ebof::Scratch> batch_slots;
-    char* batch_table_dev = nullptr;  // arena, sized for EBOF_MAX_BATCH
-    size_t batch_table_bytes = 0;
-    struct Pinned {
-        char* host = nullptr;
-        hipEvent_t done = nullptr;
-        bool used = false;
-    };
-    std::vector<Pinned> pinned;  // staging ring for batch tables
-    int pinned_next = 0;
-    struct GraphEntry {
-        hipGraphExec_t exec = nullptr;
-        int pinned_slot = -1;
-    };
-    std::map<std::string, GraphEntry> graphs;
+    ebof::BatchRunner batch;
     bool use_graphs = true;
 
     // timing
@@ -122,8 +132,10 @@ int lut_for(ebof_ctx* ctx, float alpha, Lut* out);
 int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t stream);
 void scratch_free(ebof_ctx* ctx, Scratch* s);
 void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratch& s, WinDesc* d);
-int run_batch_impl(ebof_ctx* ctx, const ebof_window* w, int32_t n, hipStream_t stream,
-                   std::vector<Scratch>* slots, bool allow_graph);
+int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const WinExtra* extra, int32_t n,
+                   hipStream_t stream, Scratch* const* scr, int graph_mode);
+void runner_release(BatchRunner& br);
+int validate_params(const ebof_params* p);
 int check_hip(ebof_ctx* ctx, hipError_t e, const char* what);
 void serve_shutdown(ebof_ctx* ctx);
 }  // namespace ebof

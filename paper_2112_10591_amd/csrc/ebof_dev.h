@@ -60,6 +60,9 @@ struct WinDesc {
     const float* pyr_prev;  // reference pyramid for the flow, or null
     const uint8_t* mask;    // reference edge image for EBOF_MASK_FLOW, or null
     float* flow;            // 2*W*H output flow
+    uint8_t* mask_out;      // W*H copy of the reference edge image, or null
+    uint32_t zero_out;      // no reference window: flow and mask_out written as 0
+    uint32_t pad1;
     double2* puv;           // patch displacements (u, v), all levels
     unsigned long long* n_dropped;  // optional counter
     LevelGeom lv[kMaxLevels];
@@ -79,13 +82,18 @@ enum Stage : int32_t {
     kNumStages = kStDensify + 1
 };
 
-// Batched launch arguments (device table form).
+// Batched launch arguments (device table form).  The table holds the window
+// count, then per window i (and i = nwin) the running sums of every stage's
+// items (prefix[i * kNumStages + stage]), then the descriptors.  Reading the
+// count from memory lets one captured graph serve batches of any size.
 struct BatchArgs {
-    const WinDesc* tab;     // nwin descriptors
-    const int32_t* prefix;  // nwin + 1 running sums of this stage's items
-    int32_t nwin;
+    const WinDesc* tab;     // descriptors
+    const int32_t* prefix;  // prefix[i * kNumStages + stage]
+    const int32_t* nwin;    // number of windows
+    int32_t stage;
     int32_t pad;
 };
+constexpr size_t kTableHeader = 256;  // bytes before the prefix sums
 
 // Host-side launch description.
 struct Launch {
@@ -99,6 +107,9 @@ struct Launch {
 
 // Work items of one stage for one window (0 when the stage does not apply).
 int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero);
+
+// stage item counts of a window described by d
+inline bool desc_has_flow(const WinDesc& d) { return d.pyr_prev != nullptr; }
 
 void launch_zero(const Launch& L);
 void launch_scatter(const Launch& L);

@@ -23,15 +23,15 @@ __device__ __forceinline__ const WinDesc* locate(const WinDesc& one, const Batch
         local = item;
         return &one;
     } else {
-        int lo = 0, hi = ba.nwin - 1;
+        int lo = 0, hi = *ba.nwin - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (ba.prefix[mid] <= item)
+            if (ba.prefix[mid * kNumStages + ba.stage] <= item)
                 lo = mid;
             else
                 hi = mid - 1;
         }
-        local = item - ba.prefix[lo];
+        local = item - ba.prefix[lo * kNumStages + ba.stage];
         return ba.tab + lo;
     }
 }
@@ -39,7 +39,7 @@ __device__ __forceinline__ const WinDesc* locate(const WinDesc& one, const Batch
 template <bool B>
 __device__ __forceinline__ int32_t item_total(const BatchArgs& ba, int32_t total_arg) {
     if constexpr (B)
-        return ba.prefix[ba.nwin];
+        return ba.prefix[*ba.nwin * kNumStages + ba.stage];
     else
         return total_arg;
 }
@@ -716,12 +716,19 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const int x = (local % tiles_x) * 64 + (threadIdx.x & 63);
         const int y = (local / tiles_x) * kDensTileH + (threadIdx.x >> 6);
         if (x >= W || y >= H) continue;
+        const size_t pix = (size_t)y * W + x;
+        if (d->zero_out) {  // first window of a served stream: no flow yet
+            d->flow[pix] = 0.f;
+            d->flow[(size_t)W * H + pix] = 0.f;
+            if (d->mask_out) d->mask_out[pix] = 0;
+            continue;
+        }
         const int s = d->stride;
         const float* __restrict__ I0 = d->pyr_prev;
         const float* __restrict__ I1 = d->pyr;
         const double2* __restrict__ pu = d->puv + g.poff;
         const Cover cx = cover_of(x, W, g.pnx, s), cy = cover_of(y, H, g.pny, s);
-        const double i0 = I0[(size_t)y * W + x];
+        const double i0 = I0[pix];
         double sw = 0.0, su = 0.0, sv = 0.0;
         for (int qy = 0; qy < cy.n; ++qy) {
             const int ky = cover_index(cy, qy);
@@ -735,9 +742,11 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
             }
         }
         float fu = (float)(su / sw), fv = (float)(sv / sw);
-        if ((d->flags & EBOF_MASK_FLOW) && d->mask && !d->mask[(size_t)y * W + x]) fu = fv = 0.f;
-        d->flow[(size_t)y * W + x] = fu;
-        d->flow[(size_t)W * H + (size_t)y * W + x] = fv;
+        const uint8_t m = d->mask ? d->mask[pix] : 1;
+        if ((d->flags & EBOF_MASK_FLOW) && !m) fu = fv = 0.f;
+        d->flow[pix] = fu;
+        d->flow[(size_t)W * H + pix] = fv;
+        if (d->mask_out) d->mask_out[pix] = m;
     }
 }
 
@@ -803,7 +812,8 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero) {
         const LevelGeom& g = d.lv[l];
         return g.pny * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
     }
-    if (stage == kStDensify) return has_flow ? ((d.W + 63) / 64) * ((d.H + kDensTileH - 1) / kDensTileH) : 0;
+    if (stage == kStDensify)
+        return (has_flow || d.zero_out) ? ((d.W + 63) / 64) * ((d.H + kDensTileH - 1) / kDensTileH) : 0;
     return 0;
 }
 

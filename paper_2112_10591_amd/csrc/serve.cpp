@@ -1,18 +1,538 @@
-// serve.cpp -- serving runtime (placeholder until the batch former lands).
+// serve.cpp -- serving runtime.
+//
+// A served stream keeps its last window's pyramid and edge image resident in
+// the arena (two of each, swapped per window) plus its own scratch; opening a
+// stream is admitted only while the arena can hold that state.  Submitted
+// windows are queued; their host events are copied into a pinned ring and
+// sent asynchronously (copy stream) into a device ring in the arena.  A
+// batch-former thread takes whatever is queued (at most one window per
+// stream per batch, in submission order) as soon as fewer than two batches
+// are on the GPU, and runs it as one launch per stage on the compute stream
+// (one captured graph, replayed for every batch).  A completion thread waits
+// for each batch and timestamps its windows.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <set>
+
 #include "ctx.h"
 
 namespace ebof {
-struct ServeState {};
-void serve_shutdown(ebof_ctx*) {}
+
+static int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+constexpr int kMaxInflight = 2;       // batches on the GPU at once
+constexpr int kServeMaxBatch = 256;   // windows per batch
+constexpr size_t kPinnedRing = size_t(128) << 20;
+constexpr size_t kDevRingMax = size_t(1) << 30;
+
+static size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// FIFO ring of byte ranges; ranges are released in any order, space is
+// reclaimed from the oldest live range on.
+class Ring {
+   public:
+    void init(size_t size) {
+        size_ = size;
+        head_ = 0;
+        live_.clear();
+    }
+    bool alloc(size_t len, size_t* off) {
+        len = a256(len ? len : 1);
+        if (len > size_) return false;
+        size_t o;
+        if (live_.empty()) {
+            o = 0;
+        } else {
+            const size_t front = live_.front().off;
+            if (head_ > front) {  // not wrapped: free space is [head, size) and [0, front)
+                if (head_ + len <= size_)
+                    o = head_;
+                else if (len <= front)
+                    o = 0;
+                else
+                    return false;
+            } else {  // wrapped: free space is [head, front)
+                if (head_ + len <= front)
+                    o = head_;
+                else
+                    return false;
+            }
+        }
+        live_.push_back({o, len, false});
+        head_ = o + len;
+        *off = o;
+        return true;
+    }
+    void release(size_t off) {
+        for (auto& s : live_)
+            if (s.off == off && !s.done) {
+                s.done = true;
+                break;
+            }
+        while (!live_.empty() && live_.front().done) live_.pop_front();
+        if (live_.empty()) head_ = 0;
+    }
+
+   private:
+    struct Seg {
+        size_t off, len;
+        bool done;
+    };
+    size_t size_ = 0, head_ = 0;
+    std::deque<Seg> live_;
+};
+
+struct ServeStream {
+    ebof_params p;
+    Geom g;
+    Scratch scr;
+    float* pyr[2] = {nullptr, nullptr};
+    uint8_t* edge[2] = {nullptr, nullptr};
+    int cur = 0;  // buffer of the newest window taken into a batch
+    bool has_prev = false;
+    int64_t last_t0 = 0;
+    bool closing = false;
+    int queued = 0;  // submitted and not completed
+};
+
+struct Pending {
+    uint64_t ticket;
+    int32_t sid;
+    const uint16_t* x;
+    const uint16_t* y;
+    const int64_t* t;
+    int64_t n, t0;
+    bool dev_ring;     // events live in the device ring at dev_off
+    size_t dev_off;
+    hipEvent_t copied; // copy into the device ring (null for caller's device events)
+    float* flow_out;
+    uint8_t* mask_out;
+};
+
+struct TicketInfo {
+    int32_t status = EBOF_E_AGAIN;
+    bool done = false;
+    int64_t t_submit = 0, t_done = 0;
+};
+
+struct Batch {
+    hipEvent_t done = nullptr;
+    std::vector<uint64_t> tickets;
+    std::vector<int32_t> status;
+    std::vector<int32_t> sids;
+    std::vector<size_t> dev_offs;  // device ring ranges to release
+    std::vector<hipEvent_t> copy_events;
+};
+
+struct ServeState {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread former, reaper;
+    bool stop = false;
+    hipStream_t stream = nullptr, copy_stream = nullptr;
+    std::map<int32_t, ServeStream> streams;
+    int32_t next_sid = 1;
+    std::deque<Pending> queue;
+    std::unordered_map<uint64_t, TicketInfo> tickets;
+    uint64_t next_ticket = 1;
+    char* pinned = nullptr;
+    Ring pin_ring;
+    std::deque<std::pair<size_t, hipEvent_t>> pin_live;  // (offset, copy event)
+    char* dev_ring = nullptr;
+    size_t dev_ring_bytes = 0;
+    Ring dev_ring_alloc;
+    std::vector<hipEvent_t> event_pool;
+    std::deque<Batch> inflight;
+    BatchRunner runner;
+    int32_t error = EBOF_OK;
+};
+
+static hipEvent_t get_event(ServeState* S) {
+    if (!S->event_pool.empty()) {
+        hipEvent_t e = S->event_pool.back();
+        S->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// pinned ranges whose copy has finished go back to the ring
+static void reclaim_pinned(ServeState* S) {
+    while (!S->pin_live.empty()) {
+        auto& f = S->pin_live.front();
+        if (hipEventQuery(f.second) != hipSuccess) break;
+        S->pin_ring.release(f.first);
+        S->event_pool.push_back(f.second);
+        S->pin_live.pop_front();
+    }
+}
+
+static void former_loop(ebof_ctx* ctx, ServeState* S) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        S->cv_work.wait(lk, [&] { return S->stop || (!S->queue.empty() && (int)S->inflight.size() < kMaxInflight); });
+        if (S->stop) break;
+        // take at most one window per stream, in submission order
+        std::vector<Pending> take;
+        std::set<int32_t> used;
+        for (auto it = S->queue.begin(); it != S->queue.end() && (int)take.size() < kServeMaxBatch;) {
+            if (used.count(it->sid)) {
+                ++it;
+                continue;
+            }
+            used.insert(it->sid);
+            take.push_back(*it);
+            it = S->queue.erase(it);
+        }
+        const int n = (int)take.size();
+        std::vector<ebof_window> win(n);
+        std::vector<WinExtra> ext(n);
+        std::vector<Scratch*> scr(n);
+        Batch b;
+        for (int i = 0; i < n; ++i) {
+            const Pending& q = take[i];
+            ServeStream& s = S->streams[q.sid];
+            if (s.has_prev && !(s.p.flags & EBOF_CHAIN_ALWAYS) && q.t0 != s.last_t0 + s.p.dt_us)
+                s.has_prev = false;  // gap in time: start over
+            const int nb = s.has_prev ? (s.cur ^ 1) : s.cur;
+            ebof_window& w = win[i];
+            std::memset(&w, 0, sizeof w);
+            w.params = &s.p;
+            w.x = q.x;
+            w.y = q.y;
+            w.t = q.t;
+            w.n = q.n;
+            w.t0_us = q.t0;
+            w.edge_out = s.edge[nb];
+            w.pyr_out = s.pyr[nb];
+            w.pyr_prev = s.has_prev ? s.pyr[s.cur] : nullptr;
+            w.mask = s.has_prev ? s.edge[s.cur] : nullptr;
+            w.flow_out = q.flow_out;
+            ext[i].mask_out = q.mask_out;
+            ext[i].zero_out = !s.has_prev;
+            scr[i] = &s.scr;
+            b.tickets.push_back(q.ticket);
+            b.status.push_back(s.has_prev ? EBOF_OK : EBOF_NO_FLOW);
+            b.sids.push_back(q.sid);
+            if (q.dev_ring) b.dev_offs.push_back(q.dev_off);
+            if (q.copied) b.copy_events.push_back(q.copied);
+            s.cur = nb;
+            s.has_prev = true;
+            s.last_t0 = q.t0;
+        }
+        // the batch's event copies were queued in order on the copy stream:
+        // waiting for the last one covers all of them
+        int rc = EBOF_OK;
+        if (!b.copy_events.empty())
+            rc = check_hip(ctx, hipStreamWaitEvent(S->stream, b.copy_events.back(), 0), "hipStreamWaitEvent");
+        if (rc == EBOF_OK) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            rc = run_batch_impl(ctx, S->runner, win.data(), ext.data(), n, S->stream, scr.data(), kGraphUniversal);
+        }
+        b.done = get_event(S);
+        if (rc == EBOF_OK && b.done) rc = check_hip(ctx, hipEventRecord(b.done, S->stream), "hipEventRecord");
+        if (rc != EBOF_OK) {
+            for (auto& st : b.status) st = rc;
+            S->error = rc;
+        }
+        S->inflight.push_back(std::move(b));
+        S->cv_done.notify_all();
+    }
+}
+
+static void reaper_loop(ServeState* S) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        S->cv_done.wait(lk, [&] { return S->stop || !S->inflight.empty(); });
+        if (S->inflight.empty()) {
+            if (S->stop) break;
+            continue;
+        }
+        hipEvent_t ev = S->inflight.front().done;
+        lk.unlock();
+        bool failed = !ev || hipEventSynchronize(ev) != hipSuccess;
+        const int64_t t = now_ns();
+        lk.lock();
+        Batch b = std::move(S->inflight.front());
+        S->inflight.pop_front();
+        for (size_t i = 0; i < b.tickets.size(); ++i) {
+            auto it = S->tickets.find(b.tickets[i]);
+            if (it != S->tickets.end()) {
+                it->second.done = true;
+                it->second.status = failed ? EBOF_E_DEVICE : b.status[i];
+                it->second.t_done = t;
+            }
+            auto st = S->streams.find(b.sids[i]);
+            if (st != S->streams.end()) --st->second.queued;
+        }
+        for (size_t off : b.dev_offs) S->dev_ring_alloc.release(off);
+        for (hipEvent_t e : b.copy_events) S->event_pool.push_back(e);
+        if (b.done) S->event_pool.push_back(b.done);
+        if (failed) S->error = EBOF_E_DEVICE;
+        S->cv_work.notify_all();
+        S->cv_done.notify_all();
+    }
+}
+
+static int serve_init(ebof_ctx* ctx) {
+    if (ctx->serve) return EBOF_OK;
+    auto* S = new ServeState();
+    int rc = check_hip(ctx, hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (!rc) rc = check_hip(ctx, hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (!rc) rc = check_hip(ctx, hipHostMalloc((void**)&S->pinned, kPinnedRing, hipHostMallocDefault), "hipHostMalloc");
+    if (!rc) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        S->dev_ring_bytes = std::min(kDevRingMax, (ctx->arena.bytes_free() / 4) & ~size_t(255));
+        S->dev_ring = S->dev_ring_bytes ? (char*)ctx->arena.alloc(S->dev_ring_bytes) : nullptr;
+        if (!S->dev_ring) {
+            set_error("arena too small for the serving event ring");
+            rc = EBOF_E_NOMEM;
+        }
+    }
+    if (rc) {
+        if (S->stream) (void)hipStreamDestroy(S->stream);
+        if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
+        if (S->pinned) (void)hipHostFree(S->pinned);
+        delete S;
+        return rc;
+    }
+    S->pin_ring.init(kPinnedRing);
+    S->dev_ring_alloc.init(S->dev_ring_bytes);
+    ctx->serve = S;
+    S->former = std::thread(former_loop, ctx, S);
+    S->reaper = std::thread(reaper_loop, S);
+    return EBOF_OK;
+}
+
+void serve_shutdown(ebof_ctx* ctx) {
+    ServeState* S = ctx->serve;
+    if (!S) return;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty(); });
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    S->cv_done.notify_all();
+    S->former.join();
+    S->reaper.join();
+    (void)hipStreamSynchronize(S->stream);
+    (void)hipStreamSynchronize(S->copy_stream);
+    runner_release(S->runner);
+    for (auto& pl : S->pin_live) (void)hipEventDestroy(pl.second);
+    for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(S->stream);
+    (void)hipStreamDestroy(S->copy_stream);
+    (void)hipHostFree(S->pinned);
+    delete S;
+    ctx->serve = nullptr;
+}
+
+static void free_stream(ebof_ctx* ctx, ServeStream& s) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (int i = 0; i < 2; ++i) {
+        ctx->arena.free(s.pyr[i]);
+        ctx->arena.free(s.edge[i]);
+        s.pyr[i] = nullptr;
+        s.edge[i] = nullptr;
+    }
+    scratch_free(ctx, &s.scr);
+}
+
 }  // namespace ebof
 
 using namespace ebof;
 
 extern "C" {
-int ebof_stream_open(ebof_ctx*, const ebof_params*, int32_t*) { set_error("serving not built"); return EBOF_E_STATE; }
-int ebof_stream_close(ebof_ctx*, int32_t) { set_error("serving not built"); return EBOF_E_STATE; }
-int ebof_submit(ebof_ctx*, int32_t, const uint16_t*, const uint16_t*, const int64_t*, int64_t, int64_t, int, float*,
-                uint8_t*, uint64_t*) { set_error("serving not built"); return EBOF_E_STATE; }
-int ebof_poll(ebof_ctx*, uint64_t, int32_t*) { set_error("serving not built"); return EBOF_E_STATE; }
-int ebof_drain(ebof_ctx*) { return EBOF_OK; }
+
+int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
+    if (!ctx || !stream_id) {
+        set_error("ebof_stream_open: NULL ctx or stream_id");
+        return EBOF_E_INVAL;
+    }
+    if (ctx->failed) return EBOF_E_DEVICE;
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if ((rc = serve_init(ctx))) return rc;
+    ServeState* S = ctx->serve;
+    ServeStream s;
+    s.p = *p;
+    s.g = make_geom(*p);
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        Lut lut;
+        if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+        const size_t N = (size_t)p->width * p->height;
+        bool ok = true;
+        for (int i = 0; i < 2; ++i) {
+            s.pyr[i] = (float*)ctx->arena.alloc(s.g.pyr_floats * sizeof(float));
+            s.edge[i] = (uint8_t*)ctx->arena.alloc(N);
+            ok = ok && s.pyr[i] && s.edge[i];
+        }
+        if (ok) ok = scratch_alloc(ctx, s.g, &s.scr, S->stream) == EBOF_OK;
+        if (!ok) {
+            for (int i = 0; i < 2; ++i) {
+                ctx->arena.free(s.pyr[i]);
+                ctx->arena.free(s.edge[i]);
+            }
+            scratch_free(ctx, &s.scr);
+            set_error("arena full: a %dx%d stream needs %zu bytes of resident state, %zu free", p->width, p->height,
+                      2 * (size_t)s.g.pyr_floats * 4 + 2 * N + (size_t)ebof_window_scratch_bytes(p),
+                      ctx->arena.bytes_free());
+            return EBOF_E_NOMEM;
+        }
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int32_t sid = S->next_sid++;
+    S->streams[sid] = s;
+    *stream_id = sid;
+    return EBOF_OK;
 }
+
+int ebof_stream_close(ebof_ctx* ctx, int32_t stream_id) {
+    if (!ctx || !ctx->serve) {
+        set_error("ebof_stream_close: no served stream");
+        return EBOF_E_NOTFOUND;
+    }
+    ServeState* S = ctx->serve;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->streams.find(stream_id);
+    if (it == S->streams.end()) {
+        set_error("ebof_stream_close: unknown stream %d", stream_id);
+        return EBOF_E_NOTFOUND;
+    }
+    it->second.closing = true;
+    S->cv_done.wait(lk, [&] {
+        auto j = S->streams.find(stream_id);
+        return j->second.queued == 0;
+    });
+    ServeStream s = it->second;
+    S->streams.erase(stream_id);
+    lk.unlock();
+    free_stream(ctx, s);
+    return EBOF_OK;
+}
+
+int ebof_submit(ebof_ctx* ctx, int32_t stream_id, const uint16_t* x, const uint16_t* y, const int64_t* t, int64_t n,
+                int64_t t0_us, int events_on_device, float* flow_out_dev, uint8_t* mask_out_dev, uint64_t* ticket) {
+    if (!ctx || !ctx->serve || !ticket || !flow_out_dev || n < 0 || (n > 0 && (!x || !y || !t))) {
+        set_error("ebof_submit: bad arguments");
+        return (!ctx || !ctx->serve) ? EBOF_E_STATE : EBOF_E_INVAL;
+    }
+    ServeState* S = ctx->serve;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->error) {
+        set_error("serving failed earlier (device error)");
+        return S->error;
+    }
+    auto it = S->streams.find(stream_id);
+    if (it == S->streams.end()) {
+        set_error("ebof_submit: unknown stream %d", stream_id);
+        return EBOF_E_NOTFOUND;
+    }
+    ServeStream& s = it->second;
+    if (s.closing) {
+        set_error("ebof_submit: stream %d is closing", stream_id);
+        return EBOF_E_STATE;
+    }
+    if (t0_us > INT64_MAX - s.p.dt_us) {
+        set_error("ebof_submit: t0 + dt overflows");
+        return EBOF_E_INVAL;
+    }
+    Pending q;
+    std::memset(&q, 0, sizeof q);
+    q.sid = stream_id;
+    q.n = n;
+    q.t0 = t0_us;
+    q.flow_out = flow_out_dev;
+    q.mask_out = mask_out_dev;
+    if (events_on_device || n == 0) {
+        q.x = x;
+        q.y = y;
+        q.t = t;
+    } else {
+        // host events: pinned ring -> device ring, asynchronously
+        reclaim_pinned(S);
+        const size_t bx = a256(2 * (size_t)n), bt = a256(8 * (size_t)n);
+        const size_t len = 2 * bx + bt;
+        size_t doff, poff;
+        if (!S->dev_ring_alloc.alloc(len, &doff)) {
+            set_error("ebof_submit: device event ring full");
+            return EBOF_E_AGAIN;
+        }
+        if (!S->pin_ring.alloc(len, &poff)) {
+            S->dev_ring_alloc.release(doff);
+            set_error("ebof_submit: pinned staging full");
+            return EBOF_E_AGAIN;
+        }
+        char* hp = S->pinned + poff;
+        std::memcpy(hp, x, 2 * (size_t)n);
+        std::memcpy(hp + bx, y, 2 * (size_t)n);
+        std::memcpy(hp + 2 * bx, t, 8 * (size_t)n);
+        char* dp = S->dev_ring + doff;
+        hipEvent_t ev = get_event(S);
+        hipEvent_t ev_pin = get_event(S);
+        int rc = EBOF_OK;
+        if (!ev || !ev_pin) rc = check_hip(ctx, hipErrorOutOfMemory, "hipEventCreate");
+        if (!rc) rc = check_hip(ctx, hipMemcpyAsync(dp, hp, len, hipMemcpyHostToDevice, S->copy_stream), "hipMemcpyAsync");
+        if (!rc) rc = check_hip(ctx, hipEventRecord(ev, S->copy_stream), "hipEventRecord");
+        if (!rc) rc = check_hip(ctx, hipEventRecord(ev_pin, S->copy_stream), "hipEventRecord");
+        if (rc) {
+            S->dev_ring_alloc.release(doff);
+            S->pin_ring.release(poff);
+            return rc;
+        }
+        S->pin_live.push_back({poff, ev_pin});
+        q.x = (const uint16_t*)dp;
+        q.y = (const uint16_t*)(dp + bx);
+        q.t = (const int64_t*)(dp + 2 * bx);
+        q.dev_ring = true;
+        q.dev_off = doff;
+        q.copied = ev;
+    }
+    q.ticket = S->next_ticket++;
+    TicketInfo ti;
+    ti.t_submit = now_ns();
+    S->tickets[q.ticket] = ti;
+    ++s.queued;
+    S->queue.push_back(q);
+    *ticket = q.ticket;
+    S->cv_work.notify_all();
+    return EBOF_OK;
+}
+
+int ebof_poll(ebof_ctx* ctx, uint64_t ticket, int32_t* status, int64_t* latency_ns) {
+    if (!ctx || !ctx->serve || !status) {
+        set_error("ebof_poll: bad arguments");
+        return EBOF_E_NOTFOUND;
+    }
+    ServeState* S = ctx->serve;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) {
+        set_error("ebof_poll: unknown ticket %llu", (unsigned long long)ticket);
+        return EBOF_E_NOTFOUND;
+    }
+    if (!it->second.done) return EBOF_E_AGAIN;
+    *status = it->second.status;
+    if (latency_ns) *latency_ns = it->second.t_done - it->second.t_submit;
+    S->tickets.erase(it);
+    return EBOF_OK;
+}
+
+int ebof_drain(ebof_ctx* ctx) {
+    if (!ctx) return EBOF_E_INVAL;
+    ServeState* S = ctx->serve;
+    if (!S) return EBOF_OK;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty(); });
+    return S->error;
+}
+
+}  // extern "C"

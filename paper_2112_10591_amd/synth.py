@@ -358,9 +358,14 @@ def generate(name, sid, ks, workers=8):
     """Windows ks of stream `sid` of workload `name` ("c1".."c5"), as a list
     of dicts x, y, t, t0 (polarity dropped), generated by `workers`
     processes."""
+    return generate_jobs([(name, sid, k) for k in ks], workers)
+
+
+def generate_jobs(jobs, workers=8):
+    """Windows for a list of (workload, stream id, window index) jobs."""
     import concurrent.futures as cf
     import multiprocessing as mp
-    jobs = [(name, sid, k) for k in ks]
+    jobs = list(jobs)
     if workers <= 1 or len(jobs) < 4:
         res = [_gen_one(j) for j in jobs]
     else:

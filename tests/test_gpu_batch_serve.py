@@ -1,0 +1,200 @@
+"""Batched and served forms against the single-window stage calls.
+
+Every window's outputs must be the same alone (stage calls) and inside a
+batch of windows of other streams and resolutions, in the directly launched
+batch, in every replay of its captured graph, and through the serving loop
+(where windows of many streams arrive interleaved and are batched as they
+come).  Designed for bit-identity: the kernels do the same arithmetic for a
+window whatever else shares the launch.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_10591_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_2112_10591_amd._lib")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = L.ebof_create(arena_bytes=3 << 30)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def mixed_streams(n_low=3, n_hd=2, windows=3):
+    """(params, [events per window]) for a mix of 346x260 and 1280x720 streams."""
+    out = []
+    for i in range(n_low + n_hd):
+        s = synth.c3_streams()[i if i < n_low else 10 + i - n_low]
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+        evs = []
+        for k in range(windows):
+            w = s.window(k)
+            evs.append(dict(x=dev(w["x"]), y=dev(w["y"]), t=dev(w["t"]), t0=w["t0"]))
+        out.append((p, evs))
+    return out
+
+
+def alone(ctx, p, evs):
+    """Stage calls, one window at a time: edge, d2, pyramid and flow per window."""
+    W, H = p.width, p.height
+    P = L.ebof_pyramid_floats(p)
+    res, prev = [], None
+    for ev in evs:
+        e = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+        d2 = torch.empty(W * H, dtype=torch.int32, device="cuda")
+        pr = torch.empty(P, dtype=torch.float32, device="cuda")
+        L.ebof_bin_events(ctx, p, ev["x"], ev["y"], ev["t"], ev["t0"], e)
+        L.ebof_edt_surface(ctx, p, e, pr, d2)
+        f = None
+        if prev is not None:
+            f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+            L.ebof_flow(ctx, p, prev[1], pr, f, mask=prev[0])
+        res.append((e, pr, d2, f))
+        prev = (e, pr)
+    torch.cuda.synchronize()
+    return res
+
+
+def test_batch_equals_alone_and_graph_replays(ctx):
+    streams = mixed_streams()
+    ref = [alone(ctx, p, evs) for p, evs in streams]
+    outs = []
+    for p, evs in streams:
+        W, H = p.width, p.height
+        P = L.ebof_pyramid_floats(p)
+        outs.append([dict(edge=torch.empty(W * H, dtype=torch.uint8, device="cuda"),
+                          d2=torch.empty(W * H, dtype=torch.int32, device="cuda"),
+                          pyr=torch.empty(P, dtype=torch.float32, device="cuda"),
+                          flow=torch.empty(2 * W * H, dtype=torch.float32, device="cuda"))
+                     for _ in evs])
+    stream = torch.cuda.Stream()
+    nwin = len(streams[0][1])
+    for rep in range(3):  # first pass captures the graphs, later ones replay them
+        for k in range(nwin):
+            batch = []
+            for s, (p, evs) in enumerate(streams):
+                o = outs[s][k]
+                w = dict(params=p, x=evs[k]["x"], y=evs[k]["y"], t=evs[k]["t"], t0_us=evs[k]["t0"],
+                         edge_out=o["edge"], d2_out=o["d2"], pyr_out=o["pyr"])
+                if k > 0:
+                    w.update(pyr_prev=outs[s][k - 1]["pyr"], mask=outs[s][k - 1]["edge"], flow_out=o["flow"])
+                batch.append(w)
+            _say(f"batch rep {rep} window {k}: {len(batch)} windows")
+            L.ebof_run_batch(ctx, batch, stream=stream)
+            # the program's own eager work between replays
+            torch.cuda.synchronize()
+        for s in range(len(streams)):
+            for k in range(nwin):
+                r, o = ref[s][k], outs[s][k]
+                assert torch.equal(o["edge"], r[0]), (rep, s, k, "edge")
+                assert torch.equal(o["pyr"], r[1]), (rep, s, k, "pyramid")
+                assert torch.equal(o["d2"], r[2]), (rep, s, k, "d2")
+                if k > 0:
+                    assert torch.equal(o["flow"], r[3]), (rep, s, k, "flow")
+        for s in range(len(streams)):  # scribble so a stale replay cannot pass
+            for k in range(nwin):
+                for v in outs[s][k].values():
+                    v.zero_()
+
+
+def test_serving_alone_vs_mix(ctx):
+    streams = mixed_streams(n_low=4, n_hd=2, windows=4)
+    ref = [alone(ctx, p, evs) for p, evs in streams]
+    sids = [L.ebof_stream_open(ctx, p) for p, _ in streams]
+    outs = {}
+    tickets = {}
+    nwin = len(streams[0][1])
+    # interleave the streams' windows, host events for half the streams
+    for k in range(nwin):
+        for s, (p, evs) in enumerate(streams):
+            W, H = p.width, p.height
+            f = torch.full((2 * W * H,), 7.0, dtype=torch.float32, device="cuda")
+            m = torch.full((W * H,), 9, dtype=torch.uint8, device="cuda")
+            ev = evs[k]
+            if s % 2:
+                x, y, t = ev["x"].cpu().numpy(), ev["y"].cpu().numpy(), ev["t"].cpu().numpy()
+            else:
+                x, y, t = ev["x"], ev["y"], ev["t"]
+            tk = None
+            while tk is None:
+                tk = L.ebof_submit(ctx, sids[s], p, x, y, t, ev["t0"], f, m)
+            tickets[(s, k)] = tk
+            outs[(s, k)] = (f, m)
+    _say(f"served {len(tickets)} windows")
+    L.ebof_drain(ctx)
+    for (s, k), tk in tickets.items():
+        st, lat = L.ebof_poll(ctx, tk, with_latency=True)
+        f, m = outs[(s, k)]
+        assert lat > 0
+        if k == 0:
+            assert st == L.EBOF_NO_FLOW
+            assert torch.count_nonzero(f) == 0 and torch.count_nonzero(m) == 0
+        else:
+            assert st == L.EBOF_OK
+            assert torch.equal(f, ref[s][k][3]), (s, k, "flow")
+            assert torch.equal(m, ref[s][k - 1][0]), (s, k, "mask")
+    with pytest.raises(L.EbofError):
+        L.ebof_poll(ctx, tickets[(0, 1)])  # already reported
+    for sid in sids:
+        L.ebof_stream_close(ctx, sid)
+
+
+def test_serving_gap_resets_stream(ctx):
+    s = synth.c1_stream(0)
+    p = L.ebof_params_default(s.W, s.H)
+    sid = L.ebof_stream_open(ctx, p)
+    W, H = s.W, s.H
+    sts = []
+    for k, shift in [(0, 0), (1, 0), (2, 5 * synth.DT_US)]:  # the third window skips ahead
+        w = s.window(k)
+        f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+        m = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+        tk = L.ebof_submit(ctx, sid, p, w["x"], w["y"], w["t"] + shift, w["t0"] + shift, f, m)
+        L.ebof_drain(ctx)
+        sts.append(L.ebof_poll(ctx, tk))
+    assert sts == [L.EBOF_NO_FLOW, L.EBOF_OK, L.EBOF_NO_FLOW]
+    L.ebof_stream_close(ctx, sid)
+    with pytest.raises(L.EbofError):
+        L.ebof_stream_close(ctx, sid)
+
+
+def test_serving_admission_by_arena():
+    """A context whose arena cannot hold a 1280x720 stream's resident state
+    refuses the stream (EBOF_E_NOMEM); a window larger than the event ring is
+    refused with EBOF_E_AGAIN."""
+    c = L.ebof_create(arena_bytes=16 << 20)
+    try:
+        p_hd = L.ebof_params_default(1280, 720)
+        with pytest.raises(L.EbofError) as ei:
+            L.ebof_stream_open(c, p_hd)
+        assert ei.value.code == L.EBOF_E_NOMEM
+        p = L.ebof_params_default(346, 260)
+        sid = L.ebof_stream_open(c, p)
+        n = 1_000_000  # 12 MB of events, more than the ring of this small arena
+        x = np.zeros(n, np.uint16)
+        t = np.zeros(n, np.int64)
+        f = torch.empty(2 * 346 * 260, dtype=torch.float32, device="cuda")
+        m = torch.empty(346 * 260, dtype=torch.uint8, device="cuda")
+        assert L.ebof_submit(c, sid, p, x, x, t, 0, f, m) is None
+        L.ebof_stream_close(c, sid)
+    finally:
+        torch.cuda.synchronize()
+        c.close()
