@@ -374,12 +374,12 @@ def _palindrome(k, n):
     return j if j < n else period - j
 
 
-def _submit(L, ctx, cam, pend):
+def _submit(L, ctx, cam, pend, lat=None):
     """Submit the camera's next pooled window into a free output slot."""
     import ctypes
     slot = cam["k"] % len(cam["outs"])
     while cam["busy"][slot] is not None:  # output slot still in flight
-        _reap(L, ctx, pend, block=True)
+        _reap(L, ctx, pend, block=True, lat=lat)
     ev = cam["evs"][_palindrome(cam["k"], len(cam["evs"]))]
     f, m = cam["outs"][slot]
     tk = ctypes.c_uint64()
@@ -392,7 +392,7 @@ def _submit(L, ctx, cam, pend):
             break
         if rc != L.EBOF_E_AGAIN:
             raise RuntimeError(ctx.lib.ebof_last_error(ctx.handle).decode())
-        _reap(L, ctx, pend, block=True)
+        _reap(L, ctx, pend, block=True, lat=lat)
     cam["busy"][slot] = tk.value
     cam["k"] += 1
     pend.append((tk.value, cam, slot))
@@ -459,7 +459,7 @@ def bench_serving(L, c4, seconds, dev):
     for ta, c in arrivals:
         while time.perf_counter() - t0 < ta:
             _reap(L, ctx, pend, lat=lat)
-        _submit(L, ctx, cams[c], pend)
+        _submit(L, ctx, cams[c], pend, lat=lat)
     while pend:
         _reap(L, ctx, pend, block=True, lat=lat)
     t_poisson = time.perf_counter() - t0
@@ -470,7 +470,7 @@ def bench_serving(L, c4, seconds, dev):
     n_sat = 0
     c = 0
     while time.perf_counter() - t1 < max(2.0, seconds / 2):
-        _submit(L, ctx, cams[c % len(cams)], pend)
+        _submit(L, ctx, cams[c % len(cams)], pend, lat=sat_lat)
         c += 1
         n_sat += 1
         _reap(L, ctx, pend, lat=sat_lat)
@@ -516,7 +516,7 @@ def bench_burst(L, c4, c5, dev):
         _reap(L, ctx, pend, block=True)
     t0 = time.perf_counter()
     for cam in cams:
-        _submit(L, ctx, cam, pend)
+        _submit(L, ctx, cam, pend, lat=lat)
     t_sub = time.perf_counter() - t0
     while pend:
         _reap(L, ctx, pend, block=True, lat=lat)
