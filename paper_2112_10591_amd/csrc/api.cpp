@@ -268,6 +268,8 @@ void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratc
     d->flags = p.flags;
     d->lambda = p.lambda_reg;
     d->lut_n = lut.n;
+    d->lut_r = 0;
+    while ((int64_t)d->lut_r * d->lut_r < lut.n) ++d->lut_r;
     d->lut = lut.dev;
     d->e_raw = s.e_raw;
     d->colmask = s.colmask;

@@ -21,12 +21,14 @@ constexpr int kBlock = 256;         // threads per block of every kernel
 
 // work-item granularity of each stage
 constexpr int kEventsPerItem = 512;   // scatter: events per block
-constexpr int kTile = 64;             // denoise/fill: 64x64 pixels per block
+constexpr int kTile = 64;             // denoise/fill: 64 wide ...
+constexpr int kTileH = 32;            // ... and 32 tall per block
 constexpr int kChunk = 64;            // column-mask chunk: 64 rows per word
 constexpr int kPyrChain = 3;          // pyramid: levels built per launch
 constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
 constexpr int kDensTileH = 4;         // densify: 64x4 pixels per block
 constexpr int kZeroBytesPerItem = 4096;
+constexpr int kRowSeg = 256;          // EDT row pass: pixels per block
 
 struct LevelGeom {
     int32_t w, h;      // level size
@@ -42,6 +44,8 @@ struct WinDesc {
     uint32_t flags;
     float lambda;
     int32_t lut_n;      // squared distances below lut_n read lut[], others 1.0f
+    int32_t lut_r;      // smallest r with r*r >= lut_n
+    int32_t pad2;
     const float* lut;
     // events of the window, SoA, and the half-open window [t0, t1)
     const uint16_t* ex;

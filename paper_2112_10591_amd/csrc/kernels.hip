@@ -127,43 +127,44 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const WinDesc one, const Bat
 }
 
 // --------------------------------------------------------------------------
-// Alg. 1 then Alg. 2 on one 64x64 tile.  The raw image is staged with a
-// 2-pixel halo, the denoised image E_d is formed on the tile plus a 1-pixel
-// halo (each pixel counts its 4 neighbours in E), then the fill forms E_df on
-// the tile (counting neighbours in E_d).  Pixels off the image are non-edges.
-// Optionally the tile's column bit masks (bit r of word (chunk, x) = E_df at
-// row 64*chunk + r) are written for the distance transform.
+// Alg. 1 then Alg. 2 on one 64-wide, 32-tall tile.  The raw image is staged
+// with a 2-pixel halo, the denoised image E_d is formed on the tile plus a
+// 1-pixel halo (each pixel counts its 4 neighbours in E), then the fill forms
+// E_df on the tile (counting neighbours in E_d).  Pixels off the image are
+// non-edges.  Optionally the tile writes its half of the column bit masks
+// (bit r of word (chunk, x) = E_df at row 64*chunk + r).
 // --------------------------------------------------------------------------
 template <bool B, bool PACK>
 __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, const BatchArgs ba,
                                                          int32_t total_arg) {
-    constexpr int R = kTile + 4;  // raw tile with 2-pixel halo
-    constexpr int D = kTile + 2;  // denoised tile with 1-pixel halo
-    __shared__ uint8_t sE[R][R + 4];
-    __shared__ uint8_t sEd[D][D + 2];
-    __shared__ uint16_t sBits[4][kTile];
+    constexpr int TW = kTile, TH = kTileH;
+    constexpr int RW = TW + 4, RH = TH + 4;  // raw tile with 2-pixel halo
+    constexpr int DW = TW + 2, DH = TH + 2;  // denoised tile with 1-pixel halo
+    __shared__ uint8_t sE[RH][RW + 4];
+    __shared__ uint8_t sEd[DH][DW + 2];
+    __shared__ uint8_t sBits[4][TW];
     const int32_t total = item_total<B>(ba, total_arg);
     const int tid = threadIdx.x;
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
-        const int tiles_x = (W + kTile - 1) / kTile;
+        const int tiles_x = (W + TW - 1) / TW;
         const int tx = local % tiles_x, ty = local / tiles_x;
-        const int x0 = tx * kTile, y0 = ty * kTile;
+        const int x0 = tx * TW, y0 = ty * TH;
         const uint8_t stamp = (uint8_t)d->stamp;
         const uint8_t* __restrict__ er = d->e_raw;
         const int n_d = d->n_d, n_f = d->n_f;
-        for (int i = tid; i < R * R; i += kBlock) {
-            const int lx = i % R, ly = i / R;
+        for (int i = tid; i < RH * RW; i += kBlock) {
+            const int ly = i / RW, lx = i - ly * RW;
             const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
             uint8_t v = 0;
             if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = er[(size_t)gy * W + gx] == stamp;
             sE[ly][lx] = v;
         }
         __syncthreads();
-        for (int i = tid; i < D * D; i += kBlock) {
-            const int lx = i % D, ly = i / D;  // pixel (x0-1+lx, y0-1+ly) = sE[ly+1][lx+1]
+        for (int i = tid; i < DH * DW; i += kBlock) {
+            const int ly = i / DW, lx = i - ly * DW;  // pixel (x0-1+lx, y0-1+ly) = sE[ly+1][lx+1]
             uint8_t v = sE[ly + 1][lx + 1];
             if (v) {
                 const int nb = sE[ly][lx + 1] + sE[ly + 2][lx + 1] + sE[ly + 1][lx] + sE[ly + 1][lx + 2];
@@ -172,11 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, cons
             sEd[ly][lx] = v;
         }
         __syncthreads();
-        const int c = tid & (kTile - 1), rg = tid / kTile;
+        const int c = tid & (TW - 1), seg = tid / TW;  // 4 segments of 8 rows
         const int gx = x0 + c;
         uint32_t bits = 0;
-        for (int r = 0; r < 16; ++r) {
-            const int ly = rg * 16 + r;  // pixel (gx, y0+ly) = sEd[ly+1][c+1]
+#pragma unroll
+        for (int r = 0; r < TH / 4; ++r) {
+            const int ly = seg * (TH / 4) + r;  // pixel (gx, y0+ly) = sEd[ly+1][c+1]
             const int gy = y0 + ly;
             uint8_t v = sEd[ly + 1][c + 1];
             if (!v) {
@@ -189,12 +191,15 @@ __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, cons
             }
         }
         if constexpr (PACK) {
-            sBits[rg][c] = (uint16_t)bits;
+            sBits[seg][c] = (uint8_t)bits;
             __syncthreads();
-            if (tid < kTile && x0 + tid < W) {
-                const uint64_t m = (uint64_t)sBits[0][tid] | ((uint64_t)sBits[1][tid] << 16) |
-                                   ((uint64_t)sBits[2][tid] << 32) | ((uint64_t)sBits[3][tid] << 48);
-                d->colmask[(size_t)ty * W + x0 + tid] = m;
+            if (tid < TW && x0 + tid < W) {
+                const uint32_t m = (uint32_t)sBits[0][tid] | ((uint32_t)sBits[1][tid] << 8) |
+                                   ((uint32_t)sBits[2][tid] << 16) | ((uint32_t)sBits[3][tid] << 24);
+                // this tile is half `ty & 1` of chunk ty/2 (little endian words)
+                uint32_t* half = (uint32_t*)(d->colmask + (size_t)(ty >> 1) * W + x0 + tid);
+                half[ty & 1] = m;
+                if (!(ty & 1) && y0 + TH >= H) half[1] = 0;  // no upper half tile
             }
         }
         __syncthreads();
@@ -317,36 +322,39 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W;
-        const int y = local;
+        const int nseg = (W + kRowSeg - 1) / kRowSeg;
+        const int y = local / nseg, x0 = (local - y * nseg) * kRowSeg;
+        int32_t* d2row = d->d2 ? d->d2 + (size_t)y * W : nullptr;
+        const int lut_n = d->lut_n;
+        // the search never looks further than sqrt(cap) from its pixel
+        const uint32_t cap = d2row ? 0xffffffffu : (uint32_t)lut_n;
+        const int reach = d2row ? W : d->lut_r;
+        const int lo = max(0, x0 - reach), hi = min(W, x0 + kRowSeg + reach);
         const uint16_t* grow = d->g + (size_t)y * W;
         int any = 0;
-        for (int x = threadIdx.x; x < W; x += kBlock) {
+        for (int x = lo + threadIdx.x; x < hi; x += kBlock) {
             const uint32_t gv = grow[x];
             any |= gv != kGInf;
-            sG2[x] = gv == kGInf ? 0x7fffffffu : gv * gv;
+            sG2[x - lo] = gv == kGInf ? 0x7fffffffu : gv * gv;
         }
         any = __syncthreads_or(any);
-        const int lut_n = d->lut_n;
-        const float* __restrict__ lut = d->lut;
-        int32_t* d2row = d->d2 ? d->d2 + (size_t)y * W : nullptr;
-        float* srow = d->pyr + (size_t)y * W;
-        const uint32_t cap = d2row ? 0xffffffffu : (uint32_t)lut_n;
-        for (int x = threadIdx.x; x < W; x += kBlock) {
+        const int x = x0 + threadIdx.x;
+        if (x < W) {
             uint32_t best = 0x7fffffffu;
             if (any) {
-                best = sG2[x];
+                const uint32_t* g2 = sG2 - lo;
+                best = g2[x];
                 for (int r = 1;; ++r) {
                     const uint32_t r2 = (uint32_t)r * (uint32_t)r;
                     if (r2 >= best || r2 >= cap) break;
-                    const bool lft = x - r >= 0, rgt = x + r < W;
+                    const bool lft = x - r >= lo, rgt = x + r < hi;
                     if (!lft && !rgt) break;
-                    if (lft) best = min(best, r2 + sG2[x - r]);
-                    if (rgt) best = min(best, r2 + sG2[x + r]);
+                    if (lft) best = min(best, r2 + g2[x - r]);
+                    if (rgt) best = min(best, r2 + g2[x + r]);
                 }
             }
-            const int32_t d2v = best >= 0x7fffffffu ? 0x7fffffff : (int32_t)best;
-            if (d2row) d2row[x] = d2v;
-            srow[x] = best < (uint32_t)lut_n ? lut[best] : 1.0f;
+            if (d2row) d2row[x] = best >= 0x7fffffffu ? 0x7fffffff : (int32_t)best;
+            d->pyr[(size_t)y * W + x] = best < (uint32_t)lut_n ? d->lut[best] : 1.0f;
         }
         __syncthreads();
     }
@@ -797,9 +805,9 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero) {
     const int bands = (d.W + 63) / 64, nch = (d.H + kChunk - 1) / kChunk;
     if (stage == kStZero) return zero ? (int32_t)((N + kZeroBytesPerItem - 1) / kZeroBytesPerItem) : 0;
     if (stage == kStScatter) return (int32_t)((d.n_ev + kEventsPerItem - 1) / kEventsPerItem);
-    if (stage == kStDenoise) return ((d.W + kTile - 1) / kTile) * ((d.H + kTile - 1) / kTile);
+    if (stage == kStDenoise) return ((d.W + kTile - 1) / kTile) * ((d.H + kTileH - 1) / kTileH);
     if (stage == kStPack || stage == kStCols) return bands * nch;
-    if (stage == kStRows) return d.H;
+    if (stage == kStRows) return d.H * ((d.W + kRowSeg - 1) / kRowSeg);
     if (stage >= kStPyr && stage < kStPyr + kMaxLevels - 1) {
         const int from = (stage - kStPyr) * kPyrChain;
         if (from >= d.L - 1) return 0;

@@ -84,7 +84,8 @@ def random_events(W, H, n, seed, t0=0, dt=10_000, spill=0):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("W,H,n,levels", [
     (8, 8, 20, 1), (13, 9, 40, 1), (64, 64, 300, 3), (65, 130, 2000, 3), (67, 45, 900, 2),
-    (346, 260, 20_000, 3), (200, 33, 3000, 2), (1280, 720, 300_000, 4),
+    (346, 260, 20_000, 3), (200, 33, 3000, 2), (1280, 720, 300_000, 4), (1280, 720, 200_000, 5),
+    (2048, 1100, 120_000, 8),
 ])
 def test_window_random_events(ctx, W, H, n, levels):
     for seed, spill in [(1, 0), (2, 5)]:
@@ -244,7 +245,8 @@ def test_flow_mask(ctx):
 
 
 def test_flow_odd_sizes_and_strides(ctx):
-    for (W, H, lv, st) in [(8, 8, 1, 4), (9, 17, 1, 3), (77, 51, 3, 4), (130, 66, 2, 2), (64, 40, 2, 8)]:
+    for (W, H, lv, st) in [(8, 8, 1, 4), (9, 17, 1, 3), (77, 51, 3, 4), (130, 66, 2, 2), (64, 40, 2, 8),
+                           (520, 400, 5, 4)]:
         _say(f"flow odd W={W} H={H} L={lv} stride={st}")
         p = L.ebof_params_default(W, H, levels=lv, stride=st)
         ev0 = random_events(W, H, W * H // 6, 21)
