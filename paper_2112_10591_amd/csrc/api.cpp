@@ -27,60 +27,6 @@ int check_hip(ebof_ctx* ctx, hipError_t e, const char* what) {
     return EBOF_E_DEVICE;
 }
 
-// ---------------------------------------------------------------- arena
-void Arena::init(char* base, size_t size) {
-    base_ = base;
-    size_ = size;
-    used_ = 0;
-    free_.clear();
-    inuse_.clear();
-    if (size) free_[0] = size;
-}
-
-void* Arena::alloc(size_t bytes, size_t align) {
-    if (bytes == 0) bytes = 1;
-    bytes = (bytes + 255) & ~size_t(255);
-    if (align < 256) align = 256;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-        const size_t off = it->first, sz = it->second;
-        const size_t aoff = (off + align - 1) / align * align;
-        if (aoff + bytes <= off + sz) {
-            free_.erase(it);
-            if (aoff > off) free_[off] = aoff - off;
-            if (off + sz > aoff + bytes) free_[aoff + bytes] = off + sz - (aoff + bytes);
-            inuse_[aoff] = bytes;
-            used_ += bytes;
-            return base_ + aoff;
-        }
-    }
-    return nullptr;
-}
-
-void Arena::free(void* p) {
-    if (!p) return;
-    size_t off = (size_t)((char*)p - base_);
-    auto it = inuse_.find(off);
-    if (it == inuse_.end()) return;
-    size_t sz = it->second;
-    inuse_.erase(it);
-    used_ -= sz;
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && off + sz == nx->first) {
-        sz += nx->second;
-        nx = free_.erase(nx);
-    }
-    if (nx != free_.begin()) {
-        auto pv = std::prev(nx);
-        if (pv->first + pv->second == off) {
-            pv->second += sz;
-            return;
-        }
-    }
-    free_[off] = sz;
-}
-
-size_t Arena::bytes_free() const { return size_ - used_; }
-
 // ---------------------------------------------------------------- params
 static int64_t lut_entries(float alpha, std::vector<float>* out) {
     // squared distances whose surface value is below 1.0f in float

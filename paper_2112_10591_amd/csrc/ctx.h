@@ -16,27 +16,11 @@
 #include <vector>
 
 #include "ebof_dev.h"
+#include "hostlogic.h"
 
 namespace ebof {
 
 void set_error(const char* fmt, ...);
-
-// First-fit sub-allocator over the caller's arena (host bookkeeping only).
-class Arena {
-   public:
-    void init(char* base, size_t size);
-    void* alloc(size_t bytes, size_t align = 256);
-    void free(void* p);
-    size_t bytes_free() const;
-    size_t bytes_used() const { return used_; }
-    bool contains(const void* p) const { return (const char*)p >= base_ && (const char*)p < base_ + size_; }
-
-   private:
-    char* base_ = nullptr;
-    size_t size_ = 0, used_ = 0;
-    std::map<size_t, size_t> free_;   // offset -> size
-    std::map<size_t, size_t> inuse_;  // offset -> size
-};
 
 // Geometry of one parameter set.
 struct Geom {

@@ -31,61 +31,6 @@ constexpr size_t kDevRingMax = size_t(1) << 30;
 
 static size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// FIFO ring of byte ranges; ranges are released in any order, space is
-// reclaimed from the oldest live range on.
-class Ring {
-   public:
-    void init(size_t size) {
-        size_ = size;
-        head_ = 0;
-        live_.clear();
-    }
-    bool alloc(size_t len, size_t* off) {
-        len = a256(len ? len : 1);
-        if (len > size_) return false;
-        size_t o;
-        if (live_.empty()) {
-            o = 0;
-        } else {
-            const size_t front = live_.front().off;
-            if (head_ > front) {  // not wrapped: free space is [head, size) and [0, front)
-                if (head_ + len <= size_)
-                    o = head_;
-                else if (len <= front)
-                    o = 0;
-                else
-                    return false;
-            } else {  // wrapped: free space is [head, front)
-                if (head_ + len <= front)
-                    o = head_;
-                else
-                    return false;
-            }
-        }
-        live_.push_back({o, len, false});
-        head_ = o + len;
-        *off = o;
-        return true;
-    }
-    void release(size_t off) {
-        for (auto& s : live_)
-            if (s.off == off && !s.done) {
-                s.done = true;
-                break;
-            }
-        while (!live_.empty() && live_.front().done) live_.pop_front();
-        if (live_.empty()) head_ = 0;
-    }
-
-   private:
-    struct Seg {
-        size_t off, len;
-        bool done;
-    };
-    size_t size_ = 0, head_ = 0;
-    std::deque<Seg> live_;
-};
-
 struct ServeStream {
     ebof_params p;
     Geom g;
@@ -178,18 +123,8 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
     while (true) {
         S->cv_work.wait(lk, [&] { return S->stop || (!S->queue.empty() && (int)S->inflight.size() < kMaxInflight); });
         if (S->stop) break;
-        // take at most one window per stream, in submission order
-        std::vector<Pending> take;
-        std::set<int32_t> used;
-        for (auto it = S->queue.begin(); it != S->queue.end() && (int)take.size() < kServeMaxBatch;) {
-            if (used.count(it->sid)) {
-                ++it;
-                continue;
-            }
-            used.insert(it->sid);
-            take.push_back(*it);
-            it = S->queue.erase(it);
-        }
+        std::vector<Pending> take =
+            take_one_per_stream(S->queue, kServeMaxBatch, [](const Pending& q) { return q.sid; });
         const int n = (int)take.size();
         std::vector<ebof_window> win(n);
         std::vector<WinExtra> ext(n);
