@@ -14,6 +14,7 @@ form (16 mixed-resolution streams per launch) and the serving loop.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,11 +43,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=6, help="oracle flows in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="oracle flows in the CPU sample (~15 s)")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--serving-pool", type=int, default=12, help="pre-generated windows per camera")
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB three times (the reference kernel "
+                         "for scaling HBM counters)")
+    ap.add_argument("--plain-streams", type=int, default=3,
+                    help="HIP streams the plain path is pipelined over (1 = strictly sequential)")
     return ap.parse_args()
 
 
@@ -61,6 +67,26 @@ def dis_flops_per_patch(iters, init):
     return iters * (64 * 11 + 8) + 64 * 10 + (160 if init else 0)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+    the same counters on a plain copy of known size), or None when there is
+    none for this kernel or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2112_10591_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("kernels_hip_sha256") != sha:
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
 def dis_flops_window(L, p):
     tot = 0
     for l, (w, h) in enumerate(L.level_sizes(p)):
@@ -73,7 +99,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by camera stream, see DESIGN.md)", file=sys.stderr)
+              "(the path shards by camera stream: one context per GPU)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:
         return
@@ -126,6 +152,17 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of its dispatches
+        # calibrate the same counters on the path's kernels
+        nb = args.copy_calib << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {nb} bytes copied")
+        del a, b
     ctx = L.ebof_create(arena_bytes=2 << 30)
     lib, h = ctx.lib, ctx.handle
     stream = torch.cuda.Stream()
@@ -140,9 +177,19 @@ def main():
     for ev in c2:
         evs.append(dict(x=torch.from_numpy(ev["x"]).to(dev), y=torch.from_numpy(ev["y"]).to(dev),
                         t=torch.from_numpy(ev["t"]).to(dev), t0=ev["t0"], n=len(ev["x"])))
-    pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(2)]
-    edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(2)]
-    flow = torch.empty(2 * N, dtype=torch.float32, device=dev)
+    # The plain path is the paper's pipeline (Fig. 1): one camera stream, one
+    # window per launch, stage calls only.  Window k's binning + EDT and the
+    # flow from window k-1 run on HIP stream k mod S; the flow waits for window
+    # k-1's pyramid (an event), and a window reusing a buffer waits for the
+    # flows that last read it, so consecutive windows overlap on the GPU as
+    # the paper's independent blocks do.  S = 1 is the strictly sequential form.
+    NS = max(1, args.plain_streams)
+    NB = NS + 2
+    pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(NB)]
+    edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(NB)]
+    flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NS)]
+    streams = [stream] + [torch.cuda.Stream() for _ in range(NS - 1)]
+    sptrs = [ctypes.c_void_p(st.cuda_stream) for st in streams]
     pp = ctypes.byref(p)
     vp = ctypes.c_void_p
 
@@ -153,17 +200,38 @@ def main():
     prepared = [window_args(k) for k in range(len(evs))]
     pyr_p = [vp(x.data_ptr()) for x in pyr]
     edge_p = [vp(x.data_ptr()) for x in edge]
-    flow_p = vp(flow.data_ptr())
+    flow_p = [vp(x.data_ptr()) for x in flows]
+    ev_pre, ev_flow = {}, {}
+    flow = flows[0]
 
     def step(k):
         x, y, t, n, t0 = prepared[k % len(prepared)]
-        b = k & 1
-        rc = lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[b], None, sptr)
-        rc |= lib.ebof_edt_surface(h, pp, edge_p[b], None, pyr_p[b], sptr)
+        b, si = k % NB, k % NS
+        st = streams[si]
+        # buffer b was last read by the flows of steps k-NB (its pyramid as the
+        # current one) and k-NB+1 (pyramid and edge image as the previous ones)
+        for j in (k - NB, k - NB + 1):
+            if j in ev_flow:
+                st.wait_event(ev_flow[j])
+        ev_flow.pop(k - NB, None)
+        rc = lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[b], None, sptrs[si])
+        rc |= lib.ebof_edt_surface(h, pp, edge_p[b], None, pyr_p[b], sptrs[si])
+        ev_pre[k] = torch.cuda.Event()
+        ev_pre[k].record(st)
+        prev = ev_pre.pop(k - 1, None)
         if k > 0:
-            rc |= lib.ebof_flow(h, pp, pyr_p[b ^ 1], pyr_p[b], edge_p[b ^ 1], flow_p, sptr)
+            if prev is not None:
+                st.wait_event(prev)
+            bp = (k - 1) % NB
+            rc |= lib.ebof_flow(h, pp, pyr_p[bp], pyr_p[b], edge_p[bp], flow_p[si], sptrs[si])
+            ev_flow[k] = torch.cuda.Event()
+            ev_flow[k].record(st)
         if rc:
             raise RuntimeError(lib.ebof_last_error(h).decode())
+
+    def sync_all():
+        for st in streams:
+            st.synchronize()
 
     # ---------------- EPE against the oracle on the sampled pairs ----------
     epe = None
@@ -173,8 +241,8 @@ def main():
             for k in range(max(oracle_flows) + 1):
                 step(k)
                 if k in oracle_flows:
-                    stream.synchronize()
-                    g = flow.cpu().numpy().reshape(2, H, W).astype(np.float64)
+                    sync_all()
+                    g = flows[k % NS].cpu().numpy().reshape(2, H, W).astype(np.float64)
                     r, m = oracle_flows[k]
                     errs.append(np.hypot(g[0] - r[0], g[1] - r[1])[m].mean())
         epe = float(np.mean(errs))
@@ -182,9 +250,12 @@ def main():
 
     # ---------------- per-kernel breakdown (warm-up, all kernels timed) ----
     lib.ebof_timing_enable(h, (1 << len(L.KERNELS)) - 1)
+    NS_run = NS
+    NS = 1  # breakdown on the sequential form: kernel times do not overlap
     for k in range(Wm):
         step(k)
-    stream.synchronize()
+    sync_all()
+    NS = NS_run
     breakdown = {}
     for name in L.KERNELS:
         ms, cnt = L.ebof_timing_read(ctx, name)
@@ -193,29 +264,47 @@ def main():
     dominant = max(breakdown, key=lambda n: breakdown[n]["ms_per_window"])
     log("per-kernel ms/window: " + ", ".join(f"{n} {v['ms_per_window']:.4f}" for n, v in breakdown.items()))
 
-    # ---------------- timed region: plain path ------------------------------
+    # ---------------- timed regions: plain path ----------------------------
+    # (1) the strictly sequential form, one stream, with the dominant kernel
+    # timed by HIP events around each of its launches (kernel times do not
+    # overlap here, so they are the kernel's own); (2) the pipelined form over
+    # NS streams, untimed per kernel, which gives the headline rate.
+    NS_run = NS
+    NS = 1
     lib.ebof_timing_enable(h, 1 << L.KERNELS.index(dominant))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(Wm, Wm + K):
         step(k)
-    stream.synchronize()
+    sync_all()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    fps_seq = K / (time.perf_counter() - t0)
     dom_ms, dom_cnt = L.ebof_timing_read(ctx, dominant)
     lib.ebof_timing_enable(h, 0)
-    elapsed = t1 - t0
-    fps = K / elapsed
-    log(f"plain: {fps:.1f} frames/s ({1e3 * elapsed / K:.4f} ms/window)")
+    log(f"plain (1 stream): {fps_seq:.1f} frames/s ({1e3 / fps_seq:.4f} ms/window)")
+    NS = NS_run
+    fps = fps_seq
+    if NS > 1:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(Wm + K, Wm + 2 * K):
+            step(k)
+        sync_all()
+        torch.cuda.synchronize()
+        fps = K / (time.perf_counter() - t0)
+        log(f"plain ({NS} streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window)")
+    elapsed = K / fps
 
     # ---------------- unloaded per-window latency (plain) -------------------
+    NS = 1
     lat = []
-    for k in range(Wm + K, Wm + K + 100):
+    for k in range(Wm + 2 * K, Wm + 2 * K + 100):
         s0 = time.perf_counter()
         step(k)
-        stream.synchronize()
+        sync_all()
         lat.append((time.perf_counter() - s0) * 1e3)
     lat = np.array(lat)
+    NS = NS_run
 
     # ---------------- roofline of the dominant kernel -----------------------
     per_launch_ms = dom_ms / max(1, dom_cnt)
@@ -225,8 +314,8 @@ def main():
         roof = {"kernel": "k_dis_level", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "frac_of_nonpacked_fp32": achieved / FP32_NONPACKED_TFLOPS,
-                "traffic": None, "ms_per_launch": per_launch_ms, "launches": dom_cnt,
-                "work_per_window": dis_flops_window(L, p)}
+                "traffic": measured_traffic("k_dis_level"), "ms_per_launch": per_launch_ms,
+                "launches": dom_cnt, "work_per_window": dis_flops_window(L, p)}
     else:
         bytes_per_window = {"edt_rows": 2 * N + 4 * N, "densify": 4 * N + 4 * N + N + 8 * N,
                             "scatter": 12 * 300_000, "denoise_fill": 2 * N,
@@ -234,7 +323,7 @@ def main():
                             "pyr_down": 4 * (P - N) + 4 * P}.get(dominant, 0)
         achieved = bytes_per_window * K / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_" + dominant),
                 "ms_per_launch": per_launch_ms, "launches": dom_cnt}
 
     out = {
@@ -250,13 +339,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1280x720 plain single stream: 200 windows x 300k events, 300 segments + "
+        "config": {"workload": "1280x720 plain single camera stream: 200 windows x 300k events, 300 segments + "
                                "50 ellipses under a random affine walk, 10% noise, L=4, patch 8 stride 4, "
                                "16 iterations, flow masked to the reference edge pixels",
                    "windows": len(c2), "events_per_window": 300_000, "width": W, "height": H,
                    "levels": p.levels},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
+        "plain_streams": NS,
+        "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
         "kernels_ms_per_window": {k: v["ms_per_window"] for k, v in breakdown.items()},
         "roofline": roof,

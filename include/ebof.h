@@ -123,8 +123,12 @@ int ebof_destroy(ebof_ctx *ctx);
 const char *ebof_last_error(const ebof_ctx *ctx);
 
 /* ---- stage calls (one window, caller's stream) --------------------------
- * The context's scratch for a given parameter set is shared by all stage
- * calls with that set: order such calls on one stream. */
+ * The context keeps one scratch per parameter set and HIP stream (held until
+ * ebof_destroy): calls on different streams may run concurrently, calls on
+ * one stream are ordered by it.  Only the caller's own buffers carry data
+ * from one call to the next (edge image, pyramid), so a window's stages may
+ * run on one stream and the flow that reads its pyramid on another, ordered
+ * by a HIP event. */
 
 /* Sec. III-A + III-B: bins the events with t0_us <= t < t0_us + dt_us into a
  * binary edge image (polarity is not an input; events off the sensor or off
@@ -195,6 +199,27 @@ typedef struct {
  * compute flow) replay. */
 int ebof_run_batch(ebof_ctx *ctx, const ebof_window *w, int32_t n,
                    void *hip_stream);
+
+/* ---- launch-shape tuning (batched form) ----------------------------------
+ * The batched runner times candidate launch shapes the first time it sees a
+ * batch layout and keeps the fastest: the block count of each stage's
+ * launch, the rows per item of the EDT row pass (1, 2, 4, 8) and the tile
+ * width of the densification (64, 128, 256 pixels).  No candidate changes
+ * any window's results.  Timing a new layout synchronises the stream and
+ * runs each stage a few times (milliseconds, once per layout).
+ * mode: EBOF_TUNE_AUTO (the default) or EBOF_TUNE_OFF (default shapes for
+ * layouts not tuned yet).  cache_path: NULL, or a text file from which tuned
+ * layouts are read now and to which newly tuned ones are appended, one line
+ * per layout: "<layout>\t<rows> <tile_w> <g_0> ... <g_21>", where <layout>
+ * is "W,H,levels,stride,flow,first;" for each window in batch order (flow: 1
+ * when the window computes flow; first: 1 for a served stream's first
+ * window) and g_s is the block count of internal stage s (0: default).
+ * Serving launches keep the default shapes.  Returns EBOF_E_INVAL for a bad
+ * mode or a malformed cache line (nothing is changed then).  Captured
+ * graphs are released. */
+#define EBOF_TUNE_OFF 0
+#define EBOF_TUNE_AUTO 1
+int ebof_set_tuning(ebof_ctx *ctx, int mode, const char *cache_path);
 
 /* ---- serving ----------------------------------------------------------------
  * A served stream keeps its previous window's pyramid and edge image in the

@@ -27,6 +27,9 @@ EBOF_E_STATE = -6
 EBOF_MASK_FLOW = 1
 EBOF_CHAIN_ALWAYS = 2
 EBOF_MAX_BATCH = 1024
+EBOF_TUNE_OFF = 0
+EBOF_TUNE_AUTO = 1
+EBOF_TUNE_STAGES = 22  # block counts per cache line (one per internal stage)
 
 KERNELS = ["scatter", "denoise_fill", "pack_cols", "edt_cols", "edt_rows", "pyr_down",
            "dis_level", "densify"]
@@ -102,6 +105,7 @@ def load():
         "ebof_edt_surface": ([P, pp, P, P, P, P], ctypes.c_int),
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
+        "ebof_set_tuning": ([P, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "ebof_stream_open": ([P, pp, ctypes.POINTER(i32)], ctypes.c_int),
         "ebof_stream_close": ([P, i32], ctypes.c_int),
         "ebof_submit": ([P, i32, P, P, P, i64, i64, ctypes.c_int, P, P,
@@ -124,7 +128,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_flow", "ebof_run_batch",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_flow", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
 
@@ -266,6 +270,23 @@ def ebof_flow(ctx, p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
     f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
     return _check(ctx.handle, ctx.lib.ebof_flow(ctx.handle, ctypes.byref(p), a, b, m, f,
                                                 _stream(stream)))
+
+
+def ebof_set_tuning(ctx, mode=EBOF_TUNE_AUTO, cache_path=None):
+    """Launch-shape tuning of the batched form (EBOF_TUNE_AUTO / EBOF_TUNE_OFF),
+    optionally with a cache file of tuned layouts."""
+    path = None if cache_path is None else os.fsencode(cache_path)
+    return _check(ctx.handle, ctx.lib.ebof_set_tuning(ctx.handle, int(mode), path))
+
+
+def batch_layout_key(windows):
+    """The layout string of a batch as the tuning cache file names it."""
+    out = []
+    for w in windows:
+        p = w["params"]
+        flow = 1 if w.get("pyr_prev") is not None else 0
+        out.append(f"{p.width},{p.height},{p.levels},{p.stride},{flow},0;")
+    return "".join(out)
 
 
 def ebof_run_batch(ctx, windows, stream=None):

@@ -225,7 +225,7 @@ void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratc
 }
 
 static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int* rc) {
-    auto key = std::make_tuple(g.W, g.H, g.L, g.stride);
+    auto key = std::make_tuple(g.W, g.H, g.L, g.stride, (uintptr_t)st);
     auto it = ctx->stage_scratch.find(key);
     if (it != ctx->stage_scratch.end()) return &it->second;
     Scratch s;
@@ -255,6 +255,9 @@ static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f) {
     (void)hipEventRecord(tp.b, st);
     ctx->timed[kid].push_back(tp);
 }
+
+// stage calls launch one block per item with the default tile shapes
+static const Tune kStageTune{};
 
 static Launch one_launch(const WinDesc* d, int32_t total, hipStream_t st) {
     Launch L;
@@ -325,6 +328,250 @@ static int runner_init(ebof_ctx* ctx, BatchRunner& br) {
     return EBOF_OK;
 }
 
+// ---------------------------------------------------------------- launch shapes
+// The stages of a batch in pipeline order: binning, denoise/fill, EDT,
+// pyramid chains from the finest, then the inverse search from the coarsest
+// level to the finest (each level starts from the coarser one), then the
+// densification.
+static std::vector<int> pipeline_order(int lmax) {
+    std::vector<int> o{kStZero, kStScatter, kStDenoise, kStCols, kStRows};
+    for (int c = 0; c * kPyrChain < lmax - 1; ++c) o.push_back(kStPyr + c);
+    for (int l = lmax - 1; l >= 0; --l) o.push_back(kStDis + l);
+    o.push_back(kStDensify);
+    return o;
+}
+static int stage_kernel_id(int s) {
+    if (s == kStZero) return -1;
+    if (s == kStScatter) return EBOF_K_SCATTER;
+    if (s == kStDenoise) return EBOF_K_DENOISE_FILL;
+    if (s == kStCols) return EBOF_K_EDT_COLS;
+    if (s == kStRows) return EBOF_K_EDT_ROWS;
+    if (s >= kStPyr && s < kStDis) return EBOF_K_PYR_DOWN;
+    if (s >= kStDis && s < kStDensify) return EBOF_K_DIS_LEVEL;
+    return EBOF_K_DENSIFY;
+}
+// Default persistent grids of the universal graph (any batch), and of the
+// stages whose item counts vary between batches of one layout (event counts).
+static int32_t stage_cap(int s) {
+    if (s == kStZero) return 512;
+    if (s >= kStPyr && s < kStDis) return 1024;
+    return 2048;
+}
+static int32_t stage_grid(int s, int32_t total, const Tune& t, int mode) {
+    if (t.grid[s] > 0) return t.grid[s];
+    if (mode == kGraphUniversal || s == kStZero || s == kStScatter) return stage_cap(s);
+    return std::max(1, std::min(total, 1 << 20));
+}
+static Launch batch_launch(BatchRunner& br, const WinDesc* first, int s, int32_t total, int32_t grid,
+                           hipStream_t st) {
+    Launch L;
+    L.one = first;
+    L.ba = BatchArgs{(const WinDesc*)(br.table_dev + table_desc_offset()),
+                     (const int32_t*)(br.table_dev + kTableHeader), (const int32_t*)br.table_dev, s, 0};
+    L.batch = true;
+    L.total = total;
+    L.grid = grid;
+    L.stream = st;
+    return L;
+}
+static void launch_stage(const Launch& L, int s, const Tune& t) {
+    if (s == kStZero)
+        launch_zero(L);
+    else if (s == kStScatter)
+        launch_scatter(L);
+    else if (s == kStDenoise)
+        launch_denoise_fill(L, true);
+    else if (s == kStCols)
+        launch_edt_cols(L);
+    else if (s == kStRows)
+        launch_edt_rows(L, t.rows_nr);
+    else if (s >= kStPyr && s < kStDis)
+        launch_pyr_chain(L, (s - kStPyr) * kPyrChain);
+    else if (s >= kStDis && s < kStDensify)
+        launch_dis_level(L, s - kStDis);
+    else
+        launch_densify(L, t.dens_tw);
+}
+
+// prefix sums, window-major: prefix[i * kNumStages + s]
+static int build_prefix(const std::vector<WinDesc>& descs, const std::vector<char>& flow,
+                        const std::vector<char>& zero, const Tune& t, std::vector<int32_t>* prefix,
+                        int32_t* totals) {
+    const int32_t n = (int32_t)descs.size();
+    prefix->assign((size_t)kNumStages * (n + 1), 0);
+    for (int s = 0; s < kNumStages; ++s) {
+        int64_t run = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            (*prefix)[(size_t)i * kNumStages + s] = (int32_t)run;
+            run += stage_items(descs[i], s, flow[i], zero[i], t);
+        }
+        if (run > INT32_MAX) {
+            set_error("batch too large: stage %d has %lld work items", s, (long long)run);
+            return EBOF_E_INVAL;
+        }
+        (*prefix)[(size_t)n * kNumStages + s] = (int32_t)run;
+        totals[s] = (int32_t)run;
+    }
+    return EBOF_OK;
+}
+
+// Copies [nwin | prefix sums] and the descriptors to the device table through
+// the next pinned staging buffer, ordered on st.
+static int upload_table(ebof_ctx* ctx, BatchRunner& br, const std::vector<WinDesc>& descs,
+                        const std::vector<int32_t>& prefix, hipStream_t st) {
+    const int32_t n = (int32_t)descs.size();
+    auto& pb = br.pinned[br.pinned_next];
+    br.pinned_next = (br.pinned_next + 1) % (int)br.pinned.size();
+    int rc;
+    if (pb.used && (rc = check_hip(ctx, hipEventSynchronize(pb.done), "hipEventSynchronize"))) return rc;
+    const size_t doff = table_desc_offset();
+    std::memcpy(pb.host, &n, sizeof(int32_t));
+    std::memcpy(pb.host + kTableHeader, prefix.data(), prefix_bytes(n));
+    std::memcpy(pb.host + doff, descs.data(), sizeof(WinDesc) * n);
+    if ((rc = check_hip(ctx,
+                        hipMemcpyAsync(br.table_dev, pb.host, kTableHeader + prefix_bytes(n), hipMemcpyHostToDevice,
+                                       st),
+                        "hipMemcpyAsync(prefix)")))
+        return rc;
+    if ((rc = check_hip(ctx,
+                        hipMemcpyAsync(br.table_dev + doff, pb.host + doff, sizeof(WinDesc) * n,
+                                       hipMemcpyHostToDevice, st),
+                        "hipMemcpyAsync(table)")))
+        return rc;
+    if ((rc = check_hip(ctx, hipEventRecord(pb.done, st), "hipEventRecord"))) return rc;
+    pb.used = true;
+    return EBOF_OK;
+}
+
+// The autotuner.  For a new batch layout it runs the batch once with default
+// shapes (so every stage's inputs exist), then times each stage alone for
+// each candidate shape (the persistent grid; the rows per item of the EDT row
+// pass; the tile width of the densification), stage by stage in pipeline
+// order, keeping the fastest.  Every stage is idempotent given its inputs
+// and the candidates change no window's arithmetic, so the outputs are the
+// same whatever is chosen.  The tuning copy of the table counts no dropped
+// events; the caller's run that follows does.
+static int autotune(ebof_ctx* ctx, BatchRunner& br, const std::vector<WinDesc>& descs, const std::vector<char>& flow,
+                    const std::vector<char>& zero, int lmax, hipStream_t st, Tune* out) {
+    std::vector<WinDesc> td = descs;
+    for (auto& d : td) d.n_dropped = nullptr;
+    Tune best;
+    std::vector<int32_t> prefix;
+    int32_t totals[kNumStages];
+    int rc;
+    // the previous batch on st may still read the table
+    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "hipStreamSynchronize"))) return rc;
+    auto upload = [&](const Tune& t) -> int {
+        int r = build_prefix(td, flow, zero, t, &prefix, totals);
+        if (!r) r = upload_table(ctx, br, td, prefix, st);
+        return r;
+    };
+    if ((rc = upload(best))) return rc;
+    for (int s : pipeline_order(lmax))
+        if (totals[s])
+            launch_stage(batch_launch(br, &td[0], s, totals[s], stage_grid(s, totals[s], best, kGraphLayout), st), s,
+                         best);
+    if ((rc = launch_status(ctx))) return rc;
+    hipEvent_t e0, e1;
+    if ((rc = check_hip(ctx, hipEventCreate(&e0), "hipEventCreate"))) return rc;
+    if ((rc = check_hip(ctx, hipEventCreate(&e1), "hipEventCreate"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    auto time_stage = [&](int s, const Tune& t, float* ms) -> int {
+        int r = upload(t);
+        if (r) return r;
+        if (!totals[s]) {
+            *ms = 0.f;
+            return EBOF_OK;
+        }
+        const Launch L = batch_launch(br, &td[0], s, totals[s], stage_grid(s, totals[s], t, kGraphLayout), st);
+        launch_stage(L, s, t);  // warm
+        if ((r = check_hip(ctx, hipEventRecord(e0, st), "hipEventRecord"))) return r;
+        for (int rep = 0; rep < 3; ++rep) launch_stage(L, s, t);
+        if ((r = check_hip(ctx, hipEventRecord(e1, st), "hipEventRecord"))) return r;
+        if ((r = launch_status(ctx))) return r;
+        if ((r = check_hip(ctx, hipEventSynchronize(e1), "hipEventSynchronize"))) return r;
+        return check_hip(ctx, hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime");
+    };
+    static const int32_t kGrids[] = {0, 256, 512, 1024, 2048, 4096};
+    for (int s : pipeline_order(lmax)) {
+        if (rc) break;
+        if (s == kStZero) continue;
+        std::vector<int> shapes{0};
+        if (s == kStRows) shapes = {1, 2, 4, 8};
+        if (s == kStDensify) shapes = {64, 128, 256};
+        float best_ms = -1.f;
+        Tune win = best;
+        for (int shape : shapes) {
+            Tune t = best;
+            if (s == kStRows) t.rows_nr = shape;
+            if (s == kStDensify) t.dens_tw = shape;
+            if ((rc = build_prefix(td, flow, zero, t, &prefix, totals))) break;
+            for (int32_t g : kGrids) {
+                if (g == 0 && s == kStScatter) continue;  // its item count varies: a fixed grid
+                if (g > 0 && g >= totals[s]) continue;    // no more blocks than items
+                t.grid[s] = g;
+                float ms = 0.f;
+                if ((rc = time_stage(s, t, &ms))) break;
+                if (best_ms < 0.f || ms < best_ms) {
+                    best_ms = ms;
+                    win = t;
+                }
+            }
+            if (rc) break;
+        }
+        best = win;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *out = best;
+    return EBOF_OK;
+}
+
+// Appends one tuned layout to the cache file, if one is set.
+static void save_tune(ebof_ctx* ctx, const std::string& key, const Tune& t) {
+    if (ctx->tune_path.empty()) return;
+    FILE* f = std::fopen(ctx->tune_path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%d %d", key.c_str(), t.rows_nr, t.dens_tw);
+    for (int s = 0; s < kNumStages; ++s) std::fprintf(f, " %d", t.grid[s]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
+// Reads a cache file written by save_tune (or by hand); EBOF_E_INVAL names
+// the first malformed line.
+static int load_tunes(const char* path, std::map<std::string, Tune>* out) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return EBOF_OK;  // nothing tuned yet
+    char line[1 << 14];
+    int lineno = 0, rc = EBOF_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        std::string l(line), key;
+        if (l.find_first_not_of(" \r\n") == std::string::npos) continue;
+        std::vector<int> v;
+        Tune t;
+        bool ok = parse_tune_line(l, 2 + kNumStages, &key, &v);
+        if (ok) {
+            t.rows_nr = v[0];
+            t.dens_tw = v[1];
+            for (int s = 0; s < kNumStages; ++s) t.grid[s] = v[2 + s];
+            ok = tune_valid(t);
+        }
+        if (!ok) {
+            set_error("tuning cache %s: malformed line %d", path, lineno);
+            rc = EBOF_E_INVAL;
+            break;
+        }
+        (*out)[key] = t;
+    }
+    std::fclose(f);
+    return rc;
+}
+
 // Runs n windows, one launch per stage.  scr[i] is window i's scratch (its
 // geometry must match the window's parameters).  graph_mode: kGraphNone
 // launches directly; kGraphLayout captures one graph per batch layout with
@@ -393,89 +640,47 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
         flow[i] = w[i].pyr_prev != nullptr;
         lmax = std::max(lmax, p.levels);
     }
-    // prefix sums, window-major: prefix[i * kNumStages + s]
-    std::vector<int32_t> prefix((size_t)kNumStages * (n + 1));
-    int32_t totals[kNumStages];
-    for (int s = 0; s < kNumStages; ++s) {
-        int64_t run = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            prefix[(size_t)i * kNumStages + s] = (int32_t)run;
-            run += stage_items(descs[i], s, flow[i], zero[i]);
+    const bool universal = graph_mode == kGraphUniversal;
+    const std::string key = universal ? "U" + std::to_string(lmax) : layout_key(descs, flow);
+    // launch shapes: defaults for the universal graph, else this layout's
+    // tuned shapes (timed now if the layout is new and tuning is on)
+    Tune tune;
+    if (!universal) {
+        auto ti = br.tunes.find(key);
+        if (ti != br.tunes.end()) {
+            tune = ti->second;
+        } else if (ctx->tune_mode == EBOF_TUNE_AUTO) {
+            // (not while the caller captures the stream: tuning synchronises it)
+            hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+            if (st && (rc = check_hip(ctx, hipStreamIsCapturing(st, &cst), "hipStreamIsCapturing"))) return rc;
+            if (cst == hipStreamCaptureStatusNone) {
+                if ((rc = autotune(ctx, br, descs, flow, zero, lmax, st, &tune))) return rc;
+                br.tunes[key] = tune;
+                save_tune(ctx, key, tune);
+            }
         }
-        if (run > INT32_MAX) {
-            set_error("batch too large: stage %d has %lld work items", s, (long long)run);
-            return EBOF_E_INVAL;
-        }
-        prefix[(size_t)n * kNumStages + s] = (int32_t)run;
-        totals[s] = (int32_t)run;
     }
+    std::vector<int32_t> prefix;
+    int32_t totals[kNumStages];
+    if ((rc = build_prefix(descs, flow, zero, tune, &prefix, totals))) return rc;
     // upload through a pinned staging buffer: [nwin | prefix sums] and the descriptors
-    auto& pb = br.pinned[br.pinned_next];
-    br.pinned_next = (br.pinned_next + 1) % (int)br.pinned.size();
-    if (pb.used && (rc = check_hip(ctx, hipEventSynchronize(pb.done), "hipEventSynchronize"))) return rc;
-    const size_t doff = table_desc_offset();
-    std::memcpy(pb.host, &n, sizeof(int32_t));
-    std::memcpy(pb.host + kTableHeader, prefix.data(), prefix_bytes(n));
-    std::memcpy(pb.host + doff, descs.data(), sizeof(WinDesc) * n);
-    if ((rc = check_hip(ctx,
-                        hipMemcpyAsync(br.table_dev, pb.host, kTableHeader + prefix_bytes(n), hipMemcpyHostToDevice,
-                                       st),
-                        "hipMemcpyAsync(prefix)")))
-        return rc;
-    if ((rc = check_hip(ctx,
-                        hipMemcpyAsync(br.table_dev + doff, pb.host + doff, sizeof(WinDesc) * n,
-                                       hipMemcpyHostToDevice, st),
-                        "hipMemcpyAsync(table)")))
-        return rc;
-    if ((rc = check_hip(ctx, hipEventRecord(pb.done, st), "hipEventRecord"))) return rc;
-    pb.used = true;
+    if ((rc = upload_table(ctx, br, descs, prefix, st))) return rc;
 
-    const WinDesc* tab = (const WinDesc*)(br.table_dev + doff);
-    const int32_t* pre = (const int32_t*)(br.table_dev + kTableHeader);
-    const int32_t* nw = (const int32_t*)br.table_dev;
     const int mode = (ctx->timing_mask == 0 && ctx->use_graphs) ? graph_mode : kGraphNone;
-    const bool universal = mode == kGraphUniversal;
-    auto mk = [&](int s, int32_t cap) {
-        Launch L;
-        L.one = &descs[0];
-        L.ba = BatchArgs{tab, pre, nw, s, 0};
-        L.batch = true;
-        L.total = totals[s];
-        if (universal)
-            L.grid = cap;
-        else if (mode == kGraphLayout && (s == kStZero || s == kStScatter))
-            L.grid = cap;  // these counts vary between batches of one layout
-        else
-            L.grid = std::max(1, std::min(totals[s], 1 << 20));
-        L.stream = st;
-        return L;
-    };
     auto run_all = [&](bool all) {
-        if (all || totals[kStZero]) launch_zero(mk(kStZero, 512));
-        if (all || totals[kStScatter]) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(mk(kStScatter, 2048)); });
-        if (all || totals[kStDenoise])
-            timed(ctx, EBOF_K_DENOISE_FILL, st, [&] { launch_denoise_fill(mk(kStDenoise, 2048), true); });
-        if (all || totals[kStCols]) timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(mk(kStCols, 2048)); });
-        if (all || totals[kStRows]) timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(mk(kStRows, 2048)); });
-        for (int from = 0; from < lmax - 1; from += kPyrChain)
-            if (all || totals[kStPyr + from / kPyrChain])
-                timed(ctx, EBOF_K_PYR_DOWN, st,
-                      [&] { launch_pyr_chain(mk(kStPyr + from / kPyrChain, 1024), from); });
-        for (int l = lmax - 1; l >= 0; --l)
-            if (all || totals[kStDis + l])
-                timed(ctx, EBOF_K_DIS_LEVEL, st, [&] { launch_dis_level(mk(kStDis + l, 2048), l); });
-        if (all || totals[kStDensify])
-            timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(mk(kStDensify, 2048)); });
+        for (int s : pipeline_order(lmax)) {
+            if (!all && !totals[s]) continue;
+            const int kid = stage_kernel_id(s);
+            Launch L = batch_launch(br, &descs[0], s, totals[s], stage_grid(s, totals[s], tune, mode), st);
+            if (kid < 0)
+                launch_stage(L, s, tune);
+            else
+                timed(ctx, kid, st, [&] { launch_stage(L, s, tune); });
+        }
     };
     if (mode == kGraphNone) {
         run_all(false);
         return launch_status(ctx);
-    }
-    std::string key;
-    if (universal) {
-        key = "U" + std::to_string(lmax);
-    } else {
-        key = layout_key(descs, flow);
     }
     auto it = br.graphs.find(key);
     if (it == br.graphs.end()) {
@@ -634,12 +839,12 @@ int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
     d.e_df = edge_out;
     d.n_dropped = (unsigned long long*)n_dropped_dev;
     if (s->needs_zero) {
-        launch_zero(one_launch(&d, stage_items(d, kStZero, false, true), st));
+        launch_zero(one_launch(&d, stage_items(d, kStZero, false, true, kStageTune), st));
         s->needs_zero = false;
     }
-    if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false), st)); });
+    if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_DENOISE_FILL, st,
-          [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false), st), false); });
+          [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false, kStageTune), st), false); });
     return launch_status(ctx);
 }
 
@@ -664,12 +869,12 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
     d.e_df = const_cast<uint8_t*>(edge);  // read only by these kernels
     d.d2 = d2_out;
     d.pyr = pyr_out;
-    timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false), st)); });
-    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false), st)); });
-    timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false), st)); });
+    timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
+    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
+    timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
     for (int from = 0; from < p->levels - 1; from += kPyrChain)
         timed(ctx, EBOF_K_PYR_DOWN, st, [&] {
-            launch_pyr_chain(one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false), st), from);
+            launch_pyr_chain(one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
         });
     return launch_status(ctx);
 }
@@ -697,9 +902,30 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
     d.flow = flow_out;
     for (int l = p->levels - 1; l >= 0; --l)
         timed(ctx, EBOF_K_DIS_LEVEL, st,
-              [&] { launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false), st), l); });
-    timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false), st)); });
+              [&] { launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, kStageTune), st), l); });
+    timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw); });
     return launch_status(ctx);
+}
+
+int ebof_set_tuning(ebof_ctx* ctx, int mode, const char* cache_path) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if (mode != EBOF_TUNE_OFF && mode != EBOF_TUNE_AUTO) {
+        set_error("tuning mode %d is neither EBOF_TUNE_OFF nor EBOF_TUNE_AUTO", mode);
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::map<std::string, Tune> loaded;
+    if (cache_path && (rc = load_tunes(cache_path, &loaded))) return rc;
+    // graphs were captured with the shapes in effect then
+    if (ctx->batch.table_dev && (rc = check_hip(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize"))) return rc;
+    for (auto& kv : ctx->batch.graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    ctx->batch.graphs.clear();
+    for (auto& kv : loaded) ctx->batch.tunes[kv.first] = kv.second;
+    ctx->tune_mode = mode;
+    ctx->tune_path = cache_path ? cache_path : "";
+    return EBOF_OK;
 }
 
 int ebof_run_batch(ebof_ctx* ctx, const ebof_window* w, int32_t n, void* hip_stream) {

@@ -74,6 +74,7 @@ struct BatchRunner {
     std::vector<Pinned> pinned;
     int pinned_next = 0;
     std::map<std::string, hipGraphExec_t> graphs;
+    std::map<std::string, Tune> tunes;  // launch shapes per batch layout (autotuner)
 };
 
 // Extra per-window outputs of the served form.
@@ -95,12 +96,16 @@ struct ebof_ctx {
     std::mutex mu;  // guards arena, luts, scratch maps against the server thread
 
     std::vector<ebof::Lut> luts;
-    std::map<std::tuple<int, int, int, int>, ebof::Scratch> stage_scratch;
+    // stage-call scratch per (W, H, levels, stride, HIP stream): calls on
+    // different streams may overlap, calls on one stream are ordered by it
+    std::map<std::tuple<int, int, int, int, uintptr_t>, ebof::Scratch> stage_scratch;
 
     // batched form
     std::vector<ebof::Scratch> batch_slots;
     ebof::BatchRunner batch;
     bool use_graphs = true;
+    int tune_mode = EBOF_TUNE_AUTO;  // batched launch shapes: defaults or timed candidates
+    std::string tune_path;           // cache file of tuned shapes ("" = none)
 
     // timing
     uint32_t timing_mask = 0;

@@ -26,9 +26,10 @@ constexpr int kTileH = 32;            // ... and 32 tall per block
 constexpr int kChunk = 64;            // column-mask chunk: 64 rows per word
 constexpr int kPyrChain = 3;          // pyramid: levels built per launch
 constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
-constexpr int kDensTileH = 4;         // densify: 64x4 pixels per block
 constexpr int kZeroBytesPerItem = 4096;
-constexpr int kRowSeg = 256;          // EDT row pass: pixels per block
+constexpr int kRowSeg = 256;          // EDT row pass: pixels per item row
+constexpr int kRowReach = 64;         // EDT row pass: columns staged each side of a segment
+constexpr int kLutLds = 1024;         // EDT row pass: surface tables up to this size sit in LDS
 
 struct LevelGeom {
     int32_t w, h;      // level size
@@ -109,8 +110,24 @@ struct Launch {
     hipStream_t stream;
 };
 
+// Launch shapes the autotuner chooses among.  None of them changes what a
+// window computes: they decide how work is cut into items and how many
+// blocks a batched launch runs.
+struct Tune {
+    int32_t rows_nr = 4;    // k_edt_rows: rows per item (1, 2, 4 or 8)
+    int32_t dens_tw = 64;   // k_densify: tile width (64, 128 or 256), kBlock / dens_tw rows
+    int32_t grid[kNumStages] = {};  // batched launch blocks per stage (0: the default)
+};
+inline bool tune_valid(const Tune& t) {
+    const bool nr = t.rows_nr == 1 || t.rows_nr == 2 || t.rows_nr == 4 || t.rows_nr == 8;
+    const bool tw = t.dens_tw == 64 || t.dens_tw == 128 || t.dens_tw == 256;
+    for (int s = 0; s < kNumStages; ++s)
+        if (t.grid[s] < 0 || t.grid[s] > (1 << 20)) return false;
+    return nr && tw;
+}
+
 // Work items of one stage for one window (0 when the stage does not apply).
-int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero);
+int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const Tune& t);
 
 // stage item counts of a window described by d
 inline bool desc_has_flow(const WinDesc& d) { return d.pyr_prev != nullptr; }
@@ -120,9 +137,9 @@ void launch_scatter(const Launch& L);
 void launch_denoise_fill(const Launch& L, bool pack);
 void launch_pack_cols(const Launch& L);
 void launch_edt_cols(const Launch& L);
-void launch_edt_rows(const Launch& L);
+void launch_edt_rows(const Launch& L, int rows_nr);
 void launch_pyr_chain(const Launch& L, int from);
 void launch_dis_level(const Launch& L, int level);
-void launch_densify(const Launch& L);
+void launch_densify(const Launch& L, int tile_w);
 
 }  // namespace ebof

@@ -4,12 +4,16 @@
 // be unit-tested on the CPU.
 #pragma once
 
+#include <cerrno>
+#include <climits>
 #include <cstddef>
 #include <cstdint>
+#include <cstdlib>
 #include <deque>
 #include <iterator>
 #include <map>
 #include <set>
+#include <string>
 #include <vector>
 
 namespace ebof {
@@ -151,6 +155,31 @@ std::vector<T> take_one_per_stream(std::deque<T>& queue, int max_n, SidOf sid_of
         it = queue.erase(it);
     }
     return take;
+}
+
+// One line of the launch-shape cache: "<key>\t<v_0> <v_1> ... <v_{n-1}>"
+// (exactly n integers after the tab; trailing CR/LF ignored).  False for a
+// line of any other form.
+inline bool parse_tune_line(const std::string& line, int n, std::string* key, std::vector<int>* vals) {
+    std::string l = line;
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    const size_t tab = l.find('\t');
+    if (tab == std::string::npos || tab == 0) return false;
+    std::vector<int> v;
+    const char* q = l.c_str() + tab + 1;
+    for (int i = 0; i < n; ++i) {
+        char* end = nullptr;
+        errno = 0;
+        const long x = std::strtol(q, &end, 10);
+        if (end == q || errno || x < INT32_MIN || x > INT32_MAX) return false;
+        v.push_back((int)x);
+        q = end;
+    }
+    while (*q == ' ') ++q;
+    if (*q) return false;
+    *key = l.substr(0, tab);
+    *vals = v;
+    return true;
 }
 
 }  // namespace ebof

@@ -46,16 +46,53 @@ __device__ __forceinline__ int32_t item_total(const BatchArgs& ba, int32_t total
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Copies an h x w window into LDS (row pitch w, or `pitch`): element (r, c) =
+// src(r, c).
+// Thread t takes elements t, t + kBlock, ...; it issues U of its loads before
+// its first LDS write, so U global loads per thread are in flight instead of
+// one (a load feeding an LDS store otherwise waits out the full memory
+// latency before the next load issues).
+template <int U, class T, class Src>
+__device__ __forceinline__ void stage_window(T* __restrict__ dst, int w, int h, Src src, int pitch = 0) {
+    const int n = w * h;
+    if (pitch == 0) pitch = w;
+    int r = threadIdx.x / w, cc = threadIdx.x - r * w;
+    const int dr = kBlock / w, dc = kBlock - dr * w;
+    for (int base = 0; base < n; base += U * kBlock) {
+        T v[U];
+        int off[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            off[u] = r < h ? r * pitch + cc : -1;
+            v[u] = r < h ? src(r, cc) : T(0);
+            cc += dc;
+            r += dr;
+            if (cc >= w) {
+                cc -= w;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (off[u] >= 0) dst[off[u]] = v[u];
+    }
+}
+
 // Patches of one axis that contain pixel p: the regular ones (origin k*s,
 // k <= np-2, never clamped) with k*s <= p <= k*s+7, plus the last patch
 // (origin n-8) when p >= n-8.
 struct Cover {
     int lo, nreg, last, n;
 };
-__device__ __forceinline__ Cover cover_of(int p, int n, int np, int s) {
+// q / s for 0 <= q < 2^16 and 1 <= s <= 8, with inv_s = 1/s: (q + 1/2) / s
+// lies at least 1/(2s) >= 1/16 from an integer, and the float product's
+// relative error (2^-23) keeps it within 2^-7 of the exact quotient.
+__device__ __forceinline__ int div_small(int q, float inv_s) { return (int)(((float)q + 0.5f) * inv_s); }
+
+__device__ __forceinline__ Cover cover_of(int p, int n, int np, int s, float inv_s) {
     Cover c;
-    c.lo = p >= kPatch - 1 ? (p - (kPatch - 1) + s - 1) / s : 0;
-    const int hi = min(np - 2, p / s);
+    c.lo = p >= kPatch - 1 ? div_small(p - (kPatch - 1) + s - 1, inv_s) : 0;
+    const int hi = min(np - 2, div_small(p, inv_s));
     c.nreg = max(0, hi - c.lo + 1);
     c.last = np - 1;
     c.n = c.nreg + (p >= n - kPatch ? 1 : 0);
@@ -155,12 +192,22 @@ __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, cons
         const uint8_t stamp = (uint8_t)d->stamp;
         const uint8_t* __restrict__ er = d->e_raw;
         const int n_d = d->n_d, n_f = d->n_f;
-        for (int i = tid; i < RH * RW; i += kBlock) {
-            const int ly = i / RW, lx = i - ly * RW;
-            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-            uint8_t v = 0;
-            if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = er[(size_t)gy * W + gx] == stamp;
-            sE[ly][lx] = v;
+        {
+            // staged with pitch RW into the padded rows of sE (pitch RW + 4)
+            uint8_t raw[(RH * RW + kBlock - 1) / kBlock];
+            int i = tid;
+#pragma unroll
+            for (int u = 0; u < (RH * RW + kBlock - 1) / kBlock; ++u, i += kBlock) {
+                const int ly = i / RW, lx = i - ly * RW;
+                const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+                raw[u] = (i < RH * RW && gx >= 0 && gx < W && gy >= 0 && gy < H) ? er[(size_t)gy * W + gx] : 0;
+            }
+            i = tid;
+#pragma unroll
+            for (int u = 0; u < (RH * RW + kBlock - 1) / kBlock; ++u, i += kBlock) {
+                const int ly = i / RW, lx = i - ly * RW;
+                if (i < RH * RW) sE[ly][lx] = raw[u] == stamp;  // stamps are 1..255: off-image 0 never matches
+            }
         }
         __syncthreads();
         for (int i = tid; i < DH * DW; i += kBlock) {
@@ -266,21 +313,25 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
         if (x >= W) continue;
         const uint64_t* cm = d->colmask + x;
         const uint64_t m = cm[(size_t)ck * W];
-        int above = -1;  // last edge row above the chunk
-        for (int c2 = ck - 1; c2 >= 0; --c2) {
-            const uint64_t mm = cm[(size_t)c2 * W];
-            if (mm) {
-                above = c2 * kChunk + 63 - __clzll(mm);
-                break;
-            }
+        // nearest edge rows above and below the chunk, from the neighbouring
+        // chunks' masks read kScan at a time
+        constexpr int kScan = 4;
+        int above = -1, below = -1;
+        for (int c2 = ck - 1; c2 >= 0 && above < 0; c2 -= kScan) {
+            uint64_t mm[kScan];
+#pragma unroll
+            for (int u = 0; u < kScan; ++u) mm[u] = c2 - u >= 0 ? cm[(size_t)(c2 - u) * W] : 0;
+#pragma unroll
+            for (int u = 0; u < kScan; ++u)
+                if (above < 0 && mm[u]) above = (c2 - u) * kChunk + 63 - __clzll(mm[u]);
         }
-        int below = -1;  // first edge row below the chunk
-        for (int c2 = ck + 1; c2 < nch; ++c2) {
-            const uint64_t mm = cm[(size_t)c2 * W];
-            if (mm) {
-                below = c2 * kChunk + __ffsll((unsigned long long)mm) - 1;
-                break;
-            }
+        for (int c2 = ck + 1; c2 < nch && below < 0; c2 += kScan) {
+            uint64_t mm[kScan];
+#pragma unroll
+            for (int u = 0; u < kScan; ++u) mm[u] = c2 + u < nch ? cm[(size_t)(c2 + u) * W] : 0;
+#pragma unroll
+            for (int u = 0; u < kScan; ++u)
+                if (below < 0 && mm[u]) below = (c2 + u) * kChunk + __ffsll((unsigned long long)mm[u]) - 1;
         }
         const int r0 = seg * 16;
         const int rows = min(16, H - ck * kChunk - r0);
@@ -304,57 +355,104 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
 }
 
 // --------------------------------------------------------------------------
-// Exact distance transform, row pass, fused with eq. (1).  One row per item:
-// the row's g^2 is staged in LDS, then every pixel searches outwards,
-// D2(x) = min_r r^2 + g(x +- r)^2, stopping once r^2 reaches the best value
-// found (no later column can beat it), which gives the exact minimum.  The
-// surface is looked up from the squared distance: lut[D2] below lut_n,
-// exactly 1.0f from there on.  When D2 is not exported the search also stops
-// at r^2 >= lut_n: a minimum of lut_n or more gives 1.0f whatever it is, and
-// a smaller one is always found before that radius.
+// Exact distance transform, row pass, fused with eq. (1).  Item = NR rows x
+// a kRowSeg-pixel segment; thread = one column of the segment, which
+// searches its rows together (independent LDS reads in flight).  Every pixel
+// searches outwards, D2(x) = min_r r^2 + g(x +- r)^2, stopping once r^2
+// reaches the best value found (no further column can beat it): the exact
+// minimum.  The rows' g within kRowReach of the segment are staged in LDS; a
+// search reaching further reads global memory.  The surface is looked up from
+// the squared distance: lut[D2] below lut_n, exactly 1.0f from there on.  When
+// D2 is not exported the search also stops at r^2 >= lut_n: a minimum of
+// lut_n or more gives 1.0f whatever it is, and a smaller one is always found
+// before that radius.
 // --------------------------------------------------------------------------
-template <bool B>
+__device__ __forceinline__ uint32_t g_sq(uint32_t g) { return g == kGInf ? 0x7fffffffu : g * g; }
+
+template <bool B, int NR>
 __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const BatchArgs ba,
                                                      int32_t total_arg) {
-    __shared__ uint32_t sG2[EBOF_MAX_DIM];
+    constexpr int R = kRowReach;
+    __shared__ uint32_t sG[NR * (kRowSeg + 2 * R)];  // g^2, 0x7fffffff = no edge in the column
+    __shared__ float sLut[kLutLds];
     const int32_t total = item_total<B>(ba, total_arg);
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
-        const int W = d->W;
+        const int W = d->W, H = d->H;
         const int nseg = (W + kRowSeg - 1) / kRowSeg;
-        const int y = local / nseg, x0 = (local - y * nseg) * kRowSeg;
-        int32_t* d2row = d->d2 ? d->d2 + (size_t)y * W : nullptr;
+        const int y0 = (local / nseg) * NR, x0 = (local - (local / nseg) * nseg) * kRowSeg;
+        const int nrows = min(NR, H - y0);
+        const bool exp_d2 = d->d2 != nullptr;
         const int lut_n = d->lut_n;
-        // the search never looks further than sqrt(cap) from its pixel
-        const uint32_t cap = d2row ? 0xffffffffu : (uint32_t)lut_n;
-        const int reach = d2row ? W : d->lut_r;
-        const int lo = max(0, x0 - reach), hi = min(W, x0 + kRowSeg + reach);
-        const uint16_t* grow = d->g + (size_t)y * W;
-        int any = 0;
-        for (int x = lo + threadIdx.x; x < hi; x += kBlock) {
-            const uint32_t gv = grow[x];
-            any |= gv != kGInf;
-            sG2[x - lo] = gv == kGInf ? 0x7fffffffu : gv * gv;
+        const bool lut_lds = lut_n <= kLutLds;
+        const uint32_t cap = exp_d2 ? 0xffffffffu : (uint32_t)lut_n;
+        const int lo = max(0, x0 - R), hi = min(W, x0 + kRowSeg + R);
+        const int ww = hi - lo;
+        const uint16_t* __restrict__ g = d->g + (size_t)y0 * W;
+        const float* __restrict__ lut = d->lut;
+        stage_window<8>(sG, ww, NR, [&](int r, int c) -> uint32_t {
+            return r < nrows ? g_sq(g[(size_t)r * W + lo + c]) : 0x7fffffffu;
+        });
+        if (lut_lds) {
+            float lv[kLutLds / kBlock];
+#pragma unroll
+            for (int u = 0; u < kLutLds / kBlock; ++u) {
+                const int i = threadIdx.x + u * kBlock;
+                lv[u] = i < lut_n ? lut[i] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kLutLds / kBlock; ++u) sLut[threadIdx.x + u * kBlock] = lv[u];
         }
-        any = __syncthreads_or(any);
+        __syncthreads();
         const int x = x0 + threadIdx.x;
         if (x < W) {
-            uint32_t best = 0x7fffffffu;
-            if (any) {
-                const uint32_t* g2 = sG2 - lo;
-                best = g2[x];
-                for (int r = 1;; ++r) {
+            const uint32_t* row = sG - lo;  // row k at row + k * ww, columns lo .. hi-1
+            uint32_t best[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) best[k] = k < nrows ? row[k * ww + x] : 0u;  // 0: nothing to search
+            int r = 1;
+            for (; r <= R; ++r) {
+                const uint32_t r2 = (uint32_t)(r * r);
+                const bool lft = x - r >= 0, rgt = x + r < W;
+                bool live = false;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    if (r2 < best[k] && r2 < cap) {
+                        live = true;
+                        if (lft) best[k] = min(best[k], r2 + row[k * ww + x - r]);
+                        if (rgt) best[k] = min(best[k], r2 + row[k * ww + x + r]);
+                    }
+                }
+                if (!live || (!lft && !rgt)) break;
+            }
+            if (r > R) {  // beyond the staged columns
+                for (;; ++r) {
                     const uint32_t r2 = (uint32_t)r * (uint32_t)r;
-                    if (r2 >= best || r2 >= cap) break;
-                    const bool lft = x - r >= lo, rgt = x + r < hi;
+                    const bool lft = x - r >= 0, rgt = x + r < W;
                     if (!lft && !rgt) break;
-                    if (lft) best = min(best, r2 + g2[x - r]);
-                    if (rgt) best = min(best, r2 + g2[x + r]);
+                    bool live = false;
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        if (r2 < best[k] && r2 < cap) {
+                            live = true;
+                            const uint16_t* gr = g + (size_t)k * W;
+                            if (lft) best[k] = min(best[k], r2 + g_sq(gr[x - r]));
+                            if (rgt) best[k] = min(best[k], r2 + g_sq(gr[x + r]));
+                        }
+                    }
+                    if (!live) break;
                 }
             }
-            if (d2row) d2row[x] = best >= 0x7fffffffu ? 0x7fffffff : (int32_t)best;
-            d->pyr[(size_t)y * W + x] = best < (uint32_t)lut_n ? d->lut[best] : 1.0f;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (k < nrows) {
+                    const size_t pix = (size_t)(y0 + k) * W + x;
+                    const uint32_t b = best[k];
+                    if (exp_d2) d->d2[pix] = b >= 0x7fffffffu ? 0x7fffffff : (int32_t)b;
+                    d->pyr[pix] = b < (uint32_t)lut_n ? (lut_lds ? sLut[b] : lut[b]) : 1.0f;
+                }
+            }
         }
         __syncthreads();
     }
@@ -424,13 +522,11 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
         {
             const LevelGeom g0 = d->lv[from];
             const float* __restrict__ src = d->pyr + g0.off;
-            const int n = R[0];
-            int r, cc, dr, dc;
-            rc_init(n, r, cc, dr, dc);
-            for (; r < n; rc_step(n, r, cc, dr, dc)) {
-                const int X = ox[0] + cc, Y = oy[0] + r;
-                sP[buf[0] + r * n + cc] = (X >= 0 && X < g0.w && Y >= 0 && Y < g0.h) ? src[(size_t)Y * g0.w + X] : 0.f;
-            }
+            const int oxs = ox[0], oys = oy[0];
+            stage_window<16>(sP + buf[0], R[0], R[0], [&](int r, int cc) {
+                const int X = oxs + cc, Y = oys + r;
+                return (X >= 0 && X < g0.w && Y >= 0 && Y < g0.h) ? src[(size_t)Y * g0.w + X] : 0.f;
+            });
         }
         __syncthreads();
         for (int k = 1; k <= nlev; ++k) {
@@ -475,21 +571,37 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
 }
 
 // --------------------------------------------------------------------------
-// Dense inverse search.  The iteration runs in double precision: the
-// Gauss-Newton steps of weakly textured patches and the outlier reset are
-// sensitive enough that single-precision rounding changes a visible fraction
-// of the flow, while vector FP64 runs at the rate of (non-packed) FP32 here.
+// Dense inverse search.  What a patch computes once (template gradients, the
+// regularised Hessian and its inverse, the initial displacement from the
+// coarser level) is formed in double; the iterations run in single precision.
+// With the Hessian regularised by lambda*I the step is bounded by
+// |b| / lambda, so single-precision rounding of the residual sums (relative
+// 2^-24 of sums of order one) moves a patch by far less than the endpoint
+// tolerance of the flow.
 // --------------------------------------------------------------------------
+// (every lane is a valid source for these patterns: no old value needed)
 template <int CTRL>
 __device__ __forceinline__ double dppd(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double red8d(double v) {
     v += dppd<0xB1>(v);
     v += dppd<0x4E>(v);
     v += dppd<0x141>(v);
+    return v;
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+// sum over the 8 lanes of a patch (quad swap pairs, quad swap halves, then
+// mirror within the half row), result in every lane
+__device__ __forceinline__ float red8f(float v) {
+    v += dppf<0xB1>(v);
+    v += dppf<0x4E>(v);
+    v += dppf<0x141>(v);
     return v;
 }
 
@@ -510,9 +622,52 @@ __device__ __forceinline__ double bilinear_d(const float* __restrict__ I, int W,
     return top + ay * (bot - top);
 }
 
+// Densification samples, single precision.  The sample position x + u is
+// split exactly (integer part of u in double, fraction rounded once to
+// float), so the fraction keeps full precision however wide the image; a
+// position off the image samples the border whatever its distance.  Fetch
+// and blend are separate so that several samples' loads can be in flight;
+// the blend recomputes the fractions (fewer registers held across loads).
+struct DensTap {
+    float a, b, c, d;
+};
+__device__ __forceinline__ void dens_split(int W, int H, double ux, double uy, int& ix, int& iy, float& ax,
+                                           float& ay) {
+    const double lim = (double)(W + H + 16);
+    ux = fmin(fmax(ux, -lim), lim);
+    uy = fmin(fmax(uy, -lim), lim);
+    const double fx = floor(ux), fy = floor(uy);
+    ix = (int)fx;
+    iy = (int)fy;
+    ax = (float)(ux - fx);
+    ay = (float)(uy - fy);
+}
+__device__ __forceinline__ DensTap dens_fetch(const float* __restrict__ I, int W, int H, int x, int y, double ux,
+                                              double uy) {
+    int ix, iy;
+    float ax, ay;
+    dens_split(W, H, ux, uy, ix, iy, ax, ay);
+    const int xa = clampi(x + ix, 0, W - 1), xb = clampi(x + ix + 1, 0, W - 1);
+    const int ya = clampi(y + iy, 0, H - 1), yb = clampi(y + iy + 1, 0, H - 1);
+    return DensTap{I[(size_t)ya * W + xa], I[(size_t)ya * W + xb], I[(size_t)yb * W + xa], I[(size_t)yb * W + xb]};
+}
+__device__ __forceinline__ float dens_blend(const DensTap& t, int W, int H, double ux, double uy) {
+    int ix, iy;
+    float ax, ay;
+    dens_split(W, H, ux, uy, ix, iy, ax, ay);
+    const float top = t.a + ax * (t.b - t.a);
+    const float bot = t.c + ax * (t.d - t.c);
+    return top + ay * (bot - top);
+}
+// 1 / max(1, 255 |d|) by the hardware reciprocal (1 ulp)
+__device__ __forceinline__ float dens_weight_f(float dv) {
+    return __builtin_amdgcn_rcpf(fmaxf(1.0f, 255.0f * fabsf(dv)));
+}
+
 // densification weight 1 / max(1, 255 |d|)
 __device__ __forceinline__ double dens_weight(double dv) { return 1.0 / fmax(1.0, 255.0 * fabs(dv)); }
 
+constexpr int kCov = 3;       // patches covering a pixel per axis at stride >= 4
 constexpr int kDisRW = 192;   // LDS search region, columns
 constexpr int kDisRH = 40;    // LDS search region, rows
 constexpr int kDisMargin = kPatch + 2;  // around the initial windows: covers any patch
@@ -520,20 +675,12 @@ constexpr int kDisMargin = kPatch + 2;  // around the initial windows: covers an
 
 // Copies an h x w window of img with top-left (x0, y0), indices clamped into
 // the image (replicated border), into LDS (pitch w).
+template <int U>
 __device__ __forceinline__ void stage_clamped(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
-                                              int x0, int y0, int w, int h) {
-    int r = threadIdx.x / w, cc = threadIdx.x - r * w;
-    const int dr = kBlock / w, dc = kBlock - dr * w;
-    while (r < h) {
-        const int gy = clampi(y0 + r, 0, H - 1), gx = clampi(x0 + cc, 0, W - 1);
-        dst[r * w + cc] = img[(size_t)gy * W + gx];
-        cc += dc;
-        r += dr;
-        if (cc >= w) {
-            cc -= w;
-            ++r;
-        }
-    }
+                                              int x0, int y0, int w, int h, int pitch = 0) {
+    stage_window<U>(
+        dst, w, h, [&](int r, int cc) { return img[(size_t)clampi(y0 + r, 0, H - 1) * W + clampi(x0 + cc, 0, W - 1)]; },
+        pitch);
 }
 
 // One level.  Work item = 32 consecutive patches of one patch row (4 waves x
@@ -574,16 +721,22 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         // ---- template and gradient from the staged reference strip
         const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
         const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
-        stage_clamped(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2);
+        stage_clamped<8>(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2);
         __syncthreads();
-        double T[kPatch], gxs[kPatch], gys[kPatch];
+        // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
+        // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
+        // the patch, and the bilinear sample of row j as h_j + ay (h_{j+1} -
+        // h_j) (h = the row interpolated along x), so that per lane
+        // sum_j g_j I1 = P + ay (Q - P), P = sum_j g_j h_j, Q = sum_j g_j h_{j+1}.
+        double gxs[kPatch], gys[kPatch];
+        float tf[kPatch];
         double hxx = 0.0, hxy = 0.0, hyy = 0.0;
         {
             const float* col = sR + sw + (x - sx0);
 #pragma unroll
             for (int j = 0; j < kPatch; ++j) {
                 const float* q = col + j * sw;
-                T[j] = q[0];
+                tf[j] = q[0];
                 gxs[j] = 0.5 * ((double)q[1] - (double)q[-1]);
                 gys[j] = 0.5 * ((double)q[sw] - (double)q[-sw]);
                 hxx += gxs[j] * gxs[j];
@@ -609,7 +762,8 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const double2* __restrict__ cu = d->puv + gc.poff;
             const int px = min((ox + kPatch / 2) >> 1, gc.w - 1);
             const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
-            const Cover cx = cover_of(px, gc.w, gc.pnx, s), cy = cover_of(py, gc.h, gc.pny, s);
+            const float inv_s = 1.0f / (float)s;
+            const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
             const double i0 = C0[(size_t)py * gc.w + px];
             double sw_ = 0.0, su = 0.0, sv = 0.0;
             for (int q = c; q < cx.n * cy.n; q += 8) {
@@ -648,60 +802,85 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const int RX0 = sBox[0] - kDisMargin, RY0 = sBox[2] - kDisMargin;
         const int RW = min(sBox[1] + kPatch + 1 + kDisMargin - RX0, kDisRW);
         const int RH = min(sBox[3] + kPatch + 1 + kDisMargin - RY0, kDisRH);
-        stage_clamped(sR, I1, Wl, Hl, RX0, RY0, RW, RH);
+        stage_clamped<8>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRW);  // fixed pitch: immediate LDS offsets
         __syncthreads();
 
         // ---- inverse-compositional iterations
-        double ux = u0x, uy = u0y;
+        // ---- inverse-compositional iterations (single precision)
+        float fgx[kPatch], fgy[kPatch];
+#pragma unroll
+        for (int j = 0; j < kPatch; ++j) {
+            fgx[j] = (float)gxs[j];
+            fgy[j] = (float)gys[j];
+        }
+        const float fia = (float)ia, fib = (float)ib, fic = (float)ic;
+        // c by the same single-precision chain, in the same order, as P at
+        // u = 0: where I1 equals the template the residual is exactly 0, so
+        // a patch that does not move stays exactly in place
+        float fcx = 0.f, fcy = 0.f;
+#pragma unroll
+        for (int j = 0; j < kPatch; ++j) {
+            fcx += fgx[j] * tf[j];
+            fcy += fgy[j] * tf[j];
+        }
+        fcx = red8f(fcx);
+        fcy = red8f(fcy);
+        const float flim = (float)lim;
+        float ux = (float)u0x, uy = (float)u0y;
         const int iters = d->iters;
         for (int it = 0; it < iters; ++it) {
-            const double sxu = fmin(fmax(ux, -lim), lim), syu = fmin(fmax(uy, -lim), lim);
-            const double fx = floor(sxu), fy = floor(syu);
-            const double ax = sxu - fx, ay = syu - fy;
+            const float sxu = fminf(fmaxf(ux, -flim), flim), syu = fminf(fmaxf(uy, -flim), flim);
+            const float fx = floorf(sxu), fy = floorf(syu);
+            const float ax = sxu - fx, ay = syu - fy;
             const int ix = (int)fx, iy = (int)fy;
             const int rx = x + ix - RX0, ry = oy + iy - RY0;
-            double bx = 0.0, by = 0.0, hprev = 0.0;
-            if (rx >= 0 && rx + 1 < RW && ry >= 0 && ry + kPatch < RH) {
-                const float* q = sR + ry * RW + rx;
+            float px = 0.f, qx = 0.f, py = 0.f, qy = 0.f;
+            if ((unsigned)rx < (unsigned)(RW - 1) && (unsigned)ry < (unsigned)(RH - kPatch)) {
+                const float* q = sR + ry * kDisRW + rx;
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
-                    const double A = q[j * RW], Bv = q[j * RW + 1];
-                    const double h = A + ax * (Bv - A);
-                    if (j > 0) {
-                        const double r = (hprev + ay * (h - hprev)) - T[j - 1];
-                        bx += gxs[j - 1] * r;
-                        by += gys[j - 1] * r;
+                    const float A = q[j * kDisRW], Bv = q[j * kDisRW + 1];
+                    const float h = A + ax * (Bv - A);
+                    if (j < kPatch) {
+                        px += fgx[j] * h;
+                        py += fgy[j] * h;
                     }
-                    hprev = h;
+                    if (j > 0) {
+                        qx += fgx[j - 1] * h;
+                        qy += fgy[j - 1] * h;
+                    }
                 }
             } else {
                 const int xa = clampi(x + ix, 0, Wl - 1), xb = clampi(x + ix + 1, 0, Wl - 1);
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
                     const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
-                    const double A = row[xa], Bv = row[xb];
-                    const double h = A + ax * (Bv - A);
-                    if (j > 0) {
-                        const double r = (hprev + ay * (h - hprev)) - T[j - 1];
-                        bx += gxs[j - 1] * r;
-                        by += gys[j - 1] * r;
+                    const float A = row[xa], Bv = row[xb];
+                    const float h = A + ax * (Bv - A);
+                    if (j < kPatch) {
+                        px += fgx[j] * h;
+                        py += fgy[j] * h;
                     }
-                    hprev = h;
+                    if (j > 0) {
+                        qx += fgx[j - 1] * h;
+                        qy += fgy[j - 1] * h;
+                    }
                 }
             }
-            bx = red8d(bx);
-            by = red8d(by);
-            ux -= ia * bx + ib * by;
-            uy -= ib * bx + ic * by;
+            const float bx = red8f(px + ay * (qx - px)) - fcx;
+            const float by = red8f(py + ay * (qy - py)) - fcy;
+            ux -= fia * bx + fib * by;
+            uy -= fib * bx + fic * by;
         }
         // outlier reset: back to the initial displacement when the patch
         // moved more than its size
-        const double mx = ux - u0x, my = uy - u0y;
+        double rux = ux, ruy = uy;
+        const double mx = rux - u0x, my = ruy - u0y;
         if (sqrt(mx * mx + my * my) > (double)kPatch) {
-            ux = u0x;
-            uy = u0y;
+            rux = u0x;
+            ruy = u0y;
         }
-        if (valid && c == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(ux, uy);
+        if (valid && c == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(rux, ruy);
         __syncthreads();  // the next item restages sR
     }
 }
@@ -709,20 +888,22 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
 // --------------------------------------------------------------------------
 // Densification at level 0: the flow of a pixel is the mean of the covering
 // patches' displacements weighted by 1 / max(1, 255 |I1(x+u) - I0(x)|)
-// (double precision); optionally zero outside the reference window's edge
-// pixels.
+// (single precision: a weight's relative error of a few ulp moves the mean
+// by that fraction of the spread of the displacements); optionally zero
+// outside the reference window's edge pixels.
 // --------------------------------------------------------------------------
-template <bool B>
+template <bool B, int TW>
 __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const BatchArgs ba, int32_t total_arg) {
+    constexpr int TH = kBlock / TW;  // tile TW x TH pixels, one per thread
     const int32_t total = item_total<B>(ba, total_arg);
     for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const LevelGeom g = d->lv[0];
         const int W = g.w, H = g.h;
-        const int tiles_x = (W + 63) / 64;
-        const int x = (local % tiles_x) * 64 + (threadIdx.x & 63);
-        const int y = (local / tiles_x) * kDensTileH + (threadIdx.x >> 6);
+        const int tiles_x = (W + TW - 1) / TW;
+        const int x = (local % tiles_x) * TW + (int)(threadIdx.x % TW);
+        const int y = (local / tiles_x) * TH + (int)(threadIdx.x / TW);
         if (x >= W || y >= H) continue;
         const size_t pix = (size_t)y * W + x;
         if (d->zero_out) {  // first window of a served stream: no flow yet
@@ -735,21 +916,47 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const float* __restrict__ I0 = d->pyr_prev;
         const float* __restrict__ I1 = d->pyr;
         const double2* __restrict__ pu = d->puv + g.poff;
-        const Cover cx = cover_of(x, W, g.pnx, s), cy = cover_of(y, H, g.pny, s);
-        const double i0 = I0[pix];
-        double sw = 0.0, su = 0.0, sv = 0.0;
-        for (int qy = 0; qy < cy.n; ++qy) {
-            const int ky = cover_index(cy, qy);
-            for (int qx = 0; qx < cx.n; ++qx) {
-                const int kx = cover_index(cx, qx);
-                const double2 u = pu[(size_t)ky * g.pnx + kx];
-                const double w = dens_weight(bilinear_d(I1, W, H, x + u.x, y + u.y) - i0);
-                sw += w;
-                su += w * u.x;
-                sv += w * u.y;
+        const float inv_s = 1.0f / (float)s;
+        const Cover cx = cover_of(x, W, g.pnx, s, inv_s), cy = cover_of(y, H, g.pny, s, inv_s);
+        const float i0 = I0[pix];
+        float sw = 0.f, su = 0.f, sv = 0.f;
+        if (cx.n <= kCov && cy.n <= kCov) {
+            // all covering displacements, then all their samples, then the
+            // sums in the same (row-major) order as the general loop
+            double2 u[kCov * kCov];
+#pragma unroll
+            for (int q = 0; q < kCov * kCov; ++q) {
+                const int qy = q / kCov, qx = q % kCov;
+                if (qy < cy.n && qx < cx.n)
+                    u[q] = pu[(size_t)cover_index(cy, qy) * g.pnx + cover_index(cx, qx)];
+            }
+            DensTap tp[kCov * kCov];
+#pragma unroll
+            for (int q = 0; q < kCov * kCov; ++q)
+                if (q / kCov < cy.n && q % kCov < cx.n) tp[q] = dens_fetch(I1, W, H, x, y, u[q].x, u[q].y);
+#pragma unroll
+            for (int q = 0; q < kCov * kCov; ++q) {
+                if (q / kCov < cy.n && q % kCov < cx.n) {
+                    const float w = dens_weight_f(dens_blend(tp[q], W, H, u[q].x, u[q].y) - i0);
+                    sw += w;
+                    su += w * (float)u[q].x;
+                    sv += w * (float)u[q].y;
+                }
+            }
+        } else {
+            for (int qy = 0; qy < cy.n; ++qy) {
+                const int ky = cover_index(cy, qy);
+                for (int qx = 0; qx < cx.n; ++qx) {
+                    const int kx = cover_index(cx, qx);
+                    const double2 u = pu[(size_t)ky * g.pnx + kx];
+                    const float w = dens_weight_f(dens_blend(dens_fetch(I1, W, H, x, y, u.x, u.y), W, H, u.x, u.y) - i0);
+                    sw += w;
+                    su += w * (float)u.x;
+                    sv += w * (float)u.y;
+                }
             }
         }
-        float fu = (float)(su / sw), fv = (float)(sv / sw);
+        float fu = su / sw, fv = sv / sw;
         const uint8_t m = d->mask ? d->mask[pix] : 1;
         if ((d->flags & EBOF_MASK_FLOW) && !m) fu = fv = 0.f;
         d->flow[pix] = fu;
@@ -792,22 +999,45 @@ void launch_denoise_fill(const Launch& L, bool pack) {
 }
 void launch_pack_cols(const Launch& L) { EBOF_LAUNCH(k_pack_cols, L); }
 void launch_edt_cols(const Launch& L) { EBOF_LAUNCH(k_edt_cols, L); }
-void launch_edt_rows(const Launch& L) { EBOF_LAUNCH(k_edt_rows, L); }
+#define EBOF_LAUNCH_T(KERNEL, T, L)                                                                    \
+    do {                                                                                               \
+        if ((L).batch)                                                                                 \
+            hipLaunchKernelGGL((KERNEL<true, T>), dim3((L).grid), dim3(kBlock), 0, (L).stream, *(L).one, \
+                               (L).ba, (L).total);                                                     \
+        else                                                                                           \
+            hipLaunchKernelGGL((KERNEL<false, T>), dim3((L).grid), dim3(kBlock), 0, (L).stream,        \
+                               *(L).one, (L).ba, (L).total);                                           \
+    } while (0)
+
+void launch_edt_rows(const Launch& L, int rows_nr) {
+    switch (rows_nr) {
+        case 1: EBOF_LAUNCH_T(k_edt_rows, 1, L); break;
+        case 2: EBOF_LAUNCH_T(k_edt_rows, 2, L); break;
+        case 8: EBOF_LAUNCH_T(k_edt_rows, 8, L); break;
+        default: EBOF_LAUNCH_T(k_edt_rows, 4, L); break;
+    }
+}
 void launch_pyr_chain(const Launch& L, int from) { EBOF_LAUNCH(k_pyr_chain, L, from); }
 void launch_dis_level(const Launch& L, int level) { EBOF_LAUNCH(k_dis_level, L, level); }
-void launch_densify(const Launch& L) { EBOF_LAUNCH(k_densify, L); }
+void launch_densify(const Launch& L, int tile_w) {
+    switch (tile_w) {
+        case 128: EBOF_LAUNCH_T(k_densify, 128, L); break;
+        case 256: EBOF_LAUNCH_T(k_densify, 256, L); break;
+        default: EBOF_LAUNCH_T(k_densify, 64, L); break;
+    }
+}
 
 // --------------------------------------------------------------------------
 // per-window work items of each stage
 // --------------------------------------------------------------------------
-int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero) {
+int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const Tune& t) {
     const int64_t N = (int64_t)d.W * d.H;
     const int bands = (d.W + 63) / 64, nch = (d.H + kChunk - 1) / kChunk;
     if (stage == kStZero) return zero ? (int32_t)((N + kZeroBytesPerItem - 1) / kZeroBytesPerItem) : 0;
     if (stage == kStScatter) return (int32_t)((d.n_ev + kEventsPerItem - 1) / kEventsPerItem);
     if (stage == kStDenoise) return ((d.W + kTile - 1) / kTile) * ((d.H + kTileH - 1) / kTileH);
     if (stage == kStPack || stage == kStCols) return bands * nch;
-    if (stage == kStRows) return d.H * ((d.W + kRowSeg - 1) / kRowSeg);
+    if (stage == kStRows) return ((d.H + t.rows_nr - 1) / t.rows_nr) * ((d.W + kRowSeg - 1) / kRowSeg);
     if (stage >= kStPyr && stage < kStPyr + kMaxLevels - 1) {
         const int from = (stage - kStPyr) * kPyrChain;
         if (from >= d.L - 1) return 0;
@@ -821,7 +1051,9 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero) {
         return g.pny * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
     }
     if (stage == kStDensify)
-        return (has_flow || d.zero_out) ? ((d.W + 63) / 64) * ((d.H + kDensTileH - 1) / kDensTileH) : 0;
+        return (has_flow || d.zero_out)
+                   ? ((d.W + t.dens_tw - 1) / t.dens_tw) * ((d.H + kBlock / t.dens_tw - 1) / (kBlock / t.dens_tw))
+                   : 0;
     return 0;
 }
 

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <deque>
 #include <map>
+#include <string>
 #include <set>
 #include <utility>
 #include <vector>
@@ -135,7 +136,24 @@ static void test_take_one_per_stream() {
     }
 }
 
+#define CHECK(c) do { if (!(c)) { std::fprintf(stderr, "check failed line %d: %s\n", __LINE__, #c); std::abort(); } } while (0)
+
+static void test_parse_tune_line() {
+    std::string key;
+    std::vector<int> v;
+    CHECK(ebof::parse_tune_line("1280,720,4,4,1,0;\t4 64 0 2048 -1\n", 5, &key, &v));
+    CHECK(key == "1280,720,4,4,1,0;" && v.size() == 5 && v[0] == 4 && v[2] == 0 && v[4] == -1);
+    CHECK(ebof::parse_tune_line("k\t1 2 3 \r\n", 3, &key, &v));
+    CHECK(!ebof::parse_tune_line("k\t1 2", 3, &key, &v));          // too few
+    CHECK(!ebof::parse_tune_line("k\t1 2 3 4", 3, &key, &v));      // too many
+    CHECK(!ebof::parse_tune_line("k 1 2 3", 3, &key, &v));          // no tab
+    CHECK(!ebof::parse_tune_line("\t1 2 3", 3, &key, &v));         // empty key
+    CHECK(!ebof::parse_tune_line("k\t1 x 3", 3, &key, &v));        // not a number
+    CHECK(!ebof::parse_tune_line("k\t1 99999999999 3", 3, &key, &v));  // out of range
+}
+
 int main() {
+    test_parse_tune_line();
     test_arena();
     test_ring();
     test_take_one_per_stream();

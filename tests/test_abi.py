@@ -67,3 +67,8 @@ def test_stage_calls_reject_null_context():
     p = L.ebof_params_default(64, 64)
     assert lib.ebof_bin_events(None, ctypes.byref(p), None, None, None, 0, 0, None, None, None) == L.EBOF_E_INVAL
     assert lib.ebof_flow(None, ctypes.byref(p), None, None, None, None, None) == L.EBOF_E_INVAL
+
+
+def test_set_tuning_rejects_null_context():
+    lib = L.load()
+    assert lib.ebof_set_tuning(None, L.EBOF_TUNE_AUTO, None) == L.EBOF_E_INVAL

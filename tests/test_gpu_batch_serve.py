@@ -115,6 +115,138 @@ def test_batch_equals_alone_and_graph_replays(ctx):
                     v.zero_()
 
 
+def _batch_of(streams, outs, k):
+    batch = []
+    for s, (p, evs) in enumerate(streams):
+        o = outs[s]
+        w = dict(params=p, x=evs[k]["x"], y=evs[k]["y"], t=evs[k]["t"], t0_us=evs[k]["t0"],
+                 edge_out=o["edge"], d2_out=o["d2"], pyr_out=o["pyr"])
+        if k > 0:
+            w.update(pyr_prev=o["pyr_prev"], mask=o["mask"], flow_out=o["flow"])
+        batch.append(w)
+    return batch
+
+
+def _outs_for(streams, ref, k):
+    outs = []
+    for s, (p, _) in enumerate(streams):
+        W, H = p.width, p.height
+        P = L.ebof_pyramid_floats(p)
+        outs.append(dict(edge=torch.empty(W * H, dtype=torch.uint8, device="cuda"),
+                         d2=torch.empty(W * H, dtype=torch.int32, device="cuda"),
+                         pyr=torch.empty(P, dtype=torch.float32, device="cuda"),
+                         flow=torch.empty(2 * W * H, dtype=torch.float32, device="cuda"),
+                         pyr_prev=ref[s][k - 1][1], mask=ref[s][k - 1][0]))
+    return outs
+
+
+def _check_outs(streams, ref, outs, k, tag):
+    for s in range(len(streams)):
+        r, o = ref[s][k], outs[s]
+        assert torch.equal(o["edge"], r[0]), (tag, s, "edge")
+        assert torch.equal(o["d2"], r[2]), (tag, s, "d2")
+        assert torch.equal(o["pyr"], r[1]), (tag, s, "pyramid")
+        assert torch.equal(o["flow"], r[3]), (tag, s, "flow")
+
+
+@pytest.mark.parametrize("rows, tile_w, grid", [(1, 256, 256), (8, 128, 0), (2, 64, 4096)])
+def test_batch_forced_launch_shapes_equal_alone(ctx, tmp_path, rows, tile_w, grid):
+    """Every tile shape and block count the tuner can pick gives the stage
+    calls' results: shapes forced through the tuning cache file."""
+    streams = mixed_streams(n_low=2, n_hd=1, windows=2)
+    ref = [alone(ctx, p, evs) for p, evs in streams]
+    outs = _outs_for(streams, ref, 1)
+    batch = _batch_of(streams, outs, 1)
+    path = tmp_path / "tune.txt"
+    vals = [rows, tile_w] + [grid] * L.EBOF_TUNE_STAGES
+    path.write_text(L.batch_layout_key(batch) + "\t" + " ".join(map(str, vals)) + "\n")
+    L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, str(path))
+    try:
+        stream = torch.cuda.Stream()
+        _say(f"forced shapes rows={rows} tile_w={tile_w} grid={grid}")
+        L.ebof_run_batch(ctx, batch, stream=stream)
+        torch.cuda.synchronize()
+        _check_outs(streams, ref, outs, 1, (rows, tile_w, grid))
+        # the file is unchanged: the layout was tuned already (read from it)
+        assert path.read_text().count("\n") == 1
+    finally:
+        L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, None)
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """A new layout is tuned once and appended to the cache; a context that
+    reads the cache uses the entry (appends nothing) and gives the same
+    results as the stage calls."""
+    path = tmp_path / "cache.txt"
+    streams = mixed_streams(n_low=1, n_hd=1, windows=2)
+    for round_ in range(2):
+        c = L.ebof_create(arena_bytes=1 << 30)
+        try:
+            L.ebof_set_tuning(c, L.EBOF_TUNE_AUTO, str(path))
+            ref = [alone(c, p, evs) for p, evs in streams]
+            outs = _outs_for(streams, ref, 1)
+            batch = _batch_of(streams, outs, 1)
+            _say(f"autotune round {round_}")
+            L.ebof_run_batch(c, batch, stream=torch.cuda.Stream())
+            torch.cuda.synchronize()
+            _check_outs(streams, ref, outs, 1, ("autotune", round_))
+            lines = path.read_text().splitlines()
+            assert len(lines) == 1, lines
+            key, vals = lines[0].split("\t")
+            assert key == L.batch_layout_key(batch)
+            v = [int(x) for x in vals.split()]
+            assert len(v) == 2 + L.EBOF_TUNE_STAGES
+            assert v[0] in (1, 2, 4, 8) and v[1] in (64, 128, 256)
+        finally:
+            torch.cuda.synchronize()
+            c.close()
+
+
+def test_tuning_rejects_bad_cache(ctx, tmp_path):
+    path = tmp_path / "bad.txt"
+    path.write_text("346,260,3,4,1,0;\t4 64 1 2\n")  # too few block counts
+    with pytest.raises(L.EbofError) as ei:
+        L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, str(path))
+    assert ei.value.code == L.EBOF_E_INVAL
+    with pytest.raises(L.EbofError):
+        L.ebof_set_tuning(ctx, 7, None)
+
+
+def test_stage_calls_pipelined_over_streams(ctx):
+    """Window k's binning and EDT on HIP stream k mod 3, the flow k-1 -> k on
+    the same stream after an event on window k-1's pyramid: consecutive
+    windows overlap on the device and every output equals the sequential
+    stage calls'."""
+    for p, evs in mixed_streams(n_low=1, n_hd=1, windows=4):
+        ref = alone(ctx, p, evs)
+        W, H = p.width, p.height
+        P = L.ebof_pyramid_floats(p)
+        sts = [torch.cuda.Stream() for _ in range(3)]
+        out, ev_pre = [], []
+        for k, ev in enumerate(evs):
+            st = sts[k % 3]
+            e = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+            d2 = torch.empty(W * H, dtype=torch.int32, device="cuda")
+            pr = torch.empty(P, dtype=torch.float32, device="cuda")
+            L.ebof_bin_events(ctx, p, ev["x"], ev["y"], ev["t"], ev["t0"], e, stream=st)
+            L.ebof_edt_surface(ctx, p, e, pr, d2, stream=st)
+            done = torch.cuda.Event()
+            done.record(st)
+            ev_pre.append(done)
+            f = None
+            if k > 0:
+                st.wait_event(ev_pre[k - 1])
+                f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+                L.ebof_flow(ctx, p, out[k - 1][1], pr, f, mask=out[k - 1][0], stream=st)
+            out.append((e, pr, d2, f))
+        torch.cuda.synchronize()
+        _say(f"pipelined {W}x{H}: {len(evs)} windows")
+        for k in range(len(evs)):
+            for i, name in enumerate(("edge", "pyramid", "d2", "flow")):
+                if out[k][i] is not None:
+                    assert torch.equal(out[k][i], ref[k][i]), (W, k, name)
+
+
 def test_serving_alone_vs_mix(ctx):
     streams = mixed_streams(n_low=4, n_hd=2, windows=4)
     ref = [alone(ctx, p, evs) for p, evs in streams]
