@@ -46,6 +46,16 @@ __device__ __forceinline__ int32_t item_total(const BatchArgs& ba, int32_t total
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Work-groups are dispatched round-robin over the 8 XCDs (block b on XCD
+// b mod 8), each with its own L2.  Neighbouring items share halo data, so
+// block b takes item x*q + min(x, r) + b/8 (x = b mod 8, G = 8q + r): every
+// XCD works through a contiguous run of items.  A bijection on [0, G).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t G) {
+    const int32_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 // Copies an h x w window into LDS (row pitch w, or `pitch`): element (r, c) =
 // src(r, c).
 // Thread t takes elements t, t + kBlock, ...; it issues U of its loads before
@@ -106,7 +116,7 @@ __device__ __forceinline__ int cover_index(const Cover& c, int q) { return q < c
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_zero(const WinDesc one, const BatchArgs ba, int32_t total_arg) {
     const int32_t total = item_total<B>(ba, total_arg);
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int64_t n = (int64_t)d->W * d->H;
@@ -127,7 +137,7 @@ template <bool B>
 __global__ __launch_bounds__(kBlock) void k_scatter(const WinDesc one, const BatchArgs ba, int32_t total_arg) {
     __shared__ uint32_t s_drop[kBlock / 64];
     const int32_t total = item_total<B>(ba, total_arg);
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int64_t n = d->n_ev, t0 = d->t0, t1 = d->t1;
@@ -182,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_denoise_fill(const WinDesc one, cons
     __shared__ uint8_t sBits[4][TW];
     const int32_t total = item_total<B>(ba, total_arg);
     const int tid = threadIdx.x;
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_cols(const WinDesc one, const B
     __shared__ uint16_t sBits[4][64];
     const int32_t total = item_total<B>(ba, total_arg);
     const int c = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
@@ -303,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
                                                      int32_t total_arg) {
     const int32_t total = item_total<B>(ba, total_arg);
     const int c = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
     __shared__ uint32_t sG[NR * (kRowSeg + 2 * R)];  // g^2, 0x7fffffff = no edge in the column
     __shared__ float sLut[kLutLds];
     const int32_t total = item_total<B>(ba, total_arg);
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int W = d->W, H = d->H;
@@ -500,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
     // pointers keep every access in the LDS address space
     __shared__ float sP[85 * 85 + 41 * 41 + 19 * 19];
     const int32_t total = item_total<B>(ba, total_arg);
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int nlev = min(kPyrChain, d->L - 1 - from);
@@ -699,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
     const int lane = threadIdx.x & 63;
     const int slot = (threadIdx.x >> 6) * 8 + (lane >> 3);
     const int c = lane & 7;
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const LevelGeom g = d->lv[level];
@@ -896,7 +906,7 @@ template <bool B, int TW>
 __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const BatchArgs ba, int32_t total_arg) {
     constexpr int TH = kBlock / TW;  // tile TW x TH pixels, one per thread
     const int32_t total = item_total<B>(ba, total_arg);
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const LevelGeom g = d->lv[0];
