@@ -236,12 +236,13 @@ static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int*
 
 // ---------------------------------------------------------------- timing
 template <class F>
-static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f) {
+static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f, int launches = 1) {
     if (!(ctx->timing_mask & (1u << kid))) {
         f();
         return;
     }
     TimedPair tp;
+    tp.launches = launches;
     for (hipEvent_t* e : {&tp.a, &tp.b}) {
         if (!ctx->event_pool.empty()) {
             *e = ctx->event_pool.back();
@@ -668,14 +669,27 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
 
     const int mode = (ctx->timing_mask == 0 && ctx->use_graphs) ? graph_mode : kGraphNone;
     auto run_all = [&](bool all) {
-        for (int s : pipeline_order(lmax)) {
-            if (!all && !totals[s]) continue;
-            const int kid = stage_kernel_id(s);
-            Launch L = batch_launch(br, &descs[0], s, totals[s], stage_grid(s, totals[s], tune, mode), st);
+        // consecutive launches of one kernel (pyramid chains, search levels)
+        // share one timing bracket
+        std::vector<int> order;
+        for (int s : pipeline_order(lmax))
+            if (all || totals[s]) order.push_back(s);
+        for (size_t i = 0; i < order.size();) {
+            const int kid = stage_kernel_id(order[i]);
+            size_t j = i + 1;
+            while (j < order.size() && stage_kernel_id(order[j]) == kid) ++j;
+            auto launch_group = [&] {
+                for (size_t q = i; q < j; ++q) {
+                    const int s = order[q];
+                    launch_stage(batch_launch(br, &descs[0], s, totals[s], stage_grid(s, totals[s], tune, mode), st),
+                                 s, tune);
+                }
+            };
             if (kid < 0)
-                launch_stage(L, s, tune);
+                launch_group();
             else
-                timed(ctx, kid, st, [&] { launch_stage(L, s, tune); });
+                timed(ctx, kid, st, launch_group, (int)(j - i));
+            i = j;
         }
     };
     if (mode == kGraphNone) {
@@ -872,10 +886,16 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
     timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
-    for (int from = 0; from < p->levels - 1; from += kPyrChain)
-        timed(ctx, EBOF_K_PYR_DOWN, st, [&] {
-            launch_pyr_chain(one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
-        });
+    const int nchain = (p->levels - 1 + kPyrChain - 1) / kPyrChain;
+    if (nchain > 0)
+        timed(
+            ctx, EBOF_K_PYR_DOWN, st,
+            [&] {
+                for (int from = 0; from < p->levels - 1; from += kPyrChain)
+                    launch_pyr_chain(
+                        one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
+            },
+            nchain);
     return launch_status(ctx);
 }
 
@@ -900,9 +920,13 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
     d.pyr_prev = pyr_prev;
     d.mask = mask;
     d.flow = flow_out;
-    for (int l = p->levels - 1; l >= 0; --l)
-        timed(ctx, EBOF_K_DIS_LEVEL, st,
-              [&] { launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, kStageTune), st), l); });
+    timed(
+        ctx, EBOF_K_DIS_LEVEL, st,
+        [&] {
+            for (int l = p->levels - 1; l >= 0; --l)
+                launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, kStageTune), st), l);
+        },
+        p->levels);
     timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw); });
     return launch_status(ctx);
 }
@@ -976,7 +1000,7 @@ int ebof_timing_read(ebof_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t
         rc = check_hip(ctx, hipEventElapsedTime(&ms, tp.a, tp.b), "hipEventElapsedTime");
         if (rc) return rc;
         tot += ms;
-        ++cnt;
+        cnt += tp.launches;
         ctx->event_pool.push_back(tp.a);
         ctx->event_pool.push_back(tp.b);
     }

@@ -59,6 +59,7 @@ struct Lut {
 
 struct TimedPair {
     hipEvent_t a, b;
+    int launches;  // consecutive launches between a and b
 };
 
 // Device descriptor table + pinned staging ring + captured graphs of one
