@@ -581,9 +581,10 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
 }
 
 // --------------------------------------------------------------------------
-// Dense inverse search.  What a patch computes once (template gradients, the
-// regularised Hessian and its inverse, the initial displacement from the
-// coarser level) is formed in double; the iterations run in single precision.
+// Dense inverse search.  The template gradients and the regularised Hessian
+// and its inverse are formed in double (once per patch); the initial
+// displacement from the coarser level is densified as at level 0 (single
+// precision, exact sample split); the iterations run in single precision.
 // With the Hessian regularised by lambda*I the step is bounded by
 // |b| / lambda, so single-precision rounding of the residual sums (relative
 // 2^-24 of sums of order one) moves a patch by far less than the endpoint
@@ -613,23 +614,6 @@ __device__ __forceinline__ float red8f(float v) {
     v += dppf<0x4E>(v);
     v += dppf<0x141>(v);
     return v;
-}
-
-// bilinear sample (replicated border) of a float image, in double
-__device__ __forceinline__ double bilinear_d(const float* __restrict__ I, int W, int H, double sx, double sy) {
-    const double lim = (double)(W + H + 16);
-    sx = fmin(fmax(sx, -lim), lim);
-    sy = fmin(fmax(sy, -lim), lim);
-    const double fx = floor(sx), fy = floor(sy);
-    const double ax = sx - fx, ay = sy - fy;
-    const int x0 = (int)fx, y0 = (int)fy;
-    const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
-    const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
-    const double a = I[(size_t)ya * W + xa], b = I[(size_t)ya * W + xb];
-    const double c = I[(size_t)yb * W + xa], d = I[(size_t)yb * W + xb];
-    const double top = a + ax * (b - a);
-    const double bot = c + ax * (d - c);
-    return top + ay * (bot - top);
 }
 
 // Densification samples, single precision.  The sample position x + u is
@@ -674,23 +658,36 @@ __device__ __forceinline__ float dens_weight_f(float dv) {
     return __builtin_amdgcn_rcpf(fmaxf(1.0f, 255.0f * fabsf(dv)));
 }
 
-// densification weight 1 / max(1, 255 |d|)
-__device__ __forceinline__ double dens_weight(double dv) { return 1.0 / fmax(1.0, 255.0 * fabs(dv)); }
-
 constexpr int kCov = 3;       // patches covering a pixel per axis at stride >= 4
 constexpr int kDisRW = 192;   // LDS search region, columns
 constexpr int kDisRH = 40;    // LDS search region, rows
+constexpr int kDisRP = 41;    // ... stored column-major with this (odd) pitch
 constexpr int kDisMargin = kPatch + 2;  // around the initial windows: covers any patch
                                         // that stays within the reset distance
 
-// Copies an h x w window of img with top-left (x0, y0), indices clamped into
-// the image (replicated border), into LDS (pitch w).
-template <int U>
-__device__ __forceinline__ void stage_clamped(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
-                                              int x0, int y0, int w, int h, int pitch = 0) {
-    stage_window<U>(
-        dst, w, h, [&](int r, int cc) { return img[(size_t)clampi(y0 + r, 0, H - 1) * W + clampi(x0 + cc, 0, W - 1)]; },
-        pitch);
+// Copies the h x w window of img at (x0, y0), indices clamped into the image
+// (replicated border), into LDS: element (r, c) at dst[c * cs + r * rs]
+// (row-major: cs = 1, rs = pitch; column-major: cs = pitch, rs = 1).  Lanes
+// take columns and the block's waves take rows, so a row's loads coalesce
+// and a thread computes its row offsets once; a thread's loads of a column
+// chunk are all issued before its LDS writes.  Needs h <= 4 * RMAX.
+template <int RMAX>
+__device__ __forceinline__ void stage_rows_cols(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
+                                                int x0, int y0, int w, int h, int cs, int rs) {
+    constexpr int NW = kBlock / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int roff[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) roff[i] = clampi(y0 + wave + NW * i, 0, H - 1) * W;
+    for (int c = lane; c < w; c += 64) {
+        const int gx = clampi(x0 + c, 0, W - 1);
+        float v[RMAX];
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i) v[i] = wave + NW * i < h ? img[roff[i] + gx] : 0.f;
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i)
+            if (wave + NW * i < h) dst[c * cs + (wave + NW * i) * rs] = v[i];
+    }
 }
 
 // One level.  Work item = 32 consecutive patches of one patch row (4 waves x
@@ -703,7 +700,7 @@ __device__ __forceinline__ void stage_clamped(float* __restrict__ dst, const flo
 template <bool B>
 __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                       int level) {
-    __shared__ float sR[kDisRW * kDisRH];
+    __shared__ float sR[kDisRW * kDisRP];
     __shared__ int sBox[4];
     const int32_t total = item_total<B>(ba, total_arg);
     const int lane = threadIdx.x & 63;
@@ -731,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         // ---- template and gradient from the staged reference strip
         const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
         const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
-        stage_clamped<8>(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2);
+        stage_rows_cols<(kPatch + 2 + 3) / 4>(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2, 1, sw);
         __syncthreads();
         // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
         // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
@@ -759,7 +756,8 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         hyy = red8d(hyy);
         const double ha = hxx + lam, hc = hyy + lam;
         const double det = ha * hc - hxy * hxy;
-        const double ia = hc / det, ib = -hxy / det, ic = ha / det;
+        const double idet = 1.0 / det;
+        const double ia = hc * idet, ib = -hxy * idet, ic = ha * idet;
 
         // ---- initial displacement: twice the coarser dense flow at the
         // pixel nearest the patch centre (densified there from the coarser
@@ -774,21 +772,22 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
             const float inv_s = 1.0f / (float)s;
             const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
-            const double i0 = C0[(size_t)py * gc.w + px];
-            double sw_ = 0.0, su = 0.0, sv = 0.0;
+            const float i0 = C0[(size_t)py * gc.w + px];
+            float sw_ = 0.f, su = 0.f, sv = 0.f;  // as in the densification
             for (int q = c; q < cx.n * cy.n; q += 8) {
                 const int qx = cover_index(cx, q % cx.n), qy = cover_index(cy, q / cx.n);
                 const double2 u = cu[(size_t)qy * gc.pnx + qx];
-                const double w = dens_weight(bilinear_d(C1, gc.w, gc.h, px + u.x, py + u.y) - i0);
+                const float w =
+                    dens_weight_f(dens_blend(dens_fetch(C1, gc.w, gc.h, px, py, u.x, u.y), gc.w, gc.h, u.x, u.y) - i0);
                 sw_ += w;
-                su += w * u.x;
-                sv += w * u.y;
+                su += w * (float)u.x;
+                sv += w * (float)u.y;
             }
-            sw_ = red8d(sw_);
-            su = red8d(su);
-            sv = red8d(sv);
-            u0x = 2.0 * (su / sw_);
-            u0y = 2.0 * (sv / sw_);
+            sw_ = red8f(sw_);
+            su = red8f(su);
+            sv = red8f(sv);
+            u0x = 2.0 * (double)(su / sw_);
+            u0y = 2.0 * (double)(sv / sw_);
         }
 
         // ---- stage the search region of I1
@@ -812,7 +811,9 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const int RX0 = sBox[0] - kDisMargin, RY0 = sBox[2] - kDisMargin;
         const int RW = min(sBox[1] + kPatch + 1 + kDisMargin - RX0, kDisRW);
         const int RH = min(sBox[3] + kPatch + 1 + kDisMargin - RY0, kDisRH);
-        stage_clamped<8>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRW);  // fixed pitch: immediate LDS offsets
+        // column-major: a lane's rows of one column are contiguous, so every
+        // read of an iteration is an immediate offset from one address
+        stage_rows_cols<kDisRH / 4>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP, 1);
         __syncthreads();
 
         // ---- inverse-compositional iterations
@@ -846,10 +847,10 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const int rx = x + ix - RX0, ry = oy + iy - RY0;
             float px = 0.f, qx = 0.f, py = 0.f, qy = 0.f;
             if ((unsigned)rx < (unsigned)(RW - 1) && (unsigned)ry < (unsigned)(RH - kPatch)) {
-                const float* q = sR + ry * kDisRW + rx;
+                const float* q = sR + rx * kDisRP + ry;
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
-                    const float A = q[j * kDisRW], Bv = q[j * kDisRW + 1];
+                    const float A = q[j], Bv = q[kDisRP + j];
                     const float h = A + ax * (Bv - A);
                     if (j < kPatch) {
                         px += fgx[j] * h;
