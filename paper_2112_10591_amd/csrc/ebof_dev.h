@@ -17,7 +17,8 @@ namespace ebof {
 constexpr int kMaxLevels = EBOF_MAX_LEVELS;
 constexpr int kPatch = EBOF_PATCH;
 constexpr uint16_t kGInf = 0xFFFF;  // "no edge pixel in this column"
-constexpr int kBlock = 256;         // threads per block of every kernel
+constexpr int kBlock = 256;         // threads per block of every kernel but the pyramid's
+constexpr int kPyrBlock = 1024;     // threads per block of the pyramid chain
 
 // work-item granularity of each stage
 constexpr int kEventsPerItem = 512;   // scatter: events per block
@@ -29,6 +30,7 @@ constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
 constexpr int kZeroBytesPerItem = 4096;
 constexpr int kRowSeg = 256;          // EDT row pass: pixels per item row
 constexpr int kRowReach = 64;         // EDT row pass: columns staged each side of a segment
+constexpr int kRowUnroll = 4;         // EDT row pass: radii per search step (divides kRowReach)
 constexpr int kLutLds = 1024;         // EDT row pass: surface tables up to this size sit in LDS
 
 struct LevelGeom {

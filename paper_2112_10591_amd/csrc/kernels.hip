@@ -62,13 +62,13 @@ __device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t G) {
 // its first LDS write, so U global loads per thread are in flight instead of
 // one (a load feeding an LDS store otherwise waits out the full memory
 // latency before the next load issues).
-template <int U, class T, class Src>
+template <int U, class T, class Src, int NT = kBlock>
 __device__ __forceinline__ void stage_window(T* __restrict__ dst, int w, int h, Src src, int pitch = 0) {
     const int n = w * h;
     if (pitch == 0) pitch = w;
     int r = threadIdx.x / w, cc = threadIdx.x - r * w;
-    const int dr = kBlock / w, dc = kBlock - dr * w;
-    for (int base = 0; base < n; base += U * kBlock) {
+    const int dr = NT / w, dc = NT - dr * w;
+    for (int base = 0; base < n; base += U * NT) {
         T v[U];
         int off[U];
 #pragma unroll
@@ -421,20 +421,35 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
             uint32_t best[NR];
 #pragma unroll
             for (int k = 0; k < NR; ++k) best[k] = k < nrows ? row[k * ww + x] : 0u;  // 0: nothing to search
+            // radii in steps of kRowUnroll, the loads of a step issued
+            // together; a radius past a row's stopping point only offers
+            // candidates >= r^2 >= its best (or >= the cap), which change
+            // neither D2 below the cap nor the surface
+            constexpr int U = kRowUnroll;
             int r = 1;
-            for (; r <= R; ++r) {
+            for (; r <= R; r += U) {
                 const uint32_t r2 = (uint32_t)(r * r);
-                const bool lft = x - r >= 0, rgt = x + r < W;
                 bool live = false;
 #pragma unroll
-                for (int k = 0; k < NR; ++k) {
-                    if (r2 < best[k] && r2 < cap) {
-                        live = true;
-                        if (lft) best[k] = min(best[k], r2 + row[k * ww + x - r]);
-                        if (rgt) best[k] = min(best[k], r2 + row[k * ww + x + r]);
+                for (int k = 0; k < NR; ++k) live |= r2 < best[k] && r2 < cap;
+                if (!live || (x - r < 0 && x + r >= W)) break;
+                uint32_t cl[U][NR], cr[U][NR];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int rr = r + u;
+                    const bool lft = x - rr >= 0, rgt = x + rr < W;
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        cl[u][k] = lft ? row[k * ww + x - rr] : 0x7fffffffu;
+                        cr[u][k] = rgt ? row[k * ww + x + rr] : 0x7fffffffu;
                     }
                 }
-                if (!live || (!lft && !rgt)) break;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t rr2 = (uint32_t)((r + u) * (r + u));
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) best[k] = min(best[k], rr2 + min(cl[u][k], cr[u][k]));
+                }
             }
             if (r > R) {  // beyond the staged columns
                 for (;; ++r) {
@@ -488,11 +503,12 @@ __device__ __forceinline__ int reflect101(int i, int n) {
 // part of every level.  Regions: R(deepest) = 8, R(k-1) = 2 R(k) + 3, origin
 // o(k-1) = 2 o(k) - 2.
 
+template <int NT>
 __device__ __forceinline__ void rc_init(int n, int& r, int& cc, int& dr, int& dc) {
     r = threadIdx.x / n;
     cc = threadIdx.x - r * n;
-    dr = kBlock / n;
-    dc = kBlock - dr * n;
+    dr = NT / n;
+    dc = NT - dr * n;
 }
 __device__ __forceinline__ void rc_step(int n, int& r, int& cc, int dr, int dc) {
     cc += dc;
@@ -504,8 +520,8 @@ __device__ __forceinline__ void rc_step(int n, int& r, int& cc, int dr, int dc) 
 }
 
 template <bool B>
-__global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const BatchArgs ba, int32_t total_arg,
-                                                      int from) {
+__global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, const BatchArgs ba, int32_t total_arg,
+                                                         int from) {
     // one array, three regions (85x85 | 41x41 | 19x19); offsets rather than
     // pointers keep every access in the LDS address space
     __shared__ float sP[85 * 85 + 41 * 41 + 19 * 19];
@@ -533,10 +549,11 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
             const LevelGeom g0 = d->lv[from];
             const float* __restrict__ src = d->pyr + g0.off;
             const int oxs = ox[0], oys = oy[0];
-            stage_window<16>(sP + buf[0], R[0], R[0], [&](int r, int cc) {
+            auto at = [&](int r, int cc) {
                 const int X = oxs + cc, Y = oys + r;
                 return (X >= 0 && X < g0.w && Y >= 0 && Y < g0.h) ? src[(size_t)Y * g0.w + X] : 0.f;
-            });
+            };
+            stage_window<8, float, decltype(at), kPyrBlock>(sP + buf[0], R[0], R[0], at);
         }
         __syncthreads();
         for (int k = 1; k <= nlev; ++k) {
@@ -548,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_pyr_chain(const WinDesc one, const B
             const int cx0 = span * tx, cy0 = span * ty;
             float* dst = d->pyr + gt.off;
             int r, cc, dr, dc;
-            rc_init(n, r, cc, dr, dc);
+            rc_init<kPyrBlock>(n, r, cc, dr, dc);
             for (; r < n; rc_step(n, r, cc, dr, dc)) {
                 const int X = ox[k] + cc, Y = oy[k] + r;
                 if (X < 0 || X >= gt.w || Y < 0 || Y >= gt.h) {
@@ -658,7 +675,7 @@ __device__ __forceinline__ float dens_weight_f(float dv) {
     return __builtin_amdgcn_rcpf(fmaxf(1.0f, 255.0f * fabsf(dv)));
 }
 
-constexpr int kCov = 3;       // patches covering a pixel per axis at stride >= 4
+constexpr int kDensChunk = 4;  // densification: covering patches loaded together
 constexpr int kDisRW = 192;   // LDS search region, columns
 constexpr int kDisRH = 40;    // LDS search region, rows
 constexpr int kDisRP = 41;    // ... stored column-major with this (odd) pitch
@@ -931,39 +948,31 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const Cover cx = cover_of(x, W, g.pnx, s, inv_s), cy = cover_of(y, H, g.pny, s, inv_s);
         const float i0 = I0[pix];
         float sw = 0.f, su = 0.f, sv = 0.f;
-        if (cx.n <= kCov && cy.n <= kCov) {
-            // all covering displacements, then all their samples, then the
-            // sums in the same (row-major) order as the general loop
-            double2 u[kCov * kCov];
+        // the covering patches in row-major order, kDensChunk at a time: their
+        // displacements, then their samples, are loaded before any is used
+        const int n = cx.n * cy.n;
+        int qx = 0, qy = 0;
+        for (int q0 = 0; q0 < n; q0 += kDensChunk) {
+            double2 u[kDensChunk];
+            DensTap tp[kDensChunk];
 #pragma unroll
-            for (int q = 0; q < kCov * kCov; ++q) {
-                const int qy = q / kCov, qx = q % kCov;
-                if (qy < cy.n && qx < cx.n)
-                    u[q] = pu[(size_t)cover_index(cy, qy) * g.pnx + cover_index(cx, qx)];
-            }
-            DensTap tp[kCov * kCov];
-#pragma unroll
-            for (int q = 0; q < kCov * kCov; ++q)
-                if (q / kCov < cy.n && q % kCov < cx.n) tp[q] = dens_fetch(I1, W, H, x, y, u[q].x, u[q].y);
-#pragma unroll
-            for (int q = 0; q < kCov * kCov; ++q) {
-                if (q / kCov < cy.n && q % kCov < cx.n) {
-                    const float w = dens_weight_f(dens_blend(tp[q], W, H, u[q].x, u[q].y) - i0);
-                    sw += w;
-                    su += w * (float)u[q].x;
-                    sv += w * (float)u[q].y;
+            for (int t = 0; t < kDensChunk; ++t) {
+                if (q0 + t < n) u[t] = pu[(size_t)cover_index(cy, qy) * g.pnx + cover_index(cx, qx)];
+                if (++qx == cx.n) {
+                    qx = 0;
+                    ++qy;
                 }
             }
-        } else {
-            for (int qy = 0; qy < cy.n; ++qy) {
-                const int ky = cover_index(cy, qy);
-                for (int qx = 0; qx < cx.n; ++qx) {
-                    const int kx = cover_index(cx, qx);
-                    const double2 u = pu[(size_t)ky * g.pnx + kx];
-                    const float w = dens_weight_f(dens_blend(dens_fetch(I1, W, H, x, y, u.x, u.y), W, H, u.x, u.y) - i0);
+#pragma unroll
+            for (int t = 0; t < kDensChunk; ++t)
+                if (q0 + t < n) tp[t] = dens_fetch(I1, W, H, x, y, u[t].x, u[t].y);
+#pragma unroll
+            for (int t = 0; t < kDensChunk; ++t) {
+                if (q0 + t < n) {
+                    const float w = dens_weight_f(dens_blend(tp[t], W, H, u[t].x, u[t].y) - i0);
                     sw += w;
-                    su += w * (float)u.x;
-                    sv += w * (float)u.y;
+                    su += w * (float)u[t].x;
+                    sv += w * (float)u[t].y;
                 }
             }
         }
@@ -1028,7 +1037,12 @@ void launch_edt_rows(const Launch& L, int rows_nr) {
         default: EBOF_LAUNCH_T(k_edt_rows, 4, L); break;
     }
 }
-void launch_pyr_chain(const Launch& L, int from) { EBOF_LAUNCH(k_pyr_chain, L, from); }
+void launch_pyr_chain(const Launch& L, int from) {
+    if (L.batch)
+        hipLaunchKernelGGL(k_pyr_chain<true>, dim3(L.grid), dim3(kPyrBlock), 0, L.stream, *L.one, L.ba, L.total, from);
+    else
+        hipLaunchKernelGGL(k_pyr_chain<false>, dim3(L.grid), dim3(kPyrBlock), 0, L.stream, *L.one, L.ba, L.total, from);
+}
 void launch_dis_level(const Launch& L, int level) { EBOF_LAUNCH(k_dis_level, L, level); }
 void launch_densify(const Launch& L, int tile_w) {
     switch (tile_w) {
