@@ -51,8 +51,8 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the reference kernel "
                          "for scaling HBM counters)")
-    ap.add_argument("--plain-streams", type=int, default=3,
-                    help="HIP streams the plain path is pipelined over (1 = strictly sequential)")
+    ap.add_argument("--plain-streams", type=int, default=2,
+                    help="flow streams of the pipelined plain path (preprocessing has its own stream)")
     return ap.parse_args()
 
 
@@ -177,18 +177,23 @@ def main():
     for ev in c2:
         evs.append(dict(x=torch.from_numpy(ev["x"]).to(dev), y=torch.from_numpy(ev["y"]).to(dev),
                         t=torch.from_numpy(ev["t"]).to(dev), t0=ev["t0"], n=len(ev["x"])))
-    # The plain path is the paper's pipeline (Fig. 1): one camera stream, one
-    # window per launch, stage calls only.  Window k's binning + EDT and the
-    # flow from window k-1 run on HIP stream k mod S; the flow waits for window
-    # k-1's pyramid (an event), and a window reusing a buffer waits for the
-    # flows that last read it, so consecutive windows overlap on the GPU as
-    # the paper's independent blocks do.  S = 1 is the strictly sequential form.
-    NS = max(1, args.plain_streams)
-    NB = NS + 2
+    # The plain path: one camera stream, one window per launch, stage calls
+    # only.  Sequential form: everything on one stream, one window at a time.
+    # Pipelined form, the paper's blocks (Fig. 1) as concurrent HIP streams:
+    # binning and EDT/surface/pyramid of every window on stream P, in window
+    # order; the flow k-1 -> k on stream F[k mod NF] after an event recorded
+    # on P behind window k (both pyramids it reads are then ready), so
+    # consecutive windows' flows overlap with each other and with the next
+    # windows' preprocessing.  Buffers form a ring of NB; a window reusing a
+    # buffer waits (on P) for the flows that last read it when the host sees
+    # they have not completed.  One host thread issues everything (the GPU,
+    # not the issue rate, bounds this form).
+    NF = max(1, args.plain_streams)
+    NB = 16
     pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(NB)]
     edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(NB)]
-    flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NS)]
-    streams = [stream] + [torch.cuda.Stream() for _ in range(NS - 1)]
+    flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NB)]
+    streams = [stream] + [torch.cuda.Stream() for _ in range(NF)]  # P, then the flow streams
     sptrs = [ctypes.c_void_p(st.cuda_stream) for st in streams]
     pp = ctypes.byref(p)
     vp = ctypes.c_void_p
@@ -201,37 +206,50 @@ def main():
     pyr_p = [vp(x.data_ptr()) for x in pyr]
     edge_p = [vp(x.data_ptr()) for x in edge]
     flow_p = [vp(x.data_ptr()) for x in flows]
-    ev_pre, ev_flow = {}, {}
-    flow = flows[0]
 
-    def step(k):
-        x, y, t, n, t0 = prepared[k % len(prepared)]
-        b, si = k % NB, k % NS
-        st = streams[si]
-        # buffer b was last read by the flows of steps k-NB (its pyramid as the
-        # current one) and k-NB+1 (pyramid and edge image as the previous ones)
-        for j in (k - NB, k - NB + 1):
-            if j in ev_flow:
-                st.wait_event(ev_flow[j])
-        ev_flow.pop(k - NB, None)
-        rc = lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[b], None, sptrs[si])
-        rc |= lib.ebof_edt_surface(h, pp, edge_p[b], None, pyr_p[b], sptrs[si])
-        ev_pre[k] = torch.cuda.Event()
-        ev_pre[k].record(st)
-        prev = ev_pre.pop(k - 1, None)
-        if k > 0:
-            if prev is not None:
-                st.wait_event(prev)
-            bp = (k - 1) % NB
-            rc |= lib.ebof_flow(h, pp, pyr_p[bp], pyr_p[b], edge_p[bp], flow_p[si], sptrs[si])
-            ev_flow[k] = torch.cuda.Event()
-            ev_flow[k].record(st)
+    def check(rc):
         if rc:
             raise RuntimeError(lib.ebof_last_error(h).decode())
+
+    def preprocess(k, si):
+        x, y, t, n, t0 = prepared[k % len(prepared)]
+        b = k % NB
+        check(lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[b], None, sptrs[si]))
+        check(lib.ebof_edt_surface(h, pp, edge_p[b], None, pyr_p[b], sptrs[si]))
+
+    def flow_of(k, si):
+        b, bp = k % NB, (k - 1) % NB
+        check(lib.ebof_flow(h, pp, pyr_p[bp], pyr_p[b], edge_p[bp], flow_p[b], sptrs[si]))
+
+    def step(k):  # sequential form
+        preprocess(k, 0)
+        if k > 0:
+            flow_of(k, 0)
 
     def sync_all():
         for st in streams:
             st.synchronize()
+
+    def run_pipelined(k_lo, k_hi):
+        """Windows k_lo .. k_hi-1 in the pipelined form (work issued before
+        k_lo must be complete)."""
+        ev_pre = [torch.cuda.Event() for _ in range(k_hi - k_lo)]
+        ev_flow = {}
+        sp = streams[0]
+        for k in range(k_lo, k_hi):
+            for j in (k - NB, k - NB + 1):  # the flows that last read buffer k % NB
+                e = ev_flow.pop(j, None) if j == k - NB else ev_flow.get(j)
+                if e is not None and not e.query():
+                    sp.wait_event(e)
+            preprocess(k, 0)
+            if k > 0:
+                e = ev_pre[k - k_lo]
+                e.record(sp)
+                sf = streams[1 + k % NF]
+                sf.wait_event(e)
+                flow_of(k, 1 + k % NF)
+                ev_flow[k] = torch.cuda.Event()
+                ev_flow[k].record(sf)
 
     # ---------------- EPE against the oracle on the sampled pairs ----------
     epe = None
@@ -242,7 +260,7 @@ def main():
                 step(k)
                 if k in oracle_flows:
                     sync_all()
-                    g = flows[k % NS].cpu().numpy().reshape(2, H, W).astype(np.float64)
+                    g = flows[k % NB].cpu().numpy().reshape(2, H, W).astype(np.float64)
                     r, m = oracle_flows[k]
                     errs.append(np.hypot(g[0] - r[0], g[1] - r[1])[m].mean())
         epe = float(np.mean(errs))
@@ -250,12 +268,9 @@ def main():
 
     # ---------------- per-kernel breakdown (warm-up, all kernels timed) ----
     lib.ebof_timing_enable(h, (1 << len(L.KERNELS)) - 1)
-    NS_run = NS
-    NS = 1  # breakdown on the sequential form: kernel times do not overlap
-    for k in range(Wm):
+    for k in range(Wm):  # the sequential form: kernel times do not overlap
         step(k)
     sync_all()
-    NS = NS_run
     breakdown = {}
     for name in L.KERNELS:
         ms, cnt = L.ebof_timing_read(ctx, name)
@@ -266,11 +281,9 @@ def main():
 
     # ---------------- timed regions: plain path ----------------------------
     # (1) the strictly sequential form, one stream, with the dominant kernel
-    # timed by HIP events around each of its launches (kernel times do not
-    # overlap here, so they are the kernel's own); (2) the pipelined form over
-    # NS streams, untimed per kernel, which gives the headline rate.
-    NS_run = NS
-    NS = 1
+    # timed by HIP events around its launches (kernel times do not overlap
+    # here, so they are the kernel's own); (2) the pipelined form, untimed per
+    # kernel, which gives the headline rate.
     lib.ebof_timing_enable(h, 1 << L.KERNELS.index(dominant))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -282,29 +295,26 @@ def main():
     dom_ms, dom_cnt = L.ebof_timing_read(ctx, dominant)
     lib.ebof_timing_enable(h, 0)
     log(f"plain (1 stream): {fps_seq:.1f} frames/s ({1e3 / fps_seq:.4f} ms/window)")
-    NS = NS_run
-    fps = fps_seq
-    if NS > 1:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(Wm + K, Wm + 2 * K):
-            step(k)
-        sync_all()
-        torch.cuda.synchronize()
-        fps = K / (time.perf_counter() - t0)
-        log(f"plain ({NS} streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window)")
+    run_pipelined(Wm + K, Wm + K + 4 * NF)  # untimed: streams warm
+    sync_all()
+    k0 = Wm + K + 4 * NF
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_pipelined(k0, k0 + K)
+    sync_all()
+    torch.cuda.synchronize()
+    fps = K / (time.perf_counter() - t0)
+    log(f"plain (pipelined, {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window)")
     elapsed = K / fps
 
     # ---------------- unloaded per-window latency (plain) -------------------
-    NS = 1
     lat = []
-    for k in range(Wm + 2 * K, Wm + 2 * K + 100):
+    for k in range(k0 + K, k0 + K + 100):
         s0 = time.perf_counter()
         step(k)
         sync_all()
         lat.append((time.perf_counter() - s0) * 1e3)
     lat = np.array(lat)
-    NS = NS_run
 
     # ---------------- roofline of the dominant kernel -----------------------
     # The library brackets each run of consecutive launches of the kernel
@@ -364,7 +374,7 @@ def main():
                    "levels": p.levels},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
-        "plain_streams": NS,
+        "plain_flow_streams": NF,
         "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
         "kernels_ms_per_window": {k: v["ms_per_window"] for k, v in breakdown.items()},

@@ -124,8 +124,10 @@ const char *ebof_last_error(const ebof_ctx *ctx);
 
 /* ---- stage calls (one window, caller's stream) --------------------------
  * The context keeps one scratch per parameter set and HIP stream (held until
- * ebof_destroy): calls on different streams may run concurrently, calls on
- * one stream are ordered by it.  Only the caller's own buffers carry data
+ * ebof_destroy): calls on different streams may run concurrently, also from
+ * different host threads (the context's lock covers only its bookkeeping,
+ * not the launches); calls on one stream are ordered by it and must be made
+ * in that order.  Only the caller's own buffers carry data
  * from one call to the next (edge image, pyramid), so a window's stages may
  * run on one stream and the flow that reads its pyramid on another, ordered
  * by a HIP event. */

@@ -237,23 +237,27 @@ static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int*
 // ---------------------------------------------------------------- timing
 template <class F>
 static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f, int launches = 1) {
-    if (!(ctx->timing_mask & (1u << kid))) {
+    if (!(ctx->timing_mask.load(std::memory_order_relaxed) & (1u << kid))) {
         f();
         return;
     }
     TimedPair tp;
     tp.launches = launches;
-    for (hipEvent_t* e : {&tp.a, &tp.b}) {
-        if (!ctx->event_pool.empty()) {
-            *e = ctx->event_pool.back();
-            ctx->event_pool.pop_back();
-        } else {
-            (void)hipEventCreate(e);
+    {
+        std::lock_guard<std::mutex> lk(ctx->timing_mu);
+        for (hipEvent_t* e : {&tp.a, &tp.b}) {
+            if (!ctx->event_pool.empty()) {
+                *e = ctx->event_pool.back();
+                ctx->event_pool.pop_back();
+            } else {
+                (void)hipEventCreate(e);
+            }
         }
     }
     (void)hipEventRecord(tp.a, st);
     f();
     (void)hipEventRecord(tp.b, st);
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
     ctx->timed[kid].push_back(tp);
 }
 
@@ -835,27 +839,33 @@ int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
         set_error("ebof_bin_events: t0 + dt overflows");
         return EBOF_E_INVAL;
     }
-    std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const Geom g = make_geom(*p);
-    Scratch* s = stage_scratch(ctx, g, st, &rc);
-    if (!s) return rc;
+    Scratch scr;
+    uint32_t stamp;
+    bool zero;
+    {  // the lock covers the context's maps; launches run outside it
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Scratch* s = stage_scratch(ctx, g, st, &rc);
+        if (!s) return rc;
+        stamp = s->next_stamp();
+        zero = s->needs_zero;
+        s->needs_zero = false;
+        scr = *s;
+    }
     Lut lut{p->alpha, 0, nullptr};
     WinDesc d;
-    fill_desc(*p, g, lut, *s, &d);
+    fill_desc(*p, g, lut, scr, &d);
     d.ex = x;
     d.ey = y;
     d.et = t;
     d.n_ev = n;
     d.t0 = t0_us;
     d.t1 = t0_us + p->dt_us;
-    d.stamp = s->next_stamp();
+    d.stamp = stamp;
     d.e_df = edge_out;
     d.n_dropped = (unsigned long long*)n_dropped_dev;
-    if (s->needs_zero) {
-        launch_zero(one_launch(&d, stage_items(d, kStZero, false, true, kStageTune), st));
-        s->needs_zero = false;
-    }
+    if (zero) launch_zero(one_launch(&d, stage_items(d, kStZero, false, true, kStageTune), st));
     if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_DENOISE_FILL, st,
           [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false, kStageTune), st), false); });
@@ -871,15 +881,19 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
         set_error("ebof_edt_surface: NULL edge or pyr_out");
         return EBOF_E_INVAL;
     }
-    std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const Geom g = make_geom(*p);
-    Scratch* s = stage_scratch(ctx, g, st, &rc);
-    if (!s) return rc;
+    Scratch scr;
     Lut lut;
-    if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Scratch* s = stage_scratch(ctx, g, st, &rc);
+        if (!s) return rc;
+        if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+        scr = *s;
+    }
     WinDesc d;
-    fill_desc(*p, g, lut, *s, &d);
+    fill_desc(*p, g, lut, scr, &d);
     d.e_df = const_cast<uint8_t*>(edge);  // read only by these kernels
     d.d2 = d2_out;
     d.pyr = pyr_out;
@@ -908,14 +922,18 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
         set_error("ebof_flow: NULL pyramid or flow_out");
         return EBOF_E_INVAL;
     }
-    std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const Geom g = make_geom(*p);
-    Scratch* s = stage_scratch(ctx, g, st, &rc);
-    if (!s) return rc;
+    Scratch scr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Scratch* s = stage_scratch(ctx, g, st, &rc);
+        if (!s) return rc;
+        scr = *s;
+    }
     Lut lut{p->alpha, 0, nullptr};
     WinDesc d;
-    fill_desc(*p, g, lut, *s, &d);
+    fill_desc(*p, g, lut, scr, &d);
     d.pyr = const_cast<float*>(pyr_curr);  // read only by these kernels
     d.pyr_prev = pyr_prev;
     d.mask = mask;
@@ -991,20 +1009,28 @@ int ebof_timing_read(ebof_ctx* ctx, int32_t kernel_id, double* total_ms, int64_t
         set_error("ebof_timing_read: bad kernel id or NULL output");
         return EBOF_E_INVAL;
     }
+    std::vector<TimedPair> pairs;
+    {
+        std::lock_guard<std::mutex> lk(ctx->timing_mu);
+        pairs.swap(ctx->timed[kernel_id]);
+    }
     double tot = 0.0;
     int64_t cnt = 0;
-    for (auto& tp : ctx->timed[kernel_id]) {
-        rc = check_hip(ctx, hipEventSynchronize(tp.b), "hipEventSynchronize");
-        if (rc) return rc;
+    for (auto& tp : pairs) {
+        if (!rc) rc = check_hip(ctx, hipEventSynchronize(tp.b), "hipEventSynchronize");
         float ms = 0.f;
-        rc = check_hip(ctx, hipEventElapsedTime(&ms, tp.a, tp.b), "hipEventElapsedTime");
-        if (rc) return rc;
+        if (!rc) rc = check_hip(ctx, hipEventElapsedTime(&ms, tp.a, tp.b), "hipEventElapsedTime");
         tot += ms;
         cnt += tp.launches;
-        ctx->event_pool.push_back(tp.a);
-        ctx->event_pool.push_back(tp.b);
     }
-    ctx->timed[kernel_id].clear();
+    {
+        std::lock_guard<std::mutex> lk(ctx->timing_mu);
+        for (auto& tp : pairs) {
+            ctx->event_pool.push_back(tp.a);
+            ctx->event_pool.push_back(tp.b);
+        }
+    }
+    if (rc) return rc;
     *total_ms = tot;
     *launches = cnt;
     return EBOF_OK;

@@ -109,7 +109,8 @@ struct ebof_ctx {
     std::string tune_path;           // cache file of tuned shapes ("" = none)
 
     // timing
-    uint32_t timing_mask = 0;
+    std::atomic<uint32_t> timing_mask{0};
+    std::mutex timing_mu;  // guards timed[] and event_pool (launches happen outside mu)
     std::vector<ebof::TimedPair> timed[EBOF_K_COUNT];
     std::vector<hipEvent_t> event_pool;
 

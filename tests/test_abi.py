@@ -72,3 +72,4 @@ def test_stage_calls_reject_null_context():
 def test_set_tuning_rejects_null_context():
     lib = L.load()
     assert lib.ebof_set_tuning(None, L.EBOF_TUNE_AUTO, None) == L.EBOF_E_INVAL
+
