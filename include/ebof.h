@@ -205,17 +205,20 @@ int ebof_run_batch(ebof_ctx *ctx, const ebof_window *w, int32_t n,
 /* ---- launch-shape tuning (batched form) ----------------------------------
  * The batched runner times candidate launch shapes the first time it sees a
  * batch layout and keeps the fastest: the block count of each stage's
- * launch, the rows per item of the EDT row pass (1, 2, 4, 8) and the tile
- * width of the densification (64, 128, 256 pixels).  No candidate changes
- * any window's results.  Timing a new layout synchronises the stream and
+ * launch, the rows per item of the EDT row pass (1, 2, 4, 8), the tile width
+ * of the densification (64, 128, 256 pixels) and, per pyramid level, the
+ * lanes per patch of the inverse search (8 or 4).  No candidate changes any
+ * window's results.  Timing a new layout synchronises the stream and
  * runs each stage a few times (milliseconds, once per layout).
  * mode: EBOF_TUNE_AUTO (the default) or EBOF_TUNE_OFF (default shapes for
  * layouts not tuned yet).  cache_path: NULL, or a text file from which tuned
  * layouts are read now and to which newly tuned ones are appended, one line
- * per layout: "<layout>\t<rows> <tile_w> <g_0> ... <g_21>", where <layout>
+ * per layout: "<layout>\t<rows> <tile_w> <l_0> ... <l_7> <g_0> ... <g_21>",
+ * where <layout>
  * is "W,H,levels,stride,flow,first;" for each window in batch order (flow: 1
  * when the window computes flow; first: 1 for a served stream's first
- * window) and g_s is the block count of internal stage s (0: default).
+ * window), l_k the lanes per patch at level k (0: by the level's size) and
+ * g_s the block count of internal stage s (0: default).
  * Serving launches keep the default shapes.  Returns EBOF_E_INVAL for a bad
  * mode or a malformed cache line (nothing is changed then).  Captured
  * graphs are released. */

@@ -29,6 +29,7 @@ EBOF_CHAIN_ALWAYS = 2
 EBOF_MAX_BATCH = 1024
 EBOF_TUNE_OFF = 0
 EBOF_TUNE_AUTO = 1
+EBOF_TUNE_LEVELS = 8   # lanes-per-patch values per cache line (one per level)
 EBOF_TUNE_STAGES = 22  # block counts per cache line (one per internal stage)
 
 KERNELS = ["scatter", "denoise_fill", "pack_cols", "edt_cols", "edt_rows", "pyr_down",

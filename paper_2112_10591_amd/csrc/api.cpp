@@ -393,7 +393,7 @@ static void launch_stage(const Launch& L, int s, const Tune& t) {
     else if (s >= kStPyr && s < kStDis)
         launch_pyr_chain(L, (s - kStPyr) * kPyrChain);
     else if (s >= kStDis && s < kStDensify)
-        launch_dis_level(L, s - kStDis);
+        launch_dis_level(L, s - kStDis, t.dis_lanes[s - kStDis]);
     else
         launch_densify(L, t.dens_tw);
 }
@@ -461,6 +461,7 @@ static int autotune(ebof_ctx* ctx, BatchRunner& br, const std::vector<WinDesc>& 
     std::vector<WinDesc> td = descs;
     for (auto& d : td) d.n_dropped = nullptr;
     Tune best;
+    resolve_dis_lanes(best, td.data(), (int)td.size());
     std::vector<int32_t> prefix;
     int32_t totals[kNumStages];
     int rc;
@@ -503,15 +504,18 @@ static int autotune(ebof_ctx* ctx, BatchRunner& br, const std::vector<WinDesc>& 
     for (int s : pipeline_order(lmax)) {
         if (rc) break;
         if (s == kStZero) continue;
+        const bool dis = s >= kStDis && s < kStDensify;
         std::vector<int> shapes{0};
         if (s == kStRows) shapes = {1, 2, 4, 8};
         if (s == kStDensify) shapes = {64, 128, 256};
+        if (dis) shapes = {8, 4};
         float best_ms = -1.f;
         Tune win = best;
         for (int shape : shapes) {
             Tune t = best;
             if (s == kStRows) t.rows_nr = shape;
             if (s == kStDensify) t.dens_tw = shape;
+            if (dis) t.dis_lanes[s - kStDis] = shape;
             if ((rc = build_prefix(td, flow, zero, t, &prefix, totals))) break;
             for (int32_t g : kGrids) {
                 if (g == 0 && s == kStScatter) continue;  // its item count varies: a fixed grid
@@ -541,6 +545,7 @@ static void save_tune(ebof_ctx* ctx, const std::string& key, const Tune& t) {
     FILE* f = std::fopen(ctx->tune_path.c_str(), "a");
     if (!f) return;
     std::fprintf(f, "%s\t%d %d", key.c_str(), t.rows_nr, t.dens_tw);
+    for (int l = 0; l < kMaxLevels; ++l) std::fprintf(f, " %d", t.dis_lanes[l]);
     for (int s = 0; s < kNumStages; ++s) std::fprintf(f, " %d", t.grid[s]);
     std::fprintf(f, "\n");
     std::fclose(f);
@@ -559,11 +564,12 @@ static int load_tunes(const char* path, std::map<std::string, Tune>* out) {
         if (l.find_first_not_of(" \r\n") == std::string::npos) continue;
         std::vector<int> v;
         Tune t;
-        bool ok = parse_tune_line(l, 2 + kNumStages, &key, &v);
+        bool ok = parse_tune_line(l, 2 + kMaxLevels + kNumStages, &key, &v);
         if (ok) {
             t.rows_nr = v[0];
             t.dens_tw = v[1];
-            for (int s = 0; s < kNumStages; ++s) t.grid[s] = v[2 + s];
+            for (int lv = 0; lv < kMaxLevels; ++lv) t.dis_lanes[lv] = v[2 + lv];
+            for (int s = 0; s < kNumStages; ++s) t.grid[s] = v[2 + kMaxLevels + s];
             ok = tune_valid(t);
         }
         if (!ok) {
@@ -665,6 +671,7 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
             }
         }
     }
+    resolve_dis_lanes(tune, descs.data(), n);
     std::vector<int32_t> prefix;
     int32_t totals[kNumStages];
     if ((rc = build_prefix(descs, flow, zero, tune, &prefix, totals))) return rc;
@@ -938,11 +945,14 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
     d.pyr_prev = pyr_prev;
     d.mask = mask;
     d.flow = flow_out;
+    Tune tune = kStageTune;
+    resolve_dis_lanes(tune, &d, 1);
     timed(
         ctx, EBOF_K_DIS_LEVEL, st,
         [&] {
             for (int l = p->levels - 1; l >= 0; --l)
-                launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, kStageTune), st), l);
+                launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l,
+                                 tune.dis_lanes[l]);
         },
         p->levels);
     timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw); });

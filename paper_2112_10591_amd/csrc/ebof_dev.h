@@ -118,14 +118,31 @@ struct Launch {
 struct Tune {
     int32_t rows_nr = 4;    // k_edt_rows: rows per item (1, 2, 4 or 8)
     int32_t dens_tw = 64;   // k_densify: tile width (64, 128 or 256), kBlock / dens_tw rows
-    int32_t grid[kNumStages] = {};  // batched launch blocks per stage (0: the default)
+    int32_t dis_lanes[kMaxLevels] = {};  // k_dis_level: lanes per patch (8 or 4; 0: by size)
+    int32_t grid[kNumStages] = {};       // batched launch blocks per stage (0: the default)
 };
 inline bool tune_valid(const Tune& t) {
     const bool nr = t.rows_nr == 1 || t.rows_nr == 2 || t.rows_nr == 4 || t.rows_nr == 8;
     const bool tw = t.dens_tw == 64 || t.dens_tw == 128 || t.dens_tw == 256;
+    for (int l = 0; l < kMaxLevels; ++l)
+        if (t.dis_lanes[l] != 0 && t.dis_lanes[l] != 4 && t.dis_lanes[l] != 8) return false;
     for (int s = 0; s < kNumStages; ++s)
         if (t.grid[s] < 0 || t.grid[s] > (1 << 20)) return false;
     return nr && tw;
+}
+// A level with at least this many patches in one launch uses 4 lanes per
+// patch by default (throughput), a smaller one 8 (latency).
+constexpr int64_t kDisWideMinPatches = 16384;
+// Resolves dis_lanes left at 0 from the level's patch count over the windows
+// (one launch per level serves them all, so one choice per level).
+inline void resolve_dis_lanes(Tune& t, const WinDesc* d, int n) {
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (t.dis_lanes[l]) continue;
+        int64_t patches = 0;
+        for (int i = 0; i < n; ++i)
+            if (l < d[i].L) patches += (int64_t)d[i].lv[l].pnx * d[i].lv[l].pny;
+        t.dis_lanes[l] = patches >= kDisWideMinPatches ? 4 : 8;
+    }
 }
 
 // Work items of one stage for one window (0 when the stage does not apply).
@@ -141,7 +158,7 @@ void launch_pack_cols(const Launch& L);
 void launch_edt_cols(const Launch& L);
 void launch_edt_rows(const Launch& L, int rows_nr);
 void launch_pyr_chain(const Launch& L, int from);
-void launch_dis_level(const Launch& L, int level);
+void launch_dis_level(const Launch& L, int level, int lanes);
 void launch_densify(const Launch& L, int tile_w);
 
 }  // namespace ebof

@@ -614,23 +614,9 @@ __device__ __forceinline__ double dppd(double v) {
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double red8d(double v) {
-    v += dppd<0xB1>(v);
-    v += dppd<0x4E>(v);
-    v += dppd<0x141>(v);
-    return v;
-}
 template <int CTRL>
 __device__ __forceinline__ float dppf(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-// sum over the 8 lanes of a patch (quad swap pairs, quad swap halves, then
-// mirror within the half row), result in every lane
-__device__ __forceinline__ float red8f(float v) {
-    v += dppf<0xB1>(v);
-    v += dppf<0x4E>(v);
-    v += dppf<0x141>(v);
-    return v;
 }
 
 // Densification samples, single precision.  The sample position x + u is
@@ -707,74 +693,133 @@ __device__ __forceinline__ void stage_rows_cols(float* __restrict__ dst, const f
     }
 }
 
-// One level.  Work item = 32 consecutive patches of one patch row (4 waves x
-// 8 patches); the 8 lanes of a patch each own one patch column.  The
-// reference strip (rows oy-1 .. oy+8) is staged in LDS for the template and
-// its gradient; then the region of I1 covering every patch's search window
-// at its initial displacement (plus a margin) is staged, and the iterations
-// read it there (a patch whose window leaves the region reads global memory;
-// both give the same clamped samples).
-template <bool B>
+// sums over the LP lanes of a patch (LP = 8: quad swaps then the half-row
+// mirror; LP = 4: the two quad swaps), result in every lane
+template <int LP>
+__device__ __forceinline__ float redf(float v) {
+    v += dppf<0xB1>(v);
+    v += dppf<0x4E>(v);
+    if constexpr (LP == 8) v += dppf<0x141>(v);
+    return v;
+}
+template <int LP>
+__device__ __forceinline__ double redd(double v) {
+    v += dppd<0xB1>(v);
+    v += dppd<0x4E>(v);
+    if constexpr (LP == 8) v += dppd<0x141>(v);
+    return v;
+}
+
+// One level.  LP lanes per patch, each owning 8/LP patch columns (LP = 8:
+// one column per lane, the shortest dependent chain per iteration, for small
+// levels; LP = 4: two columns per lane, the sample column between them read
+// once and the per-iteration coordinate, reduction and update work shared by
+// twice the pixels, for large levels).  Work item = 32 consecutive patches
+// of 8/LP patch rows (256 lanes).  The reference strip (rows oy-1 .. oy+8 of
+// every patch row of the item) is staged in LDS for the template and its
+// gradient; then the region of I1 covering every patch's search window at
+// its initial displacement (plus a margin) is staged, column-major, and the
+// iterations read it there (a patch whose window leaves the region reads
+// global memory; both give the same clamped samples).
+template <bool B, int LP>
 __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                       int level) {
+    constexpr int CPL = kPatch / LP;            // patch columns per lane
+    constexpr int PR = 8 / LP;                  // patch rows per item
+    constexpr int WPR = (kBlock / 64) / PR;     // waves per patch row
+    constexpr int PPW = 64 / LP;                // patches per wave
+    static_assert(WPR * PPW == kPatchesPerItem, "an item row holds kPatchesPerItem patches");
     __shared__ float sR[kDisRW * kDisRP];
     __shared__ int sBox[4];
     const int32_t total = item_total<B>(ba, total_arg);
-    const int lane = threadIdx.x & 63;
-    const int slot = (threadIdx.x >> 6) * 8 + (lane >> 3);
-    const int c = lane & 7;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int prow = wave / WPR;                      // patch row within the item
+    const int slot = (wave % WPR) * PPW + lane / LP;  // patch within the row segment
+    const int cg = lane % LP;                         // the lane's column group
     for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const LevelGeom g = d->lv[level];
-        const int Wl = g.w, Hl = g.h, pnx = g.pnx;
+        const int Wl = g.w, Hl = g.h, pnx = g.pnx, pny = g.pny;
         const int nseg = (pnx + kPatchesPerItem - 1) / kPatchesPerItem;
-        const int ky = local / nseg, seg = local - (local / nseg) * nseg;
+        const int kyi = local / nseg, seg = local - (local / nseg) * nseg;
         const int s = d->stride;
         const double lam = (double)d->lambda;
         const float* __restrict__ I0 = d->pyr_prev + g.off;
         const float* __restrict__ I1 = d->pyr + g.off;
+        const int ky0 = kyi * PR, ky_last = min(ky0 + PR, pny) - 1;
         const int kx0 = seg * kPatchesPerItem;
         const int kx_last = min(kx0 + kPatchesPerItem, pnx) - 1;
-        const int kx = kx0 + slot;
-        const bool valid = kx < pnx;
-        const int kxc = valid ? kx : kx_last;
-        const int ox = min(kxc * s, Wl - kPatch), oy = min(ky * s, Hl - kPatch);
-        const int x = ox + c;
+        const int ky = ky0 + prow, kx = kx0 + slot;
+        const bool valid = kx < pnx && ky < pny;
+        const int kxc = min(kx, kx_last), kyc = min(ky, ky_last);
+        const int ox = min(kxc * s, Wl - kPatch), oy = min(kyc * s, Hl - kPatch);
+        const int x = ox + cg * CPL;  // the lane's first column
 
         // ---- template and gradient from the staged reference strip
+        const int oyA = min(ky0 * s, Hl - kPatch), oyB = min(ky_last * s, Hl - kPatch);
+        const int sh = oyB - oyA + kPatch + 2;
         const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
         const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
-        stage_rows_cols<(kPatch + 2 + 3) / 4>(sR, I0, Wl, Hl, sx0, oy - 1, sw, kPatch + 2, 1, sw);
+        stage_rows_cols<(kPatch + 2 + kPatch * (PR - 1) + 3) / 4>(sR, I0, Wl, Hl, sx0, oyA - 1, sw, sh, 1, sw);
         __syncthreads();
         // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
         // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
         // the patch, and the bilinear sample of row j as h_j + ay (h_{j+1} -
         // h_j) (h = the row interpolated along x), so that per lane
         // sum_j g_j I1 = P + ay (Q - P), P = sum_j g_j h_j, Q = sum_j g_j h_{j+1}.
-        double gxs[kPatch], gys[kPatch];
-        float tf[kPatch];
+        // Every sum over the patch is formed per patch column (rows in order),
+        // then the columns are added as a binary tree (a lane's two columns
+        // first, then the lanes by DPP), so both lane counts give the same
+        // bits and the launch shape never changes a result.
+        float fgx[CPL][kPatch], fgy[CPL][kPatch], tf[CPL][kPatch];
         double hxx = 0.0, hxy = 0.0, hyy = 0.0;
         {
-            const float* col = sR + sw + (x - sx0);
+            const float* base = sR + (oy - oyA + 1) * sw + (x - sx0);
 #pragma unroll
-            for (int j = 0; j < kPatch; ++j) {
-                const float* q = col + j * sw;
-                tf[j] = q[0];
-                gxs[j] = 0.5 * ((double)q[1] - (double)q[-1]);
-                gys[j] = 0.5 * ((double)q[sw] - (double)q[-sw]);
-                hxx += gxs[j] * gxs[j];
-                hxy += gxs[j] * gys[j];
-                hyy += gys[j] * gys[j];
+            for (int c = 0; c < CPL; ++c) {
+                double sxx = 0.0, sxy = 0.0, syy = 0.0;
+#pragma unroll
+                for (int j = 0; j < kPatch; ++j) {
+                    const float* q = base + j * sw + c;
+                    tf[c][j] = q[0];
+                    const double gx = 0.5 * ((double)q[1] - (double)q[-1]);
+                    const double gy = 0.5 * ((double)q[sw] - (double)q[-sw]);
+                    sxx += gx * gx;
+                    sxy += gx * gy;
+                    syy += gy * gy;
+                    fgx[c][j] = (float)gx;
+                    fgy[c][j] = (float)gy;
+                }
+                hxx = c ? hxx + sxx : sxx;
+                hxy = c ? hxy + sxy : sxy;
+                hyy = c ? hyy + syy : syy;
             }
         }
-        hxx = red8d(hxx);
-        hxy = red8d(hxy);
-        hyy = red8d(hyy);
+        hxx = redd<LP>(hxx);
+        hxy = redd<LP>(hxy);
+        hyy = redd<LP>(hyy);
         const double ha = hxx + lam, hc = hyy + lam;
         const double det = ha * hc - hxy * hxy;
         const double idet = 1.0 / det;
-        const double ia = hc * idet, ib = -hxy * idet, ic = ha * idet;
+        const float fia = (float)(hc * idet), fib = (float)(-hxy * idet), fic = (float)(ha * idet);
+        // c by the same single-precision chain, in the same order, as P at
+        // u = 0: where I1 equals the template the residual is exactly 0, so
+        // a patch that does not move stays exactly in place
+        float fcx = 0.f, fcy = 0.f;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            float cx_ = 0.f, cy_ = 0.f;
+#pragma unroll
+            for (int j = 0; j < kPatch; ++j) {
+                cx_ += fgx[c][j] * tf[c][j];
+                cy_ += fgy[c][j] * tf[c][j];
+            }
+            fcx = c ? fcx + cx_ : cx_;
+            fcy = c ? fcy + cy_ : cy_;
+        }
+        fcx = redf<LP>(fcx);
+        fcy = redf<LP>(fcy);
 
         // ---- initial displacement: twice the coarser dense flow at the
         // pixel nearest the patch centre (densified there from the coarser
@@ -789,9 +834,11 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
             const float inv_s = 1.0f / (float)s;
             const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
+            // as in the densification; every lane sums all covering patches
+            // in order (the same bits whatever the lane count)
             const float i0 = C0[(size_t)py * gc.w + px];
-            float sw_ = 0.f, su = 0.f, sv = 0.f;  // as in the densification
-            for (int q = c; q < cx.n * cy.n; q += 8) {
+            float sw_ = 0.f, su = 0.f, sv = 0.f;
+            for (int q = 0; q < cx.n * cy.n; ++q) {
                 const int qx = cover_index(cx, q % cx.n), qy = cover_index(cy, q / cx.n);
                 const double2 u = cu[(size_t)qy * gc.pnx + qx];
                 const float w =
@@ -800,9 +847,6 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
                 su += w * (float)u.x;
                 sv += w * (float)u.y;
             }
-            sw_ = red8f(sw_);
-            su = red8f(su);
-            sv = red8f(sv);
             u0x = 2.0 * (double)(su / sw_);
             u0y = 2.0 * (double)(sv / sw_);
         }
@@ -816,7 +860,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             sBox[3] = INT32_MIN;
         }
         __syncthreads();  // also ends the reads of the reference strip
-        if (valid && c == 0) {
+        if (valid && cg == 0) {
             const int wx = ox + (int)floor(fmin(fmax(u0x, -lim), lim));
             const int wy = oy + (int)floor(fmin(fmax(u0y, -lim), lim));
             atomicMin(&sBox[0], wx);
@@ -833,26 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         stage_rows_cols<kDisRH / 4>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP, 1);
         __syncthreads();
 
-        // ---- inverse-compositional iterations
         // ---- inverse-compositional iterations (single precision)
-        float fgx[kPatch], fgy[kPatch];
-#pragma unroll
-        for (int j = 0; j < kPatch; ++j) {
-            fgx[j] = (float)gxs[j];
-            fgy[j] = (float)gys[j];
-        }
-        const float fia = (float)ia, fib = (float)ib, fic = (float)ic;
-        // c by the same single-precision chain, in the same order, as P at
-        // u = 0: where I1 equals the template the residual is exactly 0, so
-        // a patch that does not move stays exactly in place
-        float fcx = 0.f, fcy = 0.f;
-#pragma unroll
-        for (int j = 0; j < kPatch; ++j) {
-            fcx += fgx[j] * tf[j];
-            fcy += fgy[j] * tf[j];
-        }
-        fcx = red8f(fcx);
-        fcy = red8f(fcy);
         const float flim = (float)lim;
         float ux = (float)u0x, uy = (float)u0y;
         const int iters = d->iters;
@@ -862,41 +887,62 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const float ax = sxu - fx, ay = syu - fy;
             const int ix = (int)fx, iy = (int)fy;
             const int rx = x + ix - RX0, ry = oy + iy - RY0;
-            float px = 0.f, qx = 0.f, py = 0.f, qy = 0.f;
-            if ((unsigned)rx < (unsigned)(RW - 1) && (unsigned)ry < (unsigned)(RH - kPatch)) {
+            float px[CPL], qx[CPL], py[CPL], qy[CPL];  // per patch column
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) px[c] = qx[c] = py[c] = qy[c] = 0.f;
+            if ((unsigned)rx < (unsigned)(RW - CPL) && (unsigned)ry < (unsigned)(RH - kPatch)) {
                 const float* q = sR + rx * kDisRP + ry;
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
-                    const float A = q[j], Bv = q[kDisRP + j];
-                    const float h = A + ax * (Bv - A);
-                    if (j < kPatch) {
-                        px += fgx[j] * h;
-                        py += fgy[j] * h;
-                    }
-                    if (j > 0) {
-                        qx += fgx[j - 1] * h;
-                        qy += fgy[j - 1] * h;
+                    float a[CPL + 1];
+#pragma unroll
+                    for (int c = 0; c <= CPL; ++c) a[c] = q[c * kDisRP + j];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float h = a[c] + ax * (a[c + 1] - a[c]);
+                        if (j < kPatch) {
+                            px[c] += fgx[c][j] * h;
+                            py[c] += fgy[c][j] * h;
+                        }
+                        if (j > 0) {
+                            qx[c] += fgx[c][j - 1] * h;
+                            qy[c] += fgy[c][j - 1] * h;
+                        }
                     }
                 }
             } else {
-                const int xa = clampi(x + ix, 0, Wl - 1), xb = clampi(x + ix + 1, 0, Wl - 1);
+                int xs[CPL + 1];
+#pragma unroll
+                for (int c = 0; c <= CPL; ++c) xs[c] = clampi(x + ix + c, 0, Wl - 1);
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
                     const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
-                    const float A = row[xa], Bv = row[xb];
-                    const float h = A + ax * (Bv - A);
-                    if (j < kPatch) {
-                        px += fgx[j] * h;
-                        py += fgy[j] * h;
-                    }
-                    if (j > 0) {
-                        qx += fgx[j - 1] * h;
-                        qy += fgy[j - 1] * h;
+                    float a[CPL + 1];
+#pragma unroll
+                    for (int c = 0; c <= CPL; ++c) a[c] = row[xs[c]];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float h = a[c] + ax * (a[c + 1] - a[c]);
+                        if (j < kPatch) {
+                            px[c] += fgx[c][j] * h;
+                            py[c] += fgy[c][j] * h;
+                        }
+                        if (j > 0) {
+                            qx[c] += fgx[c][j - 1] * h;
+                            qy[c] += fgy[c][j - 1] * h;
+                        }
                     }
                 }
             }
-            const float bx = red8f(px + ay * (qx - px)) - fcx;
-            const float by = red8f(py + ay * (qy - py)) - fcy;
+            float bx = 0.f, by = 0.f;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const float bxc = px[c] + ay * (qx[c] - px[c]), byc = py[c] + ay * (qy[c] - py[c]);
+                bx = c ? bx + bxc : bxc;
+                by = c ? by + byc : byc;
+            }
+            bx = redf<LP>(bx) - fcx;
+            by = redf<LP>(by) - fcy;
             ux -= fia * bx + fib * by;
             uy -= fib * bx + fic * by;
         }
@@ -908,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             rux = u0x;
             ruy = u0y;
         }
-        if (valid && c == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(rux, ruy);
+        if (valid && cg == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(rux, ruy);
         __syncthreads();  // the next item restages sR
     }
 }
@@ -1043,7 +1089,23 @@ void launch_pyr_chain(const Launch& L, int from) {
     else
         hipLaunchKernelGGL(k_pyr_chain<false>, dim3(L.grid), dim3(kPyrBlock), 0, L.stream, *L.one, L.ba, L.total, from);
 }
-void launch_dis_level(const Launch& L, int level) { EBOF_LAUNCH(k_dis_level, L, level); }
+void launch_dis_level(const Launch& L, int level, int lanes) {
+    if (lanes == 4) {
+        if (L.batch)
+            hipLaunchKernelGGL((k_dis_level<true, 4>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba, L.total,
+                               level);
+        else
+            hipLaunchKernelGGL((k_dis_level<false, 4>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba,
+                               L.total, level);
+    } else {
+        if (L.batch)
+            hipLaunchKernelGGL((k_dis_level<true, 8>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba, L.total,
+                               level);
+        else
+            hipLaunchKernelGGL((k_dis_level<false, 8>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba,
+                               L.total, level);
+    }
+}
 void launch_densify(const Launch& L, int tile_w) {
     switch (tile_w) {
         case 128: EBOF_LAUNCH_T(k_densify, 128, L); break;
@@ -1073,7 +1135,8 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const
         const int l = stage - kStDis;
         if (!has_flow || l >= d.L) return 0;
         const LevelGeom& g = d.lv[l];
-        return g.pny * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
+        const int pr = 8 / t.dis_lanes[l];  // patch rows per item
+        return ((g.pny + pr - 1) / pr) * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
     }
     if (stage == kStDensify)
         return (has_flow || d.zero_out)

@@ -149,8 +149,8 @@ def _check_outs(streams, ref, outs, k, tag):
         assert torch.equal(o["flow"], r[3]), (tag, s, "flow")
 
 
-@pytest.mark.parametrize("rows, tile_w, grid", [(1, 256, 256), (8, 128, 0), (2, 64, 4096)])
-def test_batch_forced_launch_shapes_equal_alone(ctx, tmp_path, rows, tile_w, grid):
+@pytest.mark.parametrize("rows, tile_w, lanes, grid", [(1, 256, 8, 256), (8, 128, 4, 0), (2, 64, 4, 4096)])
+def test_batch_forced_launch_shapes_equal_alone(ctx, tmp_path, rows, tile_w, lanes, grid):
     """Every tile shape and block count the tuner can pick gives the stage
     calls' results: shapes forced through the tuning cache file."""
     streams = mixed_streams(n_low=2, n_hd=1, windows=2)
@@ -158,15 +158,15 @@ def test_batch_forced_launch_shapes_equal_alone(ctx, tmp_path, rows, tile_w, gri
     outs = _outs_for(streams, ref, 1)
     batch = _batch_of(streams, outs, 1)
     path = tmp_path / "tune.txt"
-    vals = [rows, tile_w] + [grid] * L.EBOF_TUNE_STAGES
+    vals = [rows, tile_w] + [lanes] * L.EBOF_TUNE_LEVELS + [grid] * L.EBOF_TUNE_STAGES
     path.write_text(L.batch_layout_key(batch) + "\t" + " ".join(map(str, vals)) + "\n")
     L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, str(path))
     try:
         stream = torch.cuda.Stream()
-        _say(f"forced shapes rows={rows} tile_w={tile_w} grid={grid}")
+        _say(f"forced shapes rows={rows} tile_w={tile_w} lanes={lanes} grid={grid}")
         L.ebof_run_batch(ctx, batch, stream=stream)
         torch.cuda.synchronize()
-        _check_outs(streams, ref, outs, 1, (rows, tile_w, grid))
+        _check_outs(streams, ref, outs, 1, (rows, tile_w, lanes, grid))
         # the file is unchanged: the layout was tuned already (read from it)
         assert path.read_text().count("\n") == 1
     finally:
@@ -195,8 +195,9 @@ def test_autotune_cache_roundtrip(tmp_path):
             key, vals = lines[0].split("\t")
             assert key == L.batch_layout_key(batch)
             v = [int(x) for x in vals.split()]
-            assert len(v) == 2 + L.EBOF_TUNE_STAGES
+            assert len(v) == 2 + L.EBOF_TUNE_LEVELS + L.EBOF_TUNE_STAGES
             assert v[0] in (1, 2, 4, 8) and v[1] in (64, 128, 256)
+            assert all(x in (4, 8) for x in v[2:2 + L.EBOF_TUNE_LEVELS])
         finally:
             torch.cuda.synchronize()
             c.close()
@@ -204,7 +205,7 @@ def test_autotune_cache_roundtrip(tmp_path):
 
 def test_tuning_rejects_bad_cache(ctx, tmp_path):
     path = tmp_path / "bad.txt"
-    path.write_text("346,260,3,4,1,0;\t4 64 1 2\n")  # too few block counts
+    path.write_text("346,260,3,4,1,0;\t4 64 1 2\n")  # too few values
     with pytest.raises(L.EbofError) as ei:
         L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, str(path))
     assert ei.value.code == L.EBOF_E_INVAL
