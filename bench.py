@@ -87,6 +87,17 @@ def measured_traffic(kernel):
     return k["hbm_bytes_per_launch"]
 
 
+def pyr_bytes(L, p):
+    """Algorithmic HBM bytes of one window's pyramid chains: each chain reads
+    its first level once and writes the (up to three) levels it builds."""
+    sizes = L.level_sizes(p)
+    n = [w * h for w, h in sizes]
+    b = 0
+    for frm in range(0, len(n) - 1, 3):
+        b += 4 * n[frm] + 4 * sum(n[frm + 1:frm + 4])
+    return b
+
+
 def dis_flops_window(L, p):
     tot = 0
     for l, (w, h) in enumerate(L.level_sizes(p)):
@@ -348,7 +359,7 @@ def main():
         bytes_per_window = {"edt_rows": 2 * N + 4 * N, "densify": 4 * N + 4 * N + N + 8 * N,
                             "scatter": 12 * 300_000, "denoise_fill": 2 * N,
                             "edt_cols": N // 8 + 2 * N, "pack_cols": N + N // 8,
-                            "pyr_down": 4 * (P - N) + 4 * P}.get(dominant, 0)
+                            "pyr_down": pyr_bytes(L, p)}.get(dominant, 0)
         achieved = bytes_per_window * K / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic({"pyr_down": "k_pyr_chain"}.get(dominant, "k_" + dominant)),
@@ -384,6 +395,19 @@ def main():
                          "an i9-9880H + Quadro RTX 5000 (different flow method and hardware)",
     }
 
+    # ---------------- the low-resolution plain config ------------------------
+    c1 = synth.generate("c1", 0, range(64), workers=args.workers)
+    c1_pair = None
+    if not args.no_cpu_baseline:
+        import oracle
+        p1 = L.ebof_params_default(346, 260, flags=L.EBOF_MASK_FLOW)
+        rs = [oracle.window(346, 260, w["x"], w["y"], w["t"], w["t0"], p1.dt_us, p1.n_d, p1.n_f,
+                            float(np.float32(p1.alpha)), p1.levels) for w in c1[:2]]
+        c1_pair = (oracle.dis_flow(rs[0]["pyr"], rs[1]["pyr"], 346, 260, p1.levels, stride=p1.stride,
+                                   iters=p1.iters, lam=float(np.float32(p1.lambda_reg))),
+                   rs[0]["Edf"].astype(bool))
+    out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, NF, c1_pair)
+
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
         out["batched"] = bench_batched(L, ctx, c3, args.batched_steps, dev, stream)
@@ -393,6 +417,95 @@ def main():
         out["serving"]["speedup_vs_plain"] = out["serving"]["saturation"]["frames_per_s"] / fps
         out["stress"] = bench_burst(L, c4, c5, dev)
     print(json.dumps(out), flush=True)
+
+
+def bench_c1(L, ctx, c1, steps, dev, nf, oracle_pair):
+    """346x260 plain path (the low-resolution config): sequential and
+    pipelined rates over the C1 stream's windows, and the EPE against the
+    oracle on its first pair (oracle_pair: (flow, mask) or None)."""
+    import ctypes
+    import torch
+    p = L.ebof_params_default(346, 260, flags=L.EBOF_MASK_FLOW)
+    W, H = p.width, p.height
+    N, P = W * H, L.ebof_pyramid_floats(p)
+    NB = 16
+    pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(NB)]
+    edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(NB)]
+    flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NB)]
+    evs = [dict(x=torch.from_numpy(w["x"]).to(dev), y=torch.from_numpy(w["y"]).to(dev),
+                t=torch.from_numpy(w["t"]).to(dev), t0=w["t0"], n=len(w["x"])) for w in c1]
+    streams = [torch.cuda.Stream() for _ in range(nf + 1)]
+    sp = [ctypes.c_void_p(st.cuda_stream) for st in streams]
+    lib, h = ctx.lib, ctx.handle
+    vp, pp = ctypes.c_void_p, ctypes.byref(p)
+    prep = [(vp(e["x"].data_ptr()), vp(e["y"].data_ptr()), vp(e["t"].data_ptr()), e["n"], e["t0"]) for e in evs]
+    pyr_p = [vp(x.data_ptr()) for x in pyr]
+    edge_p = [vp(x.data_ptr()) for x in edge]
+    flow_p = [vp(x.data_ptr()) for x in flows]
+
+    def check(rc):
+        if rc:
+            raise RuntimeError(lib.ebof_last_error(h).decode())
+
+    def pre(k, si):
+        x, y, t, n, t0 = prep[k % len(prep)]
+        check(lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[k % NB], None, sp[si]))
+        check(lib.ebof_edt_surface(h, pp, edge_p[k % NB], None, pyr_p[k % NB], sp[si]))
+
+    def flw(k, si):
+        b, bp = k % NB, (k - 1) % NB
+        check(lib.ebof_flow(h, pp, pyr_p[bp], pyr_p[b], edge_p[bp], flow_p[b], sp[si]))
+
+    pre(0, 0)
+    pre(1, 0)
+    flw(1, 0)
+    streams[0].synchronize()
+    epe = None
+    if oracle_pair is not None:
+        g = flows[1].cpu().numpy().reshape(2, H, W).astype(np.float64)
+        r, m = oracle_pair
+        epe = float(np.hypot(g[0] - r[0], g[1] - r[1])[m].mean())
+    for k in range(2, 12):  # warm
+        pre(k, 0)
+        flw(k, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(12, 12 + steps):
+        pre(k, 0)
+        flw(k, 0)
+    streams[0].synchronize()
+    fps_seq = steps / (time.perf_counter() - t0)
+    k0 = 12 + steps
+    ev_flow = {}
+
+    def pipelined(lo, hi):
+        for k in range(lo, hi):
+            for j in (k - NB, k - NB + 1):
+                e = ev_flow.pop(j, None) if j == k - NB else ev_flow.get(j)
+                if e is not None and not e.query():
+                    streams[0].wait_event(e)
+            pre(k, 0)
+            e = torch.cuda.Event()
+            e.record(streams[0])
+            fi = 1 + k % nf
+            streams[fi].wait_event(e)
+            flw(k, fi)
+            ev_flow[k] = torch.cuda.Event()
+            ev_flow[k].record(streams[fi])
+
+    pipelined(k0, k0 + 4 * nf)
+    torch.cuda.synchronize()
+    k0 += 4 * nf
+    t0 = time.perf_counter()
+    pipelined(k0, k0 + steps)
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    res = {"workload": "346x260 plain single camera stream, 20k events per window, 40 segments translating "
+                       "(+2.5, -1.5) px per window, 5% noise, L=3",
+           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "flow_streams": nf,
+           "epe_vs_oracle_px": epe}
+    log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined; EPE vs oracle {epe}")
+    return res
 
 
 def bench_batched(L, ctx, c3, steps, dev, stream):
@@ -458,7 +571,38 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
         run(1 + k % (nwin - 1))
         stream.synchronize()
         lat.append((time.perf_counter() - s0) * 1e3)
+    # per-kernel times over whole batches (timing launches directly, no
+    # graph), and the HBM rate of the EDT row pass and the pyramid against
+    # their algorithmic bytes (event-pair cost subtracted per bracket)
+    pairs = []
+    for _ in range(32):
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        eb.record(stream)
+        pairs.append((ea, eb))
+    stream.synchronize()
+    pair_ms = float(np.median([a.elapsed_time(b) for a, b in pairs]))
+    nb_t = 8
+    lib.ebof_timing_enable(h, (1 << len(L.KERNELS)) - 1)
+    for k in range(nb_t):
+        run(1 + k % (nwin - 1))
+    stream.synchronize()
+    kern = {}
+    for name in L.KERNELS:
+        ms, cnt = L.ebof_timing_read(ctx, name)
+        if cnt:
+            kern[name] = max(ms - nb_t * pair_ms, 0.0) / nb_t  # one bracket per kernel per batch
+    lib.ebof_timing_enable(h, 0)
+    rows_bytes = sum(6 * q.width * q.height for q in params)
+    pyr_b = sum(pyr_bytes(L, q) for q in params)
+    hbm = {}
+    for name, nbytes in (("edt_rows", rows_bytes), ("pyr_down", pyr_b)):
+        if kern.get(name):
+            gbs = nbytes / (kern[name] * 1e-3) / 1e9
+            hbm[name] = {"bytes_per_batch": nbytes, "ms_per_batch": kern[name], "GB_per_s": gbs,
+                         "frac_of_peak": gbs / HBM_PEAK_GBS}
     res = {"streams": ns, "mix": "10 x 346x260 (L3) + 6 x 1280x720 (L4)", "batch_steps": steps,
+           "kernels_ms_per_batch": kern, "hbm": hbm, "event_pair_ms": pair_ms,
            "frames_per_s": frames / dt, "hd_frames_per_s": hd / dt, "ms_per_batch": 1e3 * dt / steps,
            "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "graph": True}
