@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 346x260 plain section")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=24, help="oracle flows in the CPU sample (~15 s)")
     ap.add_argument("--batched-steps", type=int, default=40)
@@ -328,25 +329,22 @@ def main():
     lat = np.array(lat)
 
     # ---------------- roofline of the dominant kernel -----------------------
-    # The library brackets each run of consecutive launches of the kernel
-    # (one per window: its pyramid chains or search levels) with one pair of
-    # HIP events; an empty pair on the same stream measures what the pair
-    # itself adds, subtracted once per bracket.
+    # The library brackets every launch of the kernel with a pair of HIP
+    # events; an empty pair on the same stream measures what the pair itself
+    # adds, subtracted once per launch.
     e0s = []
-    with torch.cuda.stream(stream):
-        for _ in range(64):
-            ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ea.record(stream)
-            eb.record(stream)
-            e0s.append((ea, eb))
+    for _ in range(64):
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        eb.record(stream)
+        e0s.append((ea, eb))
     stream.synchronize()
     pair_ms = float(np.median([a.elapsed_time(b) for a, b in e0s]))
     dom_ms_raw = dom_ms
-    dom_ms = max(dom_ms_raw - K * pair_ms, 1e-9)  # K brackets: one per window
+    dom_ms = max(dom_ms_raw - dom_cnt * pair_ms, 1e-9)
     per_launch_ms = dom_ms / max(1, dom_cnt)
     timing = {"ms_per_launch": per_launch_ms, "launches": dom_cnt,
-              "ms_per_launch_raw": dom_ms_raw / max(1, dom_cnt), "event_pair_ms": pair_ms,
-              "brackets": K}
+              "ms_per_launch_raw": dom_ms_raw / max(1, dom_cnt), "event_pair_ms": pair_ms}
     if dominant == "dis_level":
         work = dis_flops_window(L, p) * K  # all DIS launches of the timed region
         achieved = work / (dom_ms * 1e-3) / 1e12
@@ -396,9 +394,9 @@ def main():
     }
 
     # ---------------- the low-resolution plain config ------------------------
-    c1 = synth.generate("c1", 0, range(64), workers=args.workers)
+    c1 = [] if args.no_c1 else synth.generate("c1", 0, range(64), workers=args.workers)
     c1_pair = None
-    if not args.no_cpu_baseline:
+    if c1 and not args.no_cpu_baseline:
         import oracle
         p1 = L.ebof_params_default(346, 260, flags=L.EBOF_MASK_FLOW)
         rs = [oracle.window(346, 260, w["x"], w["y"], w["t"], w["t0"], p1.dt_us, p1.n_d, p1.n_f,
@@ -406,7 +404,8 @@ def main():
         c1_pair = (oracle.dis_flow(rs[0]["pyr"], rs[1]["pyr"], 346, 260, p1.levels, stride=p1.stride,
                                    iters=p1.iters, lam=float(np.float32(p1.lambda_reg))),
                    rs[0]["Edf"].astype(bool))
-    out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, NF, c1_pair)
+    if c1:
+        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, NF, c1_pair)
 
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
@@ -572,8 +571,8 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
         stream.synchronize()
         lat.append((time.perf_counter() - s0) * 1e3)
     # per-kernel times over whole batches (timing launches directly, no
-    # graph), and the HBM rate of the EDT row pass and the pyramid against
-    # their algorithmic bytes (event-pair cost subtracted per bracket)
+    # graph; event-pair cost subtracted per launch), and the HBM rate of the
+    # EDT row pass and the pyramid against their algorithmic bytes
     pairs = []
     for _ in range(32):
         ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -581,7 +580,7 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
         eb.record(stream)
         pairs.append((ea, eb))
     stream.synchronize()
-    pair_ms = float(np.median([a.elapsed_time(b) for a, b in pairs]))
+    pair_ms = float(np.median([a.elapsed_time(b) for a, b in pairs]))  # subtracted per launch
     nb_t = 8
     lib.ebof_timing_enable(h, (1 << len(L.KERNELS)) - 1)
     for k in range(nb_t):
@@ -591,7 +590,7 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
     for name in L.KERNELS:
         ms, cnt = L.ebof_timing_read(ctx, name)
         if cnt:
-            kern[name] = max(ms - nb_t * pair_ms, 0.0) / nb_t  # one bracket per kernel per batch
+            kern[name] = max(ms - cnt * pair_ms, 0.0) / nb_t
     lib.ebof_timing_enable(h, 0)
     rows_bytes = sum(6 * q.width * q.height for q in params)
     pyr_b = sum(pyr_bytes(L, q) for q in params)

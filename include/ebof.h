@@ -261,13 +261,12 @@ int ebof_poll(ebof_ctx *ctx, uint64_t ticket, int32_t *status, int64_t *latency_
 int ebof_drain(ebof_ctx *ctx);
 
 /* ---- measurement -------------------------------------------------------------
- * Kernel timing: when enabled, the launches of the selected kernels are
- * bracketed by HIP events on the stream they are launched on, one pair per
- * run of consecutive launches of one kernel (the pyramid chains of a call,
- * the search levels of a call), so that the events' own cost is shared by
- * the run; ebof_timing_read waits for them and returns the total
- * milliseconds and the launch count accumulated since the last read (then
- * resets).  Timing disables graph capture of the batched form. */
+ * Kernel timing: when enabled, every launch of a selected kernel is
+ * bracketed by a pair of HIP events recorded on its stream right before and
+ * right after it (the pair itself adds a fixed cost, which a caller can
+ * measure with an empty pair); ebof_timing_read waits for them and returns
+ * the total milliseconds and the launch count accumulated since the last
+ * read (then resets).  Timing disables graph capture of the batched form. */
 #define EBOF_K_SCATTER 0
 #define EBOF_K_DENOISE_FILL 1
 #define EBOF_K_PACK_COLS 2

@@ -235,30 +235,43 @@ static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int*
 }
 
 // ---------------------------------------------------------------- timing
+// Kernel timing: while timed() runs f for a selected kernel, every launch
+// built (one_launch, batch_launch) takes an event pair recorded right before
+// and right after it on its stream.
+struct TimingScope {
+    ebof_ctx* ctx = nullptr;
+    int kid = -1;
+};
+static thread_local TimingScope tl_timing;
+
+static void attach_timing(Launch& L) {
+    ebof_ctx* ctx = tl_timing.ctx;
+    if (!ctx) return;
+    TimedPair tp;
+    tp.launches = 1;
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
+    for (hipEvent_t* e : {&tp.a, &tp.b}) {
+        if (!ctx->event_pool.empty()) {
+            *e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            return;  // untimed launch rather than a failed one
+        }
+    }
+    ctx->timed[tl_timing.kid].push_back(tp);
+    L.ev_start = tp.a;
+    L.ev_stop = tp.b;
+}
+
 template <class F>
-static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f, int launches = 1) {
+static void timed(ebof_ctx* ctx, int kid, hipStream_t, F&& f) {
     if (!(ctx->timing_mask.load(std::memory_order_relaxed) & (1u << kid))) {
         f();
         return;
     }
-    TimedPair tp;
-    tp.launches = launches;
-    {
-        std::lock_guard<std::mutex> lk(ctx->timing_mu);
-        for (hipEvent_t* e : {&tp.a, &tp.b}) {
-            if (!ctx->event_pool.empty()) {
-                *e = ctx->event_pool.back();
-                ctx->event_pool.pop_back();
-            } else {
-                (void)hipEventCreate(e);
-            }
-        }
-    }
-    (void)hipEventRecord(tp.a, st);
+    tl_timing = TimingScope{ctx, kid};
     f();
-    (void)hipEventRecord(tp.b, st);
-    std::lock_guard<std::mutex> lk(ctx->timing_mu);
-    ctx->timed[kid].push_back(tp);
+    tl_timing = TimingScope{};
 }
 
 // stage calls launch one block per item with the default tile shapes
@@ -272,6 +285,7 @@ static Launch one_launch(const WinDesc* d, int32_t total, hipStream_t st) {
     L.total = total;
     L.grid = std::max(1, total);
     L.stream = st;
+    attach_timing(L);
     return L;
 }
 
@@ -377,6 +391,7 @@ static Launch batch_launch(BatchRunner& br, const WinDesc* first, int s, int32_t
     L.total = total;
     L.grid = grid;
     L.stream = st;
+    attach_timing(L);
     return L;
 }
 static void launch_stage(const Launch& L, int s, const Tune& t) {
@@ -671,6 +686,11 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
             }
         }
     }
+    // One universal graph serves batches of any composition, so its launch
+    // shapes must not depend on the batch: 8 lanes per patch at every level
+    // (a layout's shapes are fixed by the layout itself).
+    if (universal)
+        for (int l = 0; l < kMaxLevels; ++l) tune.dis_lanes[l] = 8;
     resolve_dis_lanes(tune, descs.data(), n);
     std::vector<int32_t> prefix;
     int32_t totals[kNumStages];
@@ -681,7 +701,7 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
     const int mode = (ctx->timing_mask == 0 && ctx->use_graphs) ? graph_mode : kGraphNone;
     auto run_all = [&](bool all) {
         // consecutive launches of one kernel (pyramid chains, search levels)
-        // share one timing bracket
+        // form one group
         std::vector<int> order;
         for (int s : pipeline_order(lmax))
             if (all || totals[s]) order.push_back(s);
@@ -699,7 +719,7 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
             if (kid < 0)
                 launch_group();
             else
-                timed(ctx, kid, st, launch_group, (int)(j - i));
+                timed(ctx, kid, st, launch_group);
             i = j;
         }
     };
@@ -907,16 +927,14 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
     timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
-    const int nchain = (p->levels - 1 + kPyrChain - 1) / kPyrChain;
-    if (nchain > 0)
+    if (p->levels > 1)
         timed(
             ctx, EBOF_K_PYR_DOWN, st,
             [&] {
                 for (int from = 0; from < p->levels - 1; from += kPyrChain)
                     launch_pyr_chain(
                         one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
-            },
-            nchain);
+            });
     return launch_status(ctx);
 }
 
@@ -953,8 +971,7 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
             for (int l = p->levels - 1; l >= 0; --l)
                 launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l,
                                  tune.dis_lanes[l]);
-        },
-        p->levels);
+        });
     timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw); });
     return launch_status(ctx);
 }

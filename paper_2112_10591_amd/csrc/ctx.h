@@ -58,8 +58,8 @@ struct Lut {
 };
 
 struct TimedPair {
-    hipEvent_t a, b;
-    int launches;  // consecutive launches between a and b
+    hipEvent_t a, b;  // stamped with one kernel's start and end
+    int launches;
 };
 
 // Device descriptor table + pinned staging ring + captured graphs of one

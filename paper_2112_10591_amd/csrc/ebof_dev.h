@@ -110,6 +110,8 @@ struct Launch {
     int32_t total;       // items (single-window form)
     int32_t grid;        // blocks
     hipStream_t stream;
+    hipEvent_t ev_start = nullptr;  // when set: events recorded right before
+    hipEvent_t ev_stop = nullptr;   // and right after the kernel
 };
 
 // Launch shapes the autotuner chooses among.  None of them changes what a

@@ -1034,14 +1034,20 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
-#define EBOF_LAUNCH(KERNEL, L, ...)                                                              \
-    do {                                                                                         \
-        if ((L).batch)                                                                           \
-            hipLaunchKernelGGL(KERNEL<true>, dim3((L).grid), dim3(kBlock), 0, (L).stream, *(L).one, \
-                               (L).ba, (L).total, ##__VA_ARGS__);                                \
-        else                                                                                     \
-            hipLaunchKernelGGL(KERNEL<false>, dim3((L).grid), dim3(kBlock), 0, (L).stream,        \
-                               *(L).one, (L).ba, (L).total, ##__VA_ARGS__);                      \
+// Every launch goes through here; with timing events attached they are
+// recorded on the stream right before and right after the kernel.
+template <typename K, typename... Args>
+static void klaunch(const Launch& L, K kernel, int block, Args... args) {
+    if (L.ev_start) (void)hipEventRecord(L.ev_start, L.stream);
+    hipLaunchKernelGGL(kernel, dim3(L.grid), dim3(block), 0, L.stream, args...);
+    if (L.ev_stop) (void)hipEventRecord(L.ev_stop, L.stream);
+}
+#define EBOF_LAUNCH(KERNEL, L, ...)                                                        \
+    do {                                                                                   \
+        if ((L).batch)                                                                     \
+            klaunch((L), KERNEL<true>, kBlock, *(L).one, (L).ba, (L).total, ##__VA_ARGS__);  \
+        else                                                                               \
+            klaunch((L), KERNEL<false>, kBlock, *(L).one, (L).ba, (L).total, ##__VA_ARGS__); \
     } while (0)
 
 void launch_zero(const Launch& L) { EBOF_LAUNCH(k_zero, L); }
@@ -1049,30 +1055,24 @@ void launch_scatter(const Launch& L) { EBOF_LAUNCH(k_scatter, L); }
 void launch_denoise_fill(const Launch& L, bool pack) {
     if (pack) {
         if (L.batch)
-            hipLaunchKernelGGL((k_denoise_fill<true, true>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one,
-                               L.ba, L.total);
+            klaunch(L, k_denoise_fill<true, true>, kBlock, *L.one, L.ba, L.total);
         else
-            hipLaunchKernelGGL((k_denoise_fill<false, true>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one,
-                               L.ba, L.total);
+            klaunch(L, k_denoise_fill<false, true>, kBlock, *L.one, L.ba, L.total);
     } else {
         if (L.batch)
-            hipLaunchKernelGGL((k_denoise_fill<true, false>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one,
-                               L.ba, L.total);
+            klaunch(L, k_denoise_fill<true, false>, kBlock, *L.one, L.ba, L.total);
         else
-            hipLaunchKernelGGL((k_denoise_fill<false, false>), dim3(L.grid), dim3(kBlock), 0, L.stream,
-                               *L.one, L.ba, L.total);
+            klaunch(L, k_denoise_fill<false, false>, kBlock, *L.one, L.ba, L.total);
     }
 }
 void launch_pack_cols(const Launch& L) { EBOF_LAUNCH(k_pack_cols, L); }
 void launch_edt_cols(const Launch& L) { EBOF_LAUNCH(k_edt_cols, L); }
-#define EBOF_LAUNCH_T(KERNEL, T, L)                                                                    \
-    do {                                                                                               \
-        if ((L).batch)                                                                                 \
-            hipLaunchKernelGGL((KERNEL<true, T>), dim3((L).grid), dim3(kBlock), 0, (L).stream, *(L).one, \
-                               (L).ba, (L).total);                                                     \
-        else                                                                                           \
-            hipLaunchKernelGGL((KERNEL<false, T>), dim3((L).grid), dim3(kBlock), 0, (L).stream,        \
-                               *(L).one, (L).ba, (L).total);                                           \
+#define EBOF_LAUNCH_T(KERNEL, T, L)                                               \
+    do {                                                                          \
+        if ((L).batch)                                                            \
+            klaunch((L), KERNEL<true, T>, kBlock, *(L).one, (L).ba, (L).total);   \
+        else                                                                      \
+            klaunch((L), KERNEL<false, T>, kBlock, *(L).one, (L).ba, (L).total);  \
     } while (0)
 
 void launch_edt_rows(const Launch& L, int rows_nr) {
@@ -1085,25 +1085,21 @@ void launch_edt_rows(const Launch& L, int rows_nr) {
 }
 void launch_pyr_chain(const Launch& L, int from) {
     if (L.batch)
-        hipLaunchKernelGGL(k_pyr_chain<true>, dim3(L.grid), dim3(kPyrBlock), 0, L.stream, *L.one, L.ba, L.total, from);
+        klaunch(L, k_pyr_chain<true>, kPyrBlock, *L.one, L.ba, L.total, from);
     else
-        hipLaunchKernelGGL(k_pyr_chain<false>, dim3(L.grid), dim3(kPyrBlock), 0, L.stream, *L.one, L.ba, L.total, from);
+        klaunch(L, k_pyr_chain<false>, kPyrBlock, *L.one, L.ba, L.total, from);
 }
 void launch_dis_level(const Launch& L, int level, int lanes) {
     if (lanes == 4) {
         if (L.batch)
-            hipLaunchKernelGGL((k_dis_level<true, 4>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba, L.total,
-                               level);
+            klaunch(L, k_dis_level<true, 4>, kBlock, *L.one, L.ba, L.total, level);
         else
-            hipLaunchKernelGGL((k_dis_level<false, 4>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba,
-                               L.total, level);
+            klaunch(L, k_dis_level<false, 4>, kBlock, *L.one, L.ba, L.total, level);
     } else {
         if (L.batch)
-            hipLaunchKernelGGL((k_dis_level<true, 8>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba, L.total,
-                               level);
+            klaunch(L, k_dis_level<true, 8>, kBlock, *L.one, L.ba, L.total, level);
         else
-            hipLaunchKernelGGL((k_dis_level<false, 8>), dim3(L.grid), dim3(kBlock), 0, L.stream, *L.one, L.ba,
-                               L.total, level);
+            klaunch(L, k_dis_level<false, 8>, kBlock, *L.one, L.ba, L.total, level);
     }
 }
 void launch_densify(const Launch& L, int tile_w) {
