@@ -137,7 +137,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 static size_t scratch_bytes(const Geom& g) {
     const size_t N = (size_t)g.W * g.H;
     const size_t nch = (size_t)(g.H + kChunk - 1) / kChunk;
-    return align256(N) + align256(nch * g.W * 8) + align256(N * 2) + align256((size_t)g.patches * 16);
+    return align256(N) + align256(nch * g.W * 8) + align256(N * 2) + align256((size_t)g.patches * 8);
 }
 
 // ---------------------------------------------------------------- ctx helpers
@@ -181,7 +181,7 @@ int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t) {
     t.e_raw = (uint8_t*)ctx->arena.alloc(N);
     t.colmask = (uint64_t*)ctx->arena.alloc(nch * g.W * 8);
     t.g = (uint16_t*)ctx->arena.alloc(N * 2);
-    t.puv = (double2*)ctx->arena.alloc((size_t)g.patches * 16);
+    t.puv = (float2*)ctx->arena.alloc((size_t)g.patches * 8);
     if (!t.e_raw || !t.colmask || !t.g || !t.puv) {
         scratch_free(ctx, &t);
         set_error("arena full: window scratch needs %zu bytes, %zu free", scratch_bytes(g),

@@ -38,7 +38,7 @@ struct Scratch {
     uint8_t* e_raw = nullptr;
     uint64_t* colmask = nullptr;
     uint16_t* g = nullptr;
-    double2* puv = nullptr;
+    float2* puv = nullptr;
     uint32_t stamp = 0;
     bool needs_zero = true;
     // next stamp; sets needs_zero when the counter wraps

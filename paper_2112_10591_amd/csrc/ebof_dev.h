@@ -26,7 +26,7 @@ constexpr int kTile = 64;             // denoise/fill: 64 wide ...
 constexpr int kTileH = 32;            // ... and 32 tall per block
 constexpr int kChunk = 64;            // column-mask chunk: 64 rows per word
 constexpr int kPyrChain = 3;          // pyramid: levels built per launch
-constexpr int kPatchesPerItem = 32;   // inverse search: 4 waves x 8 patches
+constexpr int kPatchesPerItem = 16;   // inverse search: patches per item row
 constexpr int kZeroBytesPerItem = 4096;
 constexpr int kRowSeg = 256;          // EDT row pass: pixels per item row
 constexpr int kRowReach = 64;         // EDT row pass: columns staged each side of a segment
@@ -70,7 +70,7 @@ struct WinDesc {
     uint8_t* mask_out;      // W*H copy of the reference edge image, or null
     uint32_t zero_out;      // no reference window: flow and mask_out written as 0
     uint32_t pad1;
-    double2* puv;           // patch displacements (u, v), all levels
+    float2* puv;            // patch displacements (u, v), all levels
     unsigned long long* n_dropped;  // optional counter
     LevelGeom lv[kMaxLevels];
 };

@@ -620,41 +620,30 @@ __device__ __forceinline__ float dppf(float v) {
 }
 
 // Densification samples, single precision.  The sample position x + u is
-// split exactly (integer part of u in double, fraction rounded once to
-// float), so the fraction keeps full precision however wide the image; a
-// position off the image samples the border whatever its distance.  Fetch
-// and blend are separate so that several samples' loads can be in flight;
-// the blend recomputes the fractions (fewer registers held across loads).
+// split exactly into an integer part and a fraction (floor of a float and
+// the difference, both exact), so the fraction keeps full precision however
+// wide the image; a position off the image samples the border whatever its
+// distance.  Fetch and blend are separate so that several samples' loads can
+// be in flight.
 struct DensTap {
-    float a, b, c, d;
+    float a, b, c, d, ax, ay;
 };
-__device__ __forceinline__ void dens_split(int W, int H, double ux, double uy, int& ix, int& iy, float& ax,
-                                           float& ay) {
-    const double lim = (double)(W + H + 16);
-    ux = fmin(fmax(ux, -lim), lim);
-    uy = fmin(fmax(uy, -lim), lim);
-    const double fx = floor(ux), fy = floor(uy);
-    ix = (int)fx;
-    iy = (int)fy;
-    ax = (float)(ux - fx);
-    ay = (float)(uy - fy);
-}
-__device__ __forceinline__ DensTap dens_fetch(const float* __restrict__ I, int W, int H, int x, int y, double ux,
-                                              double uy) {
-    int ix, iy;
-    float ax, ay;
-    dens_split(W, H, ux, uy, ix, iy, ax, ay);
+__device__ __forceinline__ DensTap dens_fetch(const float* __restrict__ I, int W, int H, int x, int y, float ux,
+                                              float uy) {
+    const float lim = (float)(W + H + 16);
+    ux = fminf(fmaxf(ux, -lim), lim);
+    uy = fminf(fmaxf(uy, -lim), lim);
+    const float fx = floorf(ux), fy = floorf(uy);
+    const int ix = (int)fx, iy = (int)fy;
     const int xa = clampi(x + ix, 0, W - 1), xb = clampi(x + ix + 1, 0, W - 1);
     const int ya = clampi(y + iy, 0, H - 1), yb = clampi(y + iy + 1, 0, H - 1);
-    return DensTap{I[(size_t)ya * W + xa], I[(size_t)ya * W + xb], I[(size_t)yb * W + xa], I[(size_t)yb * W + xb]};
+    return DensTap{I[(size_t)ya * W + xa], I[(size_t)ya * W + xb], I[(size_t)yb * W + xa], I[(size_t)yb * W + xb],
+                   ux - fx, uy - fy};
 }
-__device__ __forceinline__ float dens_blend(const DensTap& t, int W, int H, double ux, double uy) {
-    int ix, iy;
-    float ax, ay;
-    dens_split(W, H, ux, uy, ix, iy, ax, ay);
-    const float top = t.a + ax * (t.b - t.a);
-    const float bot = t.c + ax * (t.d - t.c);
-    return top + ay * (bot - top);
+__device__ __forceinline__ float dens_blend(const DensTap& t) {
+    const float top = t.a + t.ax * (t.b - t.a);
+    const float bot = t.c + t.ax * (t.d - t.c);
+    return top + t.ay * (bot - top);
 }
 // 1 / max(1, 255 |d|) by the hardware reciprocal (1 ulp)
 __device__ __forceinline__ float dens_weight_f(float dv) {
@@ -662,34 +651,36 @@ __device__ __forceinline__ float dens_weight_f(float dv) {
 }
 
 constexpr int kDensChunk = 4;  // densification: covering patches loaded together
-constexpr int kDisRW = 192;   // LDS search region, columns
-constexpr int kDisRH = 40;    // LDS search region, rows
-constexpr int kDisRP = 41;    // ... stored column-major with this (odd) pitch
-constexpr int kDisMargin = kPatch + 2;  // around the initial windows: covers any patch
-                                        // that stays within the reset distance
+constexpr int kDisRW = 112;   // LDS search region, columns
+constexpr int kDisRH = 68;    // LDS search region, rows
+constexpr int kDisRP = 69;    // ... stored column-major with this (odd) pitch
+constexpr int kDisMargin = kPatch + 6;  // around the initial windows: covers a patch
+                                        // that drifts up to this far in an iteration
 
 // Copies the h x w window of img at (x0, y0), indices clamped into the image
 // (replicated border), into LDS: element (r, c) at dst[c * cs + r * rs]
 // (row-major: cs = 1, rs = pitch; column-major: cs = pitch, rs = 1).  Lanes
-// take columns and the block's waves take rows, so a row's loads coalesce
-// and a thread computes its row offsets once; a thread's loads of a column
-// chunk are all issued before its LDS writes.  Needs h <= 4 * RMAX.
+// take columns and the block's waves take rows, RMAX rows per wave per pass,
+// so a row's loads coalesce and a thread's loads of a column chunk are all
+// issued before its LDS writes.
 template <int RMAX>
 __device__ __forceinline__ void stage_rows_cols(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
                                                 int x0, int y0, int w, int h, int cs, int rs) {
     constexpr int NW = kBlock / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int roff[RMAX];
+    for (int r0 = wave; r0 < h; r0 += NW * RMAX) {
+        int roff[RMAX];
 #pragma unroll
-    for (int i = 0; i < RMAX; ++i) roff[i] = clampi(y0 + wave + NW * i, 0, H - 1) * W;
-    for (int c = lane; c < w; c += 64) {
-        const int gx = clampi(x0 + c, 0, W - 1);
-        float v[RMAX];
+        for (int i = 0; i < RMAX; ++i) roff[i] = clampi(y0 + r0 + NW * i, 0, H - 1) * W;
+        for (int c = lane; c < w; c += 64) {
+            const int gx = clampi(x0 + c, 0, W - 1);
+            float v[RMAX];
 #pragma unroll
-        for (int i = 0; i < RMAX; ++i) v[i] = wave + NW * i < h ? img[roff[i] + gx] : 0.f;
+            for (int i = 0; i < RMAX; ++i) v[i] = r0 + NW * i < h ? img[roff[i] + gx] : 0.f;
 #pragma unroll
-        for (int i = 0; i < RMAX; ++i)
-            if (wave + NW * i < h) dst[c * cs + (wave + NW * i) * rs] = v[i];
+            for (int i = 0; i < RMAX; ++i)
+                if (r0 + NW * i < h) dst[c * cs + (r0 + NW * i) * rs] = v[i];
+        }
     }
 }
 
@@ -714,8 +705,10 @@ __device__ __forceinline__ double redd(double v) {
 // one column per lane, the shortest dependent chain per iteration, for small
 // levels; LP = 4: two columns per lane, the sample column between them read
 // once and the per-iteration coordinate, reduction and update work shared by
-// twice the pixels, for large levels).  Work item = 32 consecutive patches
-// of 8/LP patch rows (256 lanes).  The reference strip (rows oy-1 .. oy+8 of
+// twice the pixels, for large levels).  Work item = 16 consecutive patches of
+// 256/(16 LP) patch rows (256 lanes), a near-square block of the image, so
+// that the spread of the patches' initial displacements, which sizes the
+// search region, stays small.  The reference strip (rows oy-1 .. oy+8 of
 // every patch row of the item) is staged in LDS for the template and its
 // gradient; then the region of I1 covering every patch's search window at
 // its initial displacement (plus a margin) is staged, column-major, and the
@@ -724,11 +717,14 @@ __device__ __forceinline__ double redd(double v) {
 template <bool B, int LP>
 __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                       int level) {
-    constexpr int CPL = kPatch / LP;            // patch columns per lane
-    constexpr int PR = 8 / LP;                  // patch rows per item
-    constexpr int WPR = (kBlock / 64) / PR;     // waves per patch row
-    constexpr int PPW = 64 / LP;                // patches per wave
-    static_assert(WPR * PPW == kPatchesPerItem, "an item row holds kPatchesPerItem patches");
+    constexpr int CPL = kPatch / LP;                   // patch columns per lane
+    constexpr int PR = kBlock / kPatchesPerItem / LP;  // patch rows per item
+    constexpr int PPW = 64 / LP;                       // patches per wave
+    constexpr int WPR = kPatchesPerItem / PPW;         // waves per patch row
+    static_assert(WPR * PR == kBlock / 64, "the block's waves tile the item");
+    // the reference strip at the largest stride (8) fits the buffer
+    static_assert(((kPatchesPerItem - 1) * 8 + kPatch + 2) * ((PR - 1) * 8 + kPatch + 2) <= kDisRW * kDisRP,
+                  "reference strip too large");
     __shared__ float sR[kDisRW * kDisRP];
     __shared__ int sBox[4];
     const int32_t total = item_total<B>(ba, total_arg);
@@ -761,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const int sh = oyB - oyA + kPatch + 2;
         const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
         const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
-        stage_rows_cols<(kPatch + 2 + kPatch * (PR - 1) + 3) / 4>(sR, I0, Wl, Hl, sx0, oyA - 1, sw, sh, 1, sw);
+        stage_rows_cols<(kPatch + 2 + 8 * (PR - 1) + 3) / 4>(sR, I0, Wl, Hl, sx0, oyA - 1, sw, sh, 1, sw);
         __syncthreads();
         // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
         // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
@@ -829,7 +825,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             const LevelGeom gc = d->lv[level + 1];
             const float* __restrict__ C0 = d->pyr_prev + gc.off;
             const float* __restrict__ C1 = d->pyr + gc.off;
-            const double2* __restrict__ cu = d->puv + gc.poff;
+            const float2* __restrict__ cu = d->puv + gc.poff;
             const int px = min((ox + kPatch / 2) >> 1, gc.w - 1);
             const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
             const float inv_s = 1.0f / (float)s;
@@ -840,12 +836,11 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             float sw_ = 0.f, su = 0.f, sv = 0.f;
             for (int q = 0; q < cx.n * cy.n; ++q) {
                 const int qx = cover_index(cx, q % cx.n), qy = cover_index(cy, q / cx.n);
-                const double2 u = cu[(size_t)qy * gc.pnx + qx];
-                const float w =
-                    dens_weight_f(dens_blend(dens_fetch(C1, gc.w, gc.h, px, py, u.x, u.y), gc.w, gc.h, u.x, u.y) - i0);
+                const float2 u = cu[(size_t)qy * gc.pnx + qx];
+                const float w = dens_weight_f(dens_blend(dens_fetch(C1, gc.w, gc.h, px, py, u.x, u.y)) - i0);
                 sw_ += w;
-                su += w * (float)u.x;
-                sv += w * (float)u.y;
+                su += w * u.x;
+                sv += w * u.y;
             }
             u0x = 2.0 * (double)(su / sw_);
             u0y = 2.0 * (double)(sv / sw_);
@@ -874,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const int RH = min(sBox[3] + kPatch + 1 + kDisMargin - RY0, kDisRH);
         // column-major: a lane's rows of one column are contiguous, so every
         // read of an iteration is an immediate offset from one address
-        stage_rows_cols<kDisRH / 4>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP, 1);
+        stage_rows_cols<(kDisRH + 7) / 8>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP, 1);
         __syncthreads();
 
         // ---- inverse-compositional iterations (single precision)
@@ -911,15 +906,21 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
                     }
                 }
             } else {
+                // every sample is loaded before the first is used, so the
+                // loads overlap
                 int xs[CPL + 1];
 #pragma unroll
                 for (int c = 0; c <= CPL; ++c) xs[c] = clampi(x + ix + c, 0, Wl - 1);
+                float A[kPatch + 1][CPL + 1];
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
                     const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
-                    float a[CPL + 1];
 #pragma unroll
-                    for (int c = 0; c <= CPL; ++c) a[c] = row[xs[c]];
+                    for (int c = 0; c <= CPL; ++c) A[j][c] = row[xs[c]];
+                }
+#pragma unroll
+                for (int j = 0; j <= kPatch; ++j) {
+                    const float* a = A[j];
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         const float h = a[c] + ax * (a[c + 1] - a[c]);
@@ -954,7 +955,8 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             rux = u0x;
             ruy = u0y;
         }
-        if (valid && cg == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_double2(rux, ruy);
+        // (exact in float: u is a float, and u0 twice a float quotient)
+        if (valid && cg == 0) d->puv[g.poff + (size_t)ky * pnx + kx] = make_float2((float)rux, (float)ruy);
         __syncthreads();  // the next item restages sR
     }
 }
@@ -989,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const int s = d->stride;
         const float* __restrict__ I0 = d->pyr_prev;
         const float* __restrict__ I1 = d->pyr;
-        const double2* __restrict__ pu = d->puv + g.poff;
+        const float2* __restrict__ pu = d->puv + g.poff;
         const float inv_s = 1.0f / (float)s;
         const Cover cx = cover_of(x, W, g.pnx, s, inv_s), cy = cover_of(y, H, g.pny, s, inv_s);
         const float i0 = I0[pix];
@@ -999,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const int n = cx.n * cy.n;
         int qx = 0, qy = 0;
         for (int q0 = 0; q0 < n; q0 += kDensChunk) {
-            double2 u[kDensChunk];
+            float2 u[kDensChunk];
             DensTap tp[kDensChunk];
 #pragma unroll
             for (int t = 0; t < kDensChunk; ++t) {
@@ -1015,10 +1017,10 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
 #pragma unroll
             for (int t = 0; t < kDensChunk; ++t) {
                 if (q0 + t < n) {
-                    const float w = dens_weight_f(dens_blend(tp[t], W, H, u[t].x, u[t].y) - i0);
+                    const float w = dens_weight_f(dens_blend(tp[t]) - i0);
                     sw += w;
-                    su += w * (float)u[t].x;
-                    sv += w * (float)u[t].y;
+                    su += w * u[t].x;
+                    sv += w * u[t].y;
                 }
             }
         }
@@ -1131,7 +1133,7 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const
         const int l = stage - kStDis;
         if (!has_flow || l >= d.L) return 0;
         const LevelGeom& g = d.lv[l];
-        const int pr = 8 / t.dis_lanes[l];  // patch rows per item
+        const int pr = kBlock / kPatchesPerItem / t.dis_lanes[l];  // patch rows per item
         return ((g.pny + pr - 1) / pr) * ((g.pnx + kPatchesPerItem - 1) / kPatchesPerItem);
     }
     if (stage == kStDensify)
