@@ -313,10 +313,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_pipelined(k0, k0 + K)
+    issue_ms = (time.perf_counter() - t0) * 1e3 / K  # host time to issue a window
     sync_all()
     torch.cuda.synchronize()
     fps = K / (time.perf_counter() - t0)
-    log(f"plain (pipelined, {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window)")
+    log(f"plain (pipelined, {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window, "
+        f"host issue {issue_ms:.4f} ms/window)")
     elapsed = K / fps
 
     # ---------------- unloaded per-window latency (plain) -------------------
@@ -384,6 +386,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
         "plain_flow_streams": NF,
+        "plain_host_issue_ms_per_window": issue_ms,
         "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
         "kernels_ms_per_window": {k: v["ms_per_window"] for k, v in breakdown.items()},

@@ -651,38 +651,69 @@ __device__ __forceinline__ float dens_weight_f(float dv) {
 }
 
 constexpr int kDensChunk = 4;  // densification: covering patches loaded together
+
+// Weighted sums over the patches (displacements pu, pnx per row) covering
+// pixel (x, y) of an image I1 of W x H whose reference intensity is i0: the
+// covering patches in row-major order, kDensChunk at a time, their
+// displacements and then their samples loaded before any is used.
+__device__ __forceinline__ void dens_sums(const float* __restrict__ I1, int W, int H, int x, int y, float i0,
+                                          const float2* __restrict__ pu, int pnx, const Cover& cx, const Cover& cy,
+                                          float& sw, float& su, float& sv) {
+    sw = su = sv = 0.f;
+    const int n = cx.n * cy.n;
+    int qx = 0, qy = 0;
+    for (int q0 = 0; q0 < n; q0 += kDensChunk) {
+        float2 u[kDensChunk];
+        DensTap tp[kDensChunk];
+#pragma unroll
+        for (int t = 0; t < kDensChunk; ++t) {
+            if (q0 + t < n) u[t] = pu[(size_t)cover_index(cy, qy) * pnx + cover_index(cx, qx)];
+            if (++qx == cx.n) {
+                qx = 0;
+                ++qy;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kDensChunk; ++t)
+            if (q0 + t < n) tp[t] = dens_fetch(I1, W, H, x, y, u[t].x, u[t].y);
+#pragma unroll
+        for (int t = 0; t < kDensChunk; ++t) {
+            if (q0 + t < n) {
+                const float w = dens_weight_f(dens_blend(tp[t]) - i0);
+                sw += w;
+                su += w * u[t].x;
+                sv += w * u[t].y;
+            }
+        }
+    }
+}
 constexpr int kDisRW = 112;   // LDS search region, columns
 constexpr int kDisRH = 68;    // LDS search region, rows
-constexpr int kDisRP = 69;    // ... stored column-major with this (odd) pitch
+constexpr int kDisRP = 113;   // ... stored row-major with this (odd) pitch
 constexpr int kDisMargin = kPatch + 6;  // around the initial windows: covers a patch
                                         // that drifts up to this far in an iteration
 
 // Copies the h x w window of img at (x0, y0), indices clamped into the image
-// (replicated border), into LDS: element (r, c) at dst[c * cs + r * rs]
-// (row-major: cs = 1, rs = pitch; column-major: cs = pitch, rs = 1).  Lanes
-// take columns and the block's waves take rows, RMAX rows per wave per pass,
-// so a row's loads coalesce and a thread's loads of a column chunk are all
-// issued before its LDS writes.
-template <int RMAX>
-__device__ __forceinline__ void stage_rows_cols(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
-                                                int x0, int y0, int w, int h, int cs, int rs) {
-    constexpr int NW = kBlock / 64;
+// (replicated border), into LDS row-major with pitch p: element (r, c) at
+// dst[r * p + c].  The block's waves take rows in turn and move each row in
+// 64-column pieces straight from global memory into LDS (lane i of a piece
+// lands at word i), so no registers hold the data and every load of the
+// window is in flight at once.  The caller waits for the loads
+// (lds_load_wait) and synchronises the block before reading.
+__device__ __forceinline__ void stage_rows_lds(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
+                                               int x0, int y0, int w, int h, int p) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int r0 = wave; r0 < h; r0 += NW * RMAX) {
-        int roff[RMAX];
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i) roff[i] = clampi(y0 + r0 + NW * i, 0, H - 1) * W;
-        for (int c = lane; c < w; c += 64) {
-            const int gx = clampi(x0 + c, 0, W - 1);
-            float v[RMAX];
-#pragma unroll
-            for (int i = 0; i < RMAX; ++i) v[i] = r0 + NW * i < h ? img[roff[i] + gx] : 0.f;
-#pragma unroll
-            for (int i = 0; i < RMAX; ++i)
-                if (r0 + NW * i < h) dst[c * cs + (r0 + NW * i) * rs] = v[i];
+    for (int c0 = 0; c0 < w; c0 += 64) {
+        const int gx = clampi(x0 + c0 + lane, 0, W - 1);
+        if (c0 + lane < w) {
+            for (int r = wave; r < h; r += kBlock / 64)
+                __builtin_amdgcn_global_load_lds(img + (size_t)clampi(y0 + r, 0, H - 1) * W + gx,
+                                                 (__attribute__((address_space(3))) void*)(dst + r * p + c0), 4, 0, 0);
         }
     }
 }
+// waits for this wave's loads into LDS (and everything else outstanding)
+__device__ __forceinline__ void lds_load_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // sums over the LP lanes of a patch (LP = 8: quad swaps then the half-row
 // mirror; LP = 4: the two quad swaps), result in every lane
@@ -723,10 +754,10 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
     constexpr int WPR = kPatchesPerItem / PPW;         // waves per patch row
     static_assert(WPR * PR == kBlock / 64, "the block's waves tile the item");
     // the reference strip at the largest stride (8) fits the buffer
-    static_assert(((kPatchesPerItem - 1) * 8 + kPatch + 2) * ((PR - 1) * 8 + kPatch + 2) <= kDisRW * kDisRP,
+    static_assert(((kPatchesPerItem - 1) * 8 + kPatch + 2) * ((PR - 1) * 8 + kPatch + 2) <= kDisRH * kDisRP,
                   "reference strip too large");
-    __shared__ float sR[kDisRW * kDisRP];
-    __shared__ int sBox[4];
+    __shared__ float sR[kDisRH * kDisRP];
+    __shared__ int sBox[kBlock / 64][4];
     const int32_t total = item_total<B>(ba, total_arg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int prow = wave / WPR;                      // patch row within the item
@@ -752,12 +783,36 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const int ox = min(kxc * s, Wl - kPatch), oy = min(kyc * s, Hl - kPatch);
         const int x = ox + cg * CPL;  // the lane's first column
 
-        // ---- template and gradient from the staged reference strip
+        // ---- the reference strip: its loads are issued first and complete
+        // while the initial displacement is formed
         const int oyA = min(ky0 * s, Hl - kPatch), oyB = min(ky_last * s, Hl - kPatch);
         const int sh = oyB - oyA + kPatch + 2;
         const int sx0 = min(kx0 * s, Wl - kPatch) - 1;
         const int sw = min(kx_last * s, Wl - kPatch) + kPatch + 1 - sx0;
-        stage_rows_cols<(kPatch + 2 + 8 * (PR - 1) + 3) / 4>(sR, I0, Wl, Hl, sx0, oyA - 1, sw, sh, 1, sw);
+        stage_rows_lds(sR, I0, Wl, Hl, sx0, oyA - 1, sw, sh, sw);
+
+        // ---- initial displacement: twice the coarser dense flow at the
+        // pixel nearest the patch centre, densified there from the coarser
+        // level's patch displacements as in the densification (every lane of
+        // the patch forms the same sums, so the lane count changes no bit)
+        double u0x = 0.0, u0y = 0.0;
+        if (level < d->L - 1) {
+            const LevelGeom gc = d->lv[level + 1];
+            const float* __restrict__ C0 = d->pyr_prev + gc.off;
+            const float* __restrict__ C1 = d->pyr + gc.off;
+            const int px = min((ox + kPatch / 2) >> 1, gc.w - 1);
+            const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
+            const float inv_s = 1.0f / (float)s;
+            const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
+            float sw_, su, sv;
+            dens_sums(C1, gc.w, gc.h, px, py, C0[(size_t)py * gc.w + px], d->puv + gc.poff, gc.pnx, cx, cy, sw_, su,
+                      sv);
+            u0x = 2.0 * (double)(su / sw_);
+            u0y = 2.0 * (double)(sv / sw_);
+        }
+
+        // ---- template and gradient from the staged reference strip
+        lds_load_wait();
         __syncthreads();
         // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
         // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
@@ -817,59 +872,43 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         fcx = redf<LP>(fcx);
         fcy = redf<LP>(fcy);
 
-        // ---- initial displacement: twice the coarser dense flow at the
-        // pixel nearest the patch centre (densified there from the coarser
-        // level's patch displacements)
-        double u0x = 0.0, u0y = 0.0;
-        if (level < d->L - 1) {
-            const LevelGeom gc = d->lv[level + 1];
-            const float* __restrict__ C0 = d->pyr_prev + gc.off;
-            const float* __restrict__ C1 = d->pyr + gc.off;
-            const float2* __restrict__ cu = d->puv + gc.poff;
-            const int px = min((ox + kPatch / 2) >> 1, gc.w - 1);
-            const int py = min((oy + kPatch / 2) >> 1, gc.h - 1);
-            const float inv_s = 1.0f / (float)s;
-            const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
-            // as in the densification; every lane sums all covering patches
-            // in order (the same bits whatever the lane count)
-            const float i0 = C0[(size_t)py * gc.w + px];
-            float sw_ = 0.f, su = 0.f, sv = 0.f;
-            for (int q = 0; q < cx.n * cy.n; ++q) {
-                const int qx = cover_index(cx, q % cx.n), qy = cover_index(cy, q / cx.n);
-                const float2 u = cu[(size_t)qy * gc.pnx + qx];
-                const float w = dens_weight_f(dens_blend(dens_fetch(C1, gc.w, gc.h, px, py, u.x, u.y)) - i0);
-                sw_ += w;
-                su += w * u.x;
-                sv += w * u.y;
-            }
-            u0x = 2.0 * (double)(su / sw_);
-            u0y = 2.0 * (double)(sv / sw_);
-        }
-
-        // ---- stage the search region of I1
+        // ---- stage the search region of I1: the box of the patches'
+        // initial windows, reduced over each wave's lanes, then over the
+        // waves through LDS
         const double lim = (double)(Wl + Hl + 16);
-        if (threadIdx.x == 0) {
-            sBox[0] = INT32_MAX;
-            sBox[1] = INT32_MIN;
-            sBox[2] = INT32_MAX;
-            sBox[3] = INT32_MIN;
+        int bx0 = INT32_MAX, bx1 = INT32_MIN, by0 = INT32_MAX, by1 = INT32_MIN;
+        if (valid) {
+            bx0 = bx1 = ox + (int)floor(fmin(fmax(u0x, -lim), lim));
+            by0 = by1 = oy + (int)floor(fmin(fmax(u0y, -lim), lim));
+        }
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            bx0 = min(bx0, __shfl_xor(bx0, m));
+            bx1 = max(bx1, __shfl_xor(bx1, m));
+            by0 = min(by0, __shfl_xor(by0, m));
+            by1 = max(by1, __shfl_xor(by1, m));
+        }
+        if (lane == 0) {
+            sBox[wave][0] = bx0;
+            sBox[wave][1] = bx1;
+            sBox[wave][2] = by0;
+            sBox[wave][3] = by1;
         }
         __syncthreads();  // also ends the reads of the reference strip
-        if (valid && cg == 0) {
-            const int wx = ox + (int)floor(fmin(fmax(u0x, -lim), lim));
-            const int wy = oy + (int)floor(fmin(fmax(u0y, -lim), lim));
-            atomicMin(&sBox[0], wx);
-            atomicMax(&sBox[1], wx);
-            atomicMin(&sBox[2], wy);
-            atomicMax(&sBox[3], wy);
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            bx0 = min(bx0, sBox[w][0]);
+            bx1 = max(bx1, sBox[w][1]);
+            by0 = min(by0, sBox[w][2]);
+            by1 = max(by1, sBox[w][3]);
         }
-        __syncthreads();
-        const int RX0 = sBox[0] - kDisMargin, RY0 = sBox[2] - kDisMargin;
-        const int RW = min(sBox[1] + kPatch + 1 + kDisMargin - RX0, kDisRW);
-        const int RH = min(sBox[3] + kPatch + 1 + kDisMargin - RY0, kDisRH);
-        // column-major: a lane's rows of one column are contiguous, so every
-        // read of an iteration is an immediate offset from one address
-        stage_rows_cols<(kDisRH + 7) / 8>(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP, 1);
+        const int RX0 = bx0 - kDisMargin, RY0 = by0 - kDisMargin;
+        const int RW = min(bx1 + kPatch + 1 + kDisMargin - RX0, kDisRW);
+        const int RH = min(by1 + kPatch + 1 + kDisMargin - RY0, kDisRH);
+        // row-major: every read of an iteration is an immediate offset from
+        // one address
+        stage_rows_lds(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP);
+        lds_load_wait();
         __syncthreads();
 
         // ---- inverse-compositional iterations (single precision)
@@ -886,12 +925,12 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
 #pragma unroll
             for (int c = 0; c < CPL; ++c) px[c] = qx[c] = py[c] = qy[c] = 0.f;
             if ((unsigned)rx < (unsigned)(RW - CPL) && (unsigned)ry < (unsigned)(RH - kPatch)) {
-                const float* q = sR + rx * kDisRP + ry;
+                const float* q = sR + ry * kDisRP + rx;
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
                     float a[CPL + 1];
 #pragma unroll
-                    for (int c = 0; c <= CPL; ++c) a[c] = q[c * kDisRP + j];
+                    for (int c = 0; c <= CPL; ++c) a[c] = q[j * kDisRP + c];
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         const float h = a[c] + ax * (a[c + 1] - a[c]);
@@ -995,35 +1034,8 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         const float inv_s = 1.0f / (float)s;
         const Cover cx = cover_of(x, W, g.pnx, s, inv_s), cy = cover_of(y, H, g.pny, s, inv_s);
         const float i0 = I0[pix];
-        float sw = 0.f, su = 0.f, sv = 0.f;
-        // the covering patches in row-major order, kDensChunk at a time: their
-        // displacements, then their samples, are loaded before any is used
-        const int n = cx.n * cy.n;
-        int qx = 0, qy = 0;
-        for (int q0 = 0; q0 < n; q0 += kDensChunk) {
-            float2 u[kDensChunk];
-            DensTap tp[kDensChunk];
-#pragma unroll
-            for (int t = 0; t < kDensChunk; ++t) {
-                if (q0 + t < n) u[t] = pu[(size_t)cover_index(cy, qy) * g.pnx + cover_index(cx, qx)];
-                if (++qx == cx.n) {
-                    qx = 0;
-                    ++qy;
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < kDensChunk; ++t)
-                if (q0 + t < n) tp[t] = dens_fetch(I1, W, H, x, y, u[t].x, u[t].y);
-#pragma unroll
-            for (int t = 0; t < kDensChunk; ++t) {
-                if (q0 + t < n) {
-                    const float w = dens_weight_f(dens_blend(tp[t]) - i0);
-                    sw += w;
-                    su += w * u[t].x;
-                    sv += w * u[t].y;
-                }
-            }
-        }
+        float sw, su, sv;
+        dens_sums(I1, W, H, x, y, i0, pu, g.pnx, cx, cy, sw, su, sv);
         float fu = su / sw, fv = sv / sw;
         const uint8_t m = d->mask ? d->mask[pix] : 1;
         if ((d->flags & EBOF_MASK_FLOW) && !m) fu = fv = 0.f;
