@@ -53,7 +53,9 @@ def parse():
                     help="first run a plain device copy of MIB MiB three times (the reference kernel "
                          "for scaling HBM counters)")
     ap.add_argument("--plain-streams", type=int, default=2,
-                    help="flow streams of the pipelined plain path (preprocessing has its own stream)")
+                    help="flow streams of the pipelined plain path")
+    ap.add_argument("--plain-pre-streams", type=int, default=2,
+                    help="preprocessing streams of the pipelined plain path (windows taken in turn)")
     return ap.parse_args()
 
 
@@ -105,6 +107,53 @@ def dis_flops_window(L, p):
         n = ((w - 8 + p.stride - 1) // p.stride + 1) * ((h - 8 + p.stride - 1) // p.stride + 1)
         tot += n * dis_flops_per_patch(p.iters, l < p.levels - 1)
     return tot
+
+
+def pipelined_driver(lib, h, sptrs, NP, NF, NB, slot0, preprocess, flow_of):
+    """The pipelined plain form: window k binned and turned into its pyramid
+    on preprocessing stream k mod NP, the flow k-1 -> k on flow stream
+    k mod NF once both pyramids are ready, buffers in a ring of NB (window k
+    reuses the buffers of window k-NB once the flows that read them are
+    done).  Streams are ordered by the context's stream counters
+    (ebof_stream_signal / ebof_stream_wait), one per stream from slot0 on:
+    window k's preprocessing stores k+1 into its stream's counter, its flow
+    stores k+1 into the flow stream's.  Returns run(k_lo, k_hi), which issues
+    windows k_lo .. k_hi-1; work issued before k_lo must be complete."""
+    import ctypes
+
+    def check(rc):
+        if rc:
+            raise RuntimeError(lib.ebof_last_error(h).decode())
+
+    seen = [0] * (NP + NF)
+    val = ctypes.c_uint32()
+
+    def flow_done(j):  # the host knows flow j has completed
+        f = NP + j % NF
+        if seen[f] < j + 1:
+            check(lib.ebof_signal_read(h, slot0 + f, ctypes.byref(val)))
+            seen[f] = val.value
+        return seen[f] >= j + 1
+
+    def run(k_lo, k_hi):
+        for i in range(NP + NF):
+            seen[i] = 0
+        for k in range(k_lo, k_hi):
+            i = k % NP
+            for j in (k - NB, k - NB + 1):  # the flows that last read buffer k % NB
+                if j >= max(1, k_lo) and not flow_done(j):
+                    check(lib.ebof_stream_wait(h, slot0 + NP + j % NF, j + 1, sptrs[i]))
+            preprocess(k, i)
+            check(lib.ebof_stream_signal(h, slot0 + i, k + 1, sptrs[i]))
+            if k > 0:
+                f = NP + k % NF
+                if NP > 1 and k - 1 >= k_lo:  # window k-1 was preprocessed on another stream
+                    check(lib.ebof_stream_wait(h, slot0 + (k - 1) % NP, k, sptrs[f]))
+                check(lib.ebof_stream_wait(h, slot0 + i, k + 1, sptrs[f]))
+                flow_of(k, f)
+                check(lib.ebof_stream_signal(h, slot0 + f, k + 1, sptrs[f]))
+
+    return run
 
 
 def main():
@@ -191,21 +240,24 @@ def main():
                         t=torch.from_numpy(ev["t"]).to(dev), t0=ev["t0"], n=len(ev["x"])))
     # The plain path: one camera stream, one window per launch, stage calls
     # only.  Sequential form: everything on one stream, one window at a time.
-    # Pipelined form, the paper's blocks (Fig. 1) as concurrent HIP streams:
-    # binning and EDT/surface/pyramid of every window on stream P, in window
-    # order; the flow k-1 -> k on stream F[k mod NF] after an event recorded
-    # on P behind window k (both pyramids it reads are then ready), so
-    # consecutive windows' flows overlap with each other and with the next
-    # windows' preprocessing.  Buffers form a ring of NB; a window reusing a
-    # buffer waits (on P) for the flows that last read it when the host sees
-    # they have not completed.  One host thread issues everything (the GPU,
-    # not the issue rate, bounds this form).
+    # Pipelined form, the paper's blocks (Fig. 1) as concurrent HIP streams
+    # (pipelined_driver): binning and EDT/surface/pyramid of window k on
+    # stream P[k mod NP], the flow k-1 -> k on stream F[k mod NF] once both
+    # pyramids it reads are ready, so consecutive windows' preprocessing and
+    # flows overlap.  Buffers form a ring of NB.  The streams are ordered by
+    # the context's stream counters (a stream wait on an event recorded on
+    # another stream costs far more host time on this runtime), so one host
+    # thread issues everything faster than the GPU completes it.
     NF = max(1, args.plain_streams)
+    NP = max(1, args.plain_pre_streams)
     NB = 16
     pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(NB)]
     edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(NB)]
     flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NB)]
-    streams = [stream] + [torch.cuda.Stream() for _ in range(NF)]  # P, then the flow streams
+    # the preprocessing streams, then the flow streams: context-owned, a
+    # hardware queue each (streams sharing a queue would run one after the
+    # other)
+    streams = [L.ebof_stream_create(ctx) for _ in range(NP + NF)]
     sptrs = [ctypes.c_void_p(st.cuda_stream) for st in streams]
     pp = ctypes.byref(p)
     vp = ctypes.c_void_p
@@ -242,32 +294,13 @@ def main():
         for st in streams:
             st.synchronize()
 
-    def run_pipelined(k_lo, k_hi):
-        """Windows k_lo .. k_hi-1 in the pipelined form (work issued before
-        k_lo must be complete)."""
-        ev_pre = [torch.cuda.Event() for _ in range(k_hi - k_lo)]
-        ev_flow = {}
-        sp = streams[0]
-        for k in range(k_lo, k_hi):
-            for j in (k - NB, k - NB + 1):  # the flows that last read buffer k % NB
-                e = ev_flow.pop(j, None) if j == k - NB else ev_flow.get(j)
-                if e is not None and not e.query():
-                    sp.wait_event(e)
-            preprocess(k, 0)
-            if k > 0:
-                e = ev_pre[k - k_lo]
-                e.record(sp)
-                sf = streams[1 + k % NF]
-                sf.wait_event(e)
-                flow_of(k, 1 + k % NF)
-                ev_flow[k] = torch.cuda.Event()
-                ev_flow[k].record(sf)
+    run_pipelined = pipelined_driver(lib, h, sptrs, NP, NF, NB, 0, preprocess, flow_of)
 
     # ---------------- EPE against the oracle on the sampled pairs ----------
     epe = None
     if oracle_flows:
         errs = []
-        with torch.cuda.stream(stream):
+        with torch.cuda.stream(streams[0]):
             for k in range(max(oracle_flows) + 1):
                 step(k)
                 if k in oracle_flows:
@@ -317,7 +350,7 @@ def main():
     sync_all()
     torch.cuda.synchronize()
     fps = K / (time.perf_counter() - t0)
-    log(f"plain (pipelined, {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window, "
+    log(f"plain (pipelined, {NP} preprocessing + {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window, "
         f"host issue {issue_ms:.4f} ms/window)")
     elapsed = K / fps
 
@@ -337,10 +370,10 @@ def main():
     e0s = []
     for _ in range(64):
         ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ea.record(stream)
-        eb.record(stream)
+        ea.record(streams[0])
+        eb.record(streams[0])
         e0s.append((ea, eb))
-    stream.synchronize()
+    streams[0].synchronize()
     pair_ms = float(np.median([a.elapsed_time(b) for a, b in e0s]))
     dom_ms_raw = dom_ms
     dom_ms = max(dom_ms_raw - dom_cnt * pair_ms, 1e-9)
@@ -386,6 +419,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
         "plain_flow_streams": NF,
+        "plain_pre_streams": NP,
         "plain_host_issue_ms_per_window": issue_ms,
         "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
@@ -408,7 +442,7 @@ def main():
                                    iters=p1.iters, lam=float(np.float32(p1.lambda_reg))),
                    rs[0]["Edf"].astype(bool))
     if c1:
-        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, NF, c1_pair)
+        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, streams, NP, NF, c1_pair)
 
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
@@ -421,7 +455,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_c1(L, ctx, c1, steps, dev, nf, oracle_pair):
+def bench_c1(L, ctx, c1, steps, dev, streams, NP, NF, oracle_pair):
+    """The 346x260 plain path, sequential and pipelined, on the 1280x720
+    section's streams (NP preprocessing, then NF flow streams)."""
     """346x260 plain path (the low-resolution config): sequential and
     pipelined rates over the C1 stream's windows, and the EPE against the
     oracle on its first pair (oracle_pair: (flow, mask) or None)."""
@@ -436,7 +472,6 @@ def bench_c1(L, ctx, c1, steps, dev, nf, oracle_pair):
     flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NB)]
     evs = [dict(x=torch.from_numpy(w["x"]).to(dev), y=torch.from_numpy(w["y"]).to(dev),
                 t=torch.from_numpy(w["t"]).to(dev), t0=w["t0"], n=len(w["x"])) for w in c1]
-    streams = [torch.cuda.Stream() for _ in range(nf + 1)]
     sp = [ctypes.c_void_p(st.cuda_stream) for st in streams]
     lib, h = ctx.lib, ctx.handle
     vp, pp = ctypes.c_void_p, ctypes.byref(p)
@@ -478,33 +513,20 @@ def bench_c1(L, ctx, c1, steps, dev, nf, oracle_pair):
     streams[0].synchronize()
     fps_seq = steps / (time.perf_counter() - t0)
     k0 = 12 + steps
-    ev_flow = {}
+    # its own counters (slots 16..), so values stored here never fall below
+    # those of the 1280x720 section on the same context
+    pipelined = pipelined_driver(lib, h, sp, NP, NF, NB, 16, pre, flw)
 
-    def pipelined(lo, hi):
-        for k in range(lo, hi):
-            for j in (k - NB, k - NB + 1):
-                e = ev_flow.pop(j, None) if j == k - NB else ev_flow.get(j)
-                if e is not None and not e.query():
-                    streams[0].wait_event(e)
-            pre(k, 0)
-            e = torch.cuda.Event()
-            e.record(streams[0])
-            fi = 1 + k % nf
-            streams[fi].wait_event(e)
-            flw(k, fi)
-            ev_flow[k] = torch.cuda.Event()
-            ev_flow[k].record(streams[fi])
-
-    pipelined(k0, k0 + 4 * nf)
+    pipelined(k0, k0 + 4 * NF)
     torch.cuda.synchronize()
-    k0 += 4 * nf
+    k0 += 4 * NF
     t0 = time.perf_counter()
     pipelined(k0, k0 + steps)
     torch.cuda.synchronize()
     fps = steps / (time.perf_counter() - t0)
     res = {"workload": "346x260 plain single camera stream, 20k events per window, 40 segments translating "
                        "(+2.5, -1.5) px per window, 5% noise, L=3",
-           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "flow_streams": nf,
+           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "pre_streams": NP, "flow_streams": NF,
            "epe_vs_oracle_px": epe}
     log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined; EPE vs oracle {epe}")
     return res

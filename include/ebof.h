@@ -260,6 +260,44 @@ int ebof_poll(ebof_ctx *ctx, uint64_t ticket, int32_t *status, int64_t *latency_
 /* Blocks until every submitted window has completed. */
 int ebof_drain(ebof_ctx *ctx);
 
+/* ---- cross-stream ordering ----------------------------------------------------
+ * For callers that pipeline stage calls over several HIP streams (binning
+ * and the distance surface of window k on one stream, the flow k-1 -> k on
+ * another, after both pyramids are ready; the blocks of Fig. 1 running
+ * concurrently).  A context owns EBOF_SIGNAL_SLOTS 32-bit counters in
+ * host-visible signal memory, all 0 at creation.
+ *
+ * ebof_stream_signal: enqueues on hip_stream the store of value into counter
+ * slot; it takes effect after all work issued to that stream before it has
+ * completed (that work's results are then visible to any stream).
+ * ebof_stream_wait: work issued to hip_stream after this call starts only
+ * once counter slot holds a value >= value (unsigned).  The caller owns the
+ * protocol: a value waited for must be stored by a signal already issued (or
+ * issued later on a stream that does not itself wait on this one); a wait
+ * for a value that is never stored blocks the stream for good.  Values
+ * stored into a slot must not decrease.
+ * ebof_signal_read: the counter's value as the host sees it now (a wait on a
+ * value <= it would not block, so a caller may skip issuing it).
+ * Each call is one stream operation (host cost a few us, a fraction of an
+ * event record plus a cross-stream event wait).  EBOF_E_INVAL for a slot out
+ * of range or a NULL output.  Streams using the counters must be idle before
+ * ebof_destroy. */
+#define EBOF_SIGNAL_SLOTS 64
+int ebof_stream_signal(ebof_ctx *ctx, int32_t slot, uint32_t value, void *hip_stream);
+int ebof_stream_wait(ebof_ctx *ctx, int32_t slot, uint32_t value, void *hip_stream);
+int ebof_signal_read(ebof_ctx *ctx, int32_t slot, uint32_t *value);
+
+/* Creates a HIP stream for such pipelining, owned by the context (destroyed
+ * by ebof_destroy; at most EBOF_MAX_OWNED_STREAMS per context), and stores
+ * it in *hip_stream.  The stream is created with a CU mask covering every
+ * compute unit, which the HIP runtime backs with a hardware queue of its
+ * own: streams that share a hardware queue run one after the other, and a
+ * stream wait at the head of a shared queue also holds up the other
+ * streams' work behind it.  EBOF_E_INVAL for a NULL output, EBOF_E_STATE
+ * when the context owns the maximum already. */
+#define EBOF_MAX_OWNED_STREAMS 16
+int ebof_stream_create(ebof_ctx *ctx, void **hip_stream);
+
 /* ---- measurement -------------------------------------------------------------
  * Kernel timing: when enabled, every launch of a selected kernel is
  * bracketed by a pair of HIP events recorded on its stream right before and

@@ -31,6 +31,8 @@ EBOF_TUNE_OFF = 0
 EBOF_TUNE_AUTO = 1
 EBOF_TUNE_LEVELS = 8   # lanes-per-patch values per cache line (one per level)
 EBOF_TUNE_STAGES = 22  # block counts per cache line (one per internal stage)
+EBOF_SIGNAL_SLOTS = 64
+EBOF_MAX_OWNED_STREAMS = 16
 
 KERNELS = ["scatter", "denoise_fill", "pack_cols", "edt_cols", "edt_rows", "pyr_down",
            "dis_level", "densify"]
@@ -113,6 +115,10 @@ def load():
                          ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "ebof_poll": ([P, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
         "ebof_drain": ([P], ctypes.c_int),
+        "ebof_stream_signal": ([P, i32, u32, P], ctypes.c_int),
+        "ebof_stream_wait": ([P, i32, u32, P], ctypes.c_int),
+        "ebof_signal_read": ([P, i32, ctypes.POINTER(u32)], ctypes.c_int),
+        "ebof_stream_create": ([P, ctypes.POINTER(P)], ctypes.c_int),
         "ebof_timing_enable": ([P, u32], ctypes.c_int),
         "ebof_timing_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
                              ctypes.c_int),
@@ -131,6 +137,7 @@ def exported_symbols():
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
             "ebof_bin_events", "ebof_edt_surface", "ebof_flow", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
+            "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
 
 
@@ -320,6 +327,33 @@ def ebof_run_batch(ctx, windows, stream=None):
         a.flow_out = _dev(w.get("flow_out"), torch.float32, 2 * N, "flow_out", optional=not need_flow)
         a.n_dropped_dev = _dev(w.get("n_dropped"), torch.uint64, 1, "n_dropped", optional=True)
     return _check(ctx.handle, ctx.lib.ebof_run_batch(ctx.handle, arr, n, _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# cross-stream ordering
+# --------------------------------------------------------------------------
+def ebof_stream_signal(ctx, slot, value, stream=None):
+    return _check(ctx.handle, ctx.lib.ebof_stream_signal(ctx.handle, int(slot), int(value) & 0xFFFFFFFF,
+                                                         _stream(stream)))
+
+
+def ebof_stream_wait(ctx, slot, value, stream=None):
+    return _check(ctx.handle, ctx.lib.ebof_stream_wait(ctx.handle, int(slot), int(value) & 0xFFFFFFFF,
+                                                       _stream(stream)))
+
+
+def ebof_signal_read(ctx, slot):
+    v = ctypes.c_uint32()
+    _check(ctx.handle, ctx.lib.ebof_signal_read(ctx.handle, int(slot), ctypes.byref(v)))
+    return v.value
+
+
+def ebof_stream_create(ctx):
+    """A context-owned HIP stream on a hardware queue of its own, wrapped as a
+    torch stream (valid until the context is closed)."""
+    s = ctypes.c_void_p()
+    _check(ctx.handle, ctx.lib.ebof_stream_create(ctx.handle, ctypes.byref(s)))
+    return torch.cuda.ExternalStream(s.value)
 
 
 def ebof_timing_enable(ctx, kernels):

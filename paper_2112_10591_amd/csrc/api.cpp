@@ -832,10 +832,112 @@ int ebof_create(int device, void* arena, size_t arena_bytes, ebof_ctx** out) {
     return EBOF_OK;
 }
 
+namespace {
+// Signal memory is never freed: the command processor reads it, and a
+// process keeps the few words it ever allocated for reuse by later contexts.
+std::mutex g_signal_pool_mu;
+std::vector<uint32_t*> g_signal_pool;
+
+int signal_slot(ebof_ctx* ctx, int32_t slot, uint32_t** out) {
+    if (slot < 0 || slot >= EBOF_SIGNAL_SLOTS) {
+        set_error("signal slot out of range");
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->signal_mu);
+    if (!ctx->signals[slot]) {
+        uint32_t* p = nullptr;
+        {
+            std::lock_guard<std::mutex> pk(g_signal_pool_mu);
+            if (!g_signal_pool.empty()) {
+                p = g_signal_pool.back();
+                g_signal_pool.pop_back();
+            }
+        }
+        if (!p) {
+            void* v = nullptr;
+            int rc = check_hip(ctx, hipExtMallocWithFlags(&v, 8, hipMallocSignalMemory), "hipExtMallocWithFlags(signal)");
+            if (rc) return rc;
+            p = (uint32_t*)v;
+        }
+        *(volatile uint32_t*)p = 0u;  // host-visible memory; no stream has used it yet
+        ctx->signals[slot] = p;
+    }
+    *out = ctx->signals[slot];
+    return EBOF_OK;
+}
+}  // namespace
+
+int ebof_stream_signal(ebof_ctx* ctx, int32_t slot, uint32_t value, void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    uint32_t* p = nullptr;
+    if ((rc = signal_slot(ctx, slot, &p))) return rc;
+    return check_hip(ctx, hipStreamWriteValue32((hipStream_t)hip_stream, p, value, 0), "hipStreamWriteValue32");
+}
+
+int ebof_stream_wait(ebof_ctx* ctx, int32_t slot, uint32_t value, void* hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    uint32_t* p = nullptr;
+    if ((rc = signal_slot(ctx, slot, &p))) return rc;
+    return check_hip(ctx,
+                     hipStreamWaitValue32((hipStream_t)hip_stream, p, value, hipStreamWaitValueGte, 0xffffffffu),
+                     "hipStreamWaitValue32");
+}
+
+int ebof_signal_read(ebof_ctx* ctx, int32_t slot, uint32_t* value) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if (!value) {
+        set_error("ebof_signal_read: NULL output");
+        return EBOF_E_INVAL;
+    }
+    uint32_t* p = nullptr;
+    if ((rc = signal_slot(ctx, slot, &p))) return rc;
+    *value = *(volatile uint32_t*)p;
+    return EBOF_OK;
+}
+
+int ebof_stream_create(ebof_ctx* ctx, void** hip_stream) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if (!hip_stream) {
+        set_error("ebof_stream_create: NULL output");
+        return EBOF_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->signal_mu);
+    if (ctx->owned_streams.size() >= (size_t)EBOF_MAX_OWNED_STREAMS) {
+        set_error("ebof_stream_create: the context owns the maximum number of streams");
+        return EBOF_E_STATE;
+    }
+    int ncu = 0;
+    if ((rc = check_hip(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device),
+                        "hipDeviceGetAttribute")))
+        return rc;
+    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0xffffffffu);
+    hipStream_t st = nullptr;
+    if ((rc = check_hip(ctx, hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()),
+                        "hipExtStreamCreateWithCUMask")))
+        return rc;
+    ctx->owned_streams.push_back(st);
+    *hip_stream = (void*)st;
+    return EBOF_OK;
+}
+
 int ebof_destroy(ebof_ctx* ctx) {
     if (!ctx) return EBOF_OK;
     serve_shutdown(ctx);
     (void)hipDeviceSynchronize();
+    for (hipStream_t st : ctx->owned_streams) (void)hipStreamDestroy(st);
+    ctx->owned_streams.clear();
+    {
+        std::lock_guard<std::mutex> pk(g_signal_pool_mu);
+        for (uint32_t*& p : ctx->signals)
+            if (p) {
+                g_signal_pool.push_back(p);
+                p = nullptr;
+            }
+    }
     runner_release(ctx->batch);
     for (auto& v : ctx->timed)
         for (auto& tp : v) {

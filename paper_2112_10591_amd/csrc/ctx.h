@@ -115,6 +115,12 @@ struct ebof_ctx {
     std::vector<hipEvent_t> event_pool;
 
     ebof::ServeState* serve = nullptr;  // owned; released by serve_shutdown
+
+    // cross-stream ordering counters (signal memory, taken lazily from a
+    // process-wide pool and returned to it by ebof_destroy)
+    std::mutex signal_mu;
+    uint32_t* signals[EBOF_SIGNAL_SLOTS] = {};
+    std::vector<hipStream_t> owned_streams;  // ebof_stream_create (guarded by signal_mu)
 };
 
 namespace ebof {

@@ -689,7 +689,7 @@ __device__ __forceinline__ void dens_sums(const float* __restrict__ I1, int W, i
 }
 constexpr int kDisRW = 112;   // LDS search region, columns
 constexpr int kDisRH = 68;    // LDS search region, rows
-constexpr int kDisRP = 113;   // ... stored row-major with this (odd) pitch
+constexpr int kDisRP = 128;   // ... stored row-major with this pitch
 constexpr int kDisMargin = kPatch + 6;  // around the initial windows: covers a patch
                                         // that drifts up to this far in an iteration
 
@@ -926,11 +926,16 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             for (int c = 0; c < CPL; ++c) px[c] = qx[c] = py[c] = qy[c] = 0.f;
             if ((unsigned)rx < (unsigned)(RW - CPL) && (unsigned)ry < (unsigned)(RH - kPatch)) {
                 const float* q = sR + ry * kDisRP + rx;
+                // all samples read before any is used (one LDS round trip)
+                float A[kPatch + 1][CPL + 1];
+#pragma unroll
+                for (int j = 0; j <= kPatch; ++j)
+#pragma unroll
+                    for (int c = 0; c <= CPL; ++c) A[j][c] = q[j * kDisRP + c];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int j = 0; j <= kPatch; ++j) {
-                    float a[CPL + 1];
-#pragma unroll
-                    for (int c = 0; c <= CPL; ++c) a[c] = q[j * kDisRP + c];
+                    const float* a = A[j];
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         const float h = a[c] + ax * (a[c + 1] - a[c]);

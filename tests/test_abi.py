@@ -73,3 +73,13 @@ def test_set_tuning_rejects_null_context():
     lib = L.load()
     assert lib.ebof_set_tuning(None, L.EBOF_TUNE_AUTO, None) == L.EBOF_E_INVAL
 
+
+def test_stream_signals_reject_null_context():
+    lib = L.load()
+    assert lib.ebof_stream_signal(None, 0, 1, None) == L.EBOF_E_INVAL
+    assert lib.ebof_stream_wait(None, 0, 1, None) == L.EBOF_E_INVAL
+    v = __import__("ctypes").c_uint32()
+    assert lib.ebof_signal_read(None, 0, __import__("ctypes").byref(v)) == L.EBOF_E_INVAL
+    st = __import__("ctypes").c_void_p()
+    assert lib.ebof_stream_create(None, __import__("ctypes").byref(st)) == L.EBOF_E_INVAL
+

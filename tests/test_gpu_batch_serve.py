@@ -248,6 +248,59 @@ def test_stage_calls_pipelined_over_streams(ctx):
                     assert torch.equal(out[k][i], ref[k][i]), (W, k, name)
 
 
+def test_stage_calls_ordered_by_stream_signals():
+    """The pipelined plain form ordered by context counters instead of
+    events, on context-owned streams: window k preprocessed on stream k mod 2, which then stores k+1
+    into counter k mod 2; the flow k-1 -> k on flow stream k mod 2 waits for
+    counter (k-1) mod 2 >= k and counter k mod 2 >= k+1.  Every output equals
+    the sequential stage calls' and the counters end at the last values
+    stored."""
+    c = L.ebof_create(arena_bytes=1 << 30)
+    try:
+        with pytest.raises(L.EbofError):
+            L.ebof_stream_signal(c, L.EBOF_SIGNAL_SLOTS, 1)
+        with pytest.raises(L.EbofError):
+            L.ebof_stream_wait(c, -1, 1)
+        assert L.ebof_signal_read(c, 5) == 0
+        owned = [L.ebof_stream_create(c) for _ in range(4)]  # a hardware queue each
+        for p, evs in mixed_streams(n_low=1, n_hd=1, windows=5):
+            ref = alone(c, p, evs)
+            W, H = p.width, p.height
+            P = L.ebof_pyramid_floats(p)
+            pre = owned[:2]
+            fl = owned[2:]
+            base = max(L.ebof_signal_read(c, i) for i in range(4))
+            out = []
+            for k, ev in enumerate(evs):
+                st = pre[k % 2]
+                e = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+                d2 = torch.empty(W * H, dtype=torch.int32, device="cuda")
+                pr = torch.empty(P, dtype=torch.float32, device="cuda")
+                L.ebof_bin_events(c, p, ev["x"], ev["y"], ev["t"], ev["t0"], e, stream=st)
+                L.ebof_edt_surface(c, p, e, pr, d2, stream=st)
+                L.ebof_stream_signal(c, k % 2, base + k + 1, stream=st)
+                f = None
+                if k > 0:
+                    sf = fl[k % 2]
+                    L.ebof_stream_wait(c, (k - 1) % 2, base + k, stream=sf)
+                    L.ebof_stream_wait(c, k % 2, base + k + 1, stream=sf)
+                    f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+                    L.ebof_flow(c, p, out[k - 1][1], pr, f, mask=out[k - 1][0], stream=sf)
+                    L.ebof_stream_signal(c, 2 + k % 2, base + k + 1, stream=sf)
+                out.append((e, pr, d2, f))
+            torch.cuda.synchronize()
+            n = len(evs)
+            _say(f"signal-ordered {W}x{H}: {n} windows")
+            assert L.ebof_signal_read(c, (n - 1) % 2) == base + n
+            assert L.ebof_signal_read(c, 2 + (n - 1) % 2) == base + n
+            for k in range(n):
+                for i, name in enumerate(("edge", "pyramid", "d2", "flow")):
+                    if out[k][i] is not None:
+                        assert torch.equal(out[k][i], ref[k][i]), (W, k, name)
+    finally:
+        c.close()
+
+
 def test_serving_alone_vs_mix(ctx):
     streams = mixed_streams(n_low=4, n_hd=2, windows=4)
     ref = [alone(ctx, p, evs) for p, evs in streams]
