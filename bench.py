@@ -52,6 +52,12 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the reference kernel "
                          "for scaling HBM counters)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="write profiles/kernels_1280x720_plain.md from a rocprofv3 kernel trace of "
+                         "PROFILE_CMD and that run's bench.py line, then exit (no GPU needed)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md from the "
+                         "FETCH_SIZE and WRITE_SIZE passes over PROFILE_CMD --copy-calib 256, then exit")
     ap.add_argument("--plain-streams", type=int, default=2,
                     help="flow streams of the pipelined plain path")
     ap.add_argument("--plain-pre-streams", type=int, default=2,
@@ -68,6 +74,131 @@ def dis_flops_per_patch(iters, init):
     # patch; set-up per pixel: template gradient 4 + Hessian 6; init from the
     # coarser level ~4 covering patches x 40.
     return iters * (64 * 11 + 8) + 64 * 10 + (160 if init else 0)
+
+
+# The command the committed profiles are taken over (the plain 1280x720 path;
+# its sequential form times every kernel alone).
+PROFILE_CMD = ("python3 bench.py --steps 60 --warmup 6 --no-cpu-baseline --no-serving --no-batched "
+               "--no-c1")
+
+
+def _csv_rows(d, name):
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(d, "**", name), recursive=True)
+    if not paths:
+        raise SystemExit(f"no {name} under {d}")
+    with open(paths[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(trace_dir, bench_json):
+    """profiles/kernels_1280x720_plain.md: per-kernel dispatch statistics of a
+    `rocprofv3 --kernel-trace --stats` run of PROFILE_CMD, and the live
+    per-launch time of the dominant kernel from that run's bench.py line."""
+    import collections
+    agg = collections.OrderedDict()
+    for r in _csv_rows(trace_dir, "run_kernel_trace.csv"):
+        name = r["Kernel_Name"]
+        if "ebof::" not in name:
+            continue
+        short = name.replace("void ebof::", "").split("(")[0]
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg.setdefault(short, [0, 0.0, 1e18, 0.0])
+        a[0] += 1
+        a[1] += dur
+        a[2] = min(a[2], dur)
+        a[3] = max(a[3], dur)
+    with open(bench_json) as f:
+        line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
+    roof = json.loads(line)["roofline"]
+    tot = sum(a[1] for a in agg.values())
+    dis = [a for k, a in agg.items() if k.startswith("k_dis_level")]
+    dn, dt = sum(a[0] for a in dis), sum(a[1] for a in dis)
+    out = ["# Kernel time, 1280x720 plain path (C2 windows)", "",
+           "Command (from the repository root, `TMPDIR=/tmp`):", "", "```",
+           f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o run -- {PROFILE_CMD}",
+           "```", "",
+           "| kernel | dispatches | total µs | avg µs | min µs | max µs | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k}` | {a[0]} | {a[1]:.1f} | {a[1] / a[0]:.2f} | {a[2]:.2f} | {a[3]:.2f} | "
+                   f"{100 * a[1] / tot:.1f} |")
+    out += ["", "`k_dis_level` runs one launch per pyramid level (`<false, 8>`: 8 lanes per patch, levels "
+            "3, 2, 1; `<false, 4>`: 4 lanes, level 0).",
+            f"Over all of its dispatches the average is {dt / dn:.2f} µs per launch ({dt:.1f} µs / {dn} launches).",
+            "", "The same run's `bench.py` line measures it live in the sequential form, each launch bracketed by "
+            f"a pair of HIP events on its stream: {1e3 * roof['ms_per_launch_raw']:.2f} µs per launch raw, minus "
+            f"the cost of an empty pair on that stream ({1e3 * roof['event_pair_ms']:.2f} µs), "
+            f"{1e3 * roof['ms_per_launch']:.2f} µs per launch over {roof['launches']} launches. The difference "
+            "from the trace is each launch's own dispatch latency inside its bracket, which a trace does not "
+            "count; the roofline uses the live (larger, so conservative) figure."]
+    path = os.path.join(ROOT, "profiles", "kernels_1280x720_plain.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(f"wrote {path}")
+
+
+def summarize_traffic(fetch_dir, write_dir):
+    """profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md: HBM
+    bytes per launch from a FETCH_SIZE and a WRITE_SIZE pass over PROFILE_CMD
+    --copy-calib 256, each scaled by the same counter on the 256 MiB copy
+    (one copyBuffer dispatch reading and writing 262144 KiB)."""
+    import collections
+
+    def load(d, counter):
+        agg, calib = collections.defaultdict(list), []
+        for r in _csv_rows(d, "run_counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            n = r["Kernel_Name"]
+            if "copyBuffer" in n and int(r["Grid_Size"]) >= 131072:
+                calib.append(float(r["Counter_Value"]))
+            if "ebof::" in n:
+                agg[n.split("(")[0].replace("void ebof::", "").split("<")[0]].append(float(r["Counter_Value"]))
+        if not calib:
+            raise SystemExit(f"no 256 MiB copy dispatch in {d} (run with --copy-calib 256)")
+        return agg, sum(calib) / len(calib)
+
+    fa, fc = load(fetch_dir, "FETCH_SIZE")
+    wa, wc = load(write_dir, "WRITE_SIZE")
+    copy_kib = 256 * 1024
+    ff, wf = copy_kib / fc, copy_kib / wc
+    with open(os.path.join(ROOT, "paper_2112_10591_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"workload": "1280x720 plain (bench.py sequential and pipelined forms)", "kernels_hip_sha256": sha,
+           "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 256 MiB)",
+                           "bytes_read": copy_kib * 1024, "bytes_written": copy_kib * 1024,
+                           "fetch_kib_measured": fc, "write_kib_measured": wc,
+                           "fetch_factor": ff, "write_factor": wf},
+           "kernels": {}}
+    cmd = f"{PROFILE_CMD} --copy-calib 256"
+    md = ["# HBM traffic per launch, 1280x720 plain path (C2 windows)", "",
+          "Commands (from the repository root, `TMPDIR=/tmp`), one counter per run:", "", "```",
+          f"timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- {cmd}",
+          f"timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- {cmd}",
+          "python3 bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write", "```", "",
+          "`--copy-calib 256` first copies 256 MiB with `torch.Tensor.copy_` (one `__amd_rocclr_copyBuffer` "
+          "dispatch reading and writing 262144 KiB), three times. On that dispatch the counters read "
+          f"FETCH_SIZE = {fc:.1f} KiB and WRITE_SIZE = {wc:.1f} KiB, so the path's counts are scaled by "
+          f"{ff:.4f} (fetch) and {wf:.4f} (write).", "",
+          f"Kernel source: `paper_2112_10591_amd/csrc/kernels.hip` sha256 `{sha[:16]}…` (bench.py reports "
+          "`traffic` only while the source still has this hash).", "",
+          "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MB | HBM write MB | total MB / launch |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in fa:
+        f_ = sum(fa[k]) / len(fa[k])
+        w_ = sum(wa[k]) / len(wa[k]) if wa.get(k) else 0.0
+        b = (f_ * ff + w_ * wf) * 1024
+        rec["kernels"][k] = {"dispatches": len(fa[k]), "fetch_kib_per_launch": f_, "write_kib_per_launch": w_,
+                             "hbm_bytes_per_launch": b}
+        md.append(f"| `{k}` | {len(fa[k])} | {f_:.1f} | {w_:.1f} | {f_ * ff / 1024:.2f} | {w_ * wf / 1024:.2f} | "
+                  f"{b / 1e6:.2f} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic_1280x720_plain.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md")
 
 
 def measured_traffic(kernel):
@@ -158,6 +289,12 @@ def pipelined_driver(lib, h, sptrs, NP, NF, NB, slot0, preprocess, flow_of):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path shards by camera stream: one context per GPU)", file=sys.stderr)

@@ -690,8 +690,10 @@ __device__ __forceinline__ void dens_sums(const float* __restrict__ I1, int W, i
 constexpr int kDisRW = 112;   // LDS search region, columns
 constexpr int kDisRH = 68;    // LDS search region, rows
 constexpr int kDisRP = 128;   // ... stored row-major with this pitch
-constexpr int kDisMargin = kPatch + 6;  // around the initial windows: covers a patch
-                                        // that drifts up to this far in an iteration
+constexpr int kDisMargin = kPatch + 6;   // around the initial windows: covers a patch
+                                         // that drifts up to this far in an iteration
+constexpr int kDisMargin0 = kPatch + 2;  // ... at level 0, where the initial displacement
+                                         // (from a level of twice the resolution) drifts less
 
 // Copies the h x w window of img at (x0, y0), indices clamped into the image
 // (replicated border), into LDS row-major with pitch p: element (r, c) at
@@ -902,9 +904,10 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
             by0 = min(by0, sBox[w][2]);
             by1 = max(by1, sBox[w][3]);
         }
-        const int RX0 = bx0 - kDisMargin, RY0 = by0 - kDisMargin;
-        const int RW = min(bx1 + kPatch + 1 + kDisMargin - RX0, kDisRW);
-        const int RH = min(by1 + kPatch + 1 + kDisMargin - RY0, kDisRH);
+        const int mg = level == 0 ? kDisMargin0 : kDisMargin;
+        const int RX0 = bx0 - mg, RY0 = by0 - mg;
+        const int RW = min(bx1 + kPatch + 1 + mg - RX0, kDisRW);
+        const int RH = min(by1 + kPatch + 1 + mg - RY0, kDisRH);
         // row-major: every read of an iteration is an immediate offset from
         // one address
         stage_rows_lds(sR, I1, Wl, Hl, RX0, RY0, RW, RH, kDisRP);
