@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md from the "
                          "FETCH_SIZE and WRITE_SIZE passes over PROFILE_CMD --copy-calib 256, then exit")
+    ap.add_argument("--sequential-only", action="store_true",
+                    help="time only the sequential plain form (value = its rate); for counter runs, "
+                         "whose per-dispatch serialisation does not mix with cross-stream waits")
     ap.add_argument("--plain-streams", type=int, default=2,
                     help="flow streams of the pipelined plain path")
     ap.add_argument("--plain-pre-streams", type=int, default=2,
@@ -79,7 +82,7 @@ def dis_flops_per_patch(iters, init):
 # The command the committed profiles are taken over (the plain 1280x720 path;
 # its sequential form times every kernel alone).
 PROFILE_CMD = ("python3 bench.py --steps 60 --warmup 6 --no-cpu-baseline --no-serving --no-batched "
-               "--no-c1")
+               "--no-c1 --sequential-only")
 
 
 def _csv_rows(d, name):
@@ -477,18 +480,22 @@ def main():
     dom_ms, dom_cnt = L.ebof_timing_read(ctx, dominant)
     lib.ebof_timing_enable(h, 0)
     log(f"plain (1 stream): {fps_seq:.1f} frames/s ({1e3 / fps_seq:.4f} ms/window)")
-    run_pipelined(Wm + K, Wm + K + 4 * NF)  # untimed: streams warm
-    sync_all()
-    k0 = Wm + K + 4 * NF
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_pipelined(k0, k0 + K)
-    issue_ms = (time.perf_counter() - t0) * 1e3 / K  # host time to issue a window
-    sync_all()
-    torch.cuda.synchronize()
-    fps = K / (time.perf_counter() - t0)
-    log(f"plain (pipelined, {NP} preprocessing + {NF} flow streams): {fps:.1f} frames/s ({1e3 / fps:.4f} ms/window, "
-        f"host issue {issue_ms:.4f} ms/window)")
+    k0 = Wm + K
+    if args.sequential_only:
+        fps, issue_ms = fps_seq, None
+    else:
+        run_pipelined(Wm + K, Wm + K + 4 * NF)  # untimed: streams warm
+        sync_all()
+        k0 = Wm + K + 4 * NF
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_pipelined(k0, k0 + K)
+        issue_ms = (time.perf_counter() - t0) * 1e3 / K  # host time to issue a window
+        sync_all()
+        torch.cuda.synchronize()
+        fps = K / (time.perf_counter() - t0)
+        log(f"plain (pipelined, {NP} preprocessing + {NF} flow streams): {fps:.1f} frames/s "
+            f"({1e3 / fps:.4f} ms/window, host issue {issue_ms:.4f} ms/window)")
     elapsed = K / fps
 
     # ---------------- unloaded per-window latency (plain) -------------------
@@ -555,6 +562,7 @@ def main():
                    "levels": p.levels},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
+        "plain_form": "sequential" if args.sequential_only else "pipelined",
         "plain_flow_streams": NF,
         "plain_pre_streams": NP,
         "plain_host_issue_ms_per_window": issue_ms,
