@@ -379,7 +379,8 @@ def main():
         evs.append(dict(x=torch.from_numpy(ev["x"]).to(dev), y=torch.from_numpy(ev["y"]).to(dev),
                         t=torch.from_numpy(ev["t"]).to(dev), t0=ev["t0"], n=len(ev["x"])))
     # The plain path: one camera stream, one window per launch, stage calls
-    # only.  Sequential form: everything on one stream, one window at a time.
+    # only (ebof_window_surface, then ebof_flow from the previous window).
+    # Sequential form: everything on one stream, one window at a time.
     # Pipelined form, the paper's blocks (Fig. 1) as concurrent HIP streams
     # (pipelined_driver): binning and EDT/surface/pyramid of window k on
     # stream P[k mod NP], the flow k-1 -> k on stream F[k mod NF] once both
@@ -418,8 +419,7 @@ def main():
     def preprocess(k, si):
         x, y, t, n, t0 = prepared[k % len(prepared)]
         b = k % NB
-        check(lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[b], None, sptrs[si]))
-        check(lib.ebof_edt_surface(h, pp, edge_p[b], None, pyr_p[b], sptrs[si]))
+        check(lib.ebof_window_surface(h, pp, x, y, t, n, t0, edge_p[b], None, None, pyr_p[b], sptrs[si]))
 
     def flow_of(k, si):
         b, bp = k % NB, (k - 1) % NB
@@ -631,8 +631,7 @@ def bench_c1(L, ctx, c1, steps, dev, streams, NP, NF, oracle_pair):
 
     def pre(k, si):
         x, y, t, n, t0 = prep[k % len(prep)]
-        check(lib.ebof_bin_events(h, pp, x, y, t, n, t0, edge_p[k % NB], None, sp[si]))
-        check(lib.ebof_edt_surface(h, pp, edge_p[k % NB], None, pyr_p[k % NB], sp[si]))
+        check(lib.ebof_window_surface(h, pp, x, y, t, n, t0, edge_p[k % NB], None, None, pyr_p[k % NB], sp[si]))
 
     def flw(k, si):
         b, bp = k % NB, (k - 1) % NB

@@ -130,7 +130,7 @@ const char *ebof_last_error(const ebof_ctx *ctx);
  * in that order.  Only the caller's own buffers carry data
  * from one call to the next (edge image, pyramid), so a window's stages may
  * run on one stream and the flow that reads its pyramid on another, ordered
- * by a HIP event. */
+ * by a HIP event or the context's stream counters (below). */
 
 /* Sec. III-A + III-B: bins the events with t0_us <= t < t0_us + dt_us into a
  * binary edge image (polarity is not an input; events off the sensor or off
@@ -155,6 +155,17 @@ int ebof_bin_events(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
 int ebof_edt_surface(ebof_ctx *ctx, const ebof_params *p,
                      const uint8_t *edge, int32_t *d2_out, float *pyr_out,
                      void *hip_stream);
+
+/* Sec. III-A to III-C in one call: ebof_bin_events into edge_out followed by
+ * ebof_edt_surface of edge_out, with the same arguments, outputs and errors,
+ * on one stream; the column masks the distance transform starts from are
+ * formed while the edge image is written (one launch and one call fewer
+ * than the two calls). */
+int ebof_window_surface(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
+                        const uint16_t *y, const int64_t *t, int64_t n,
+                        int64_t t0_us, uint8_t *edge_out,
+                        uint64_t *n_dropped_dev, int32_t *d2_out,
+                        float *pyr_out, void *hip_stream);
 
 /* Sec. III-D: dense flow from the surface pyramid of window k-1 (pyr_prev,
  * the reference) to that of window k (pyr_curr), both device, P floats, by

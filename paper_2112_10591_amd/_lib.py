@@ -106,6 +106,7 @@ def load():
         "ebof_last_error": ([P], ctypes.c_char_p),
         "ebof_bin_events": ([P, pp, P, P, P, i64, i64, P, P, P], ctypes.c_int),
         "ebof_edt_surface": ([P, pp, P, P, P, P], ctypes.c_int),
+        "ebof_window_surface": ([P, pp, P, P, P, i64, i64, P, P, P, P, P], ctypes.c_int),
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
         "ebof_set_tuning": ([P, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
@@ -135,7 +136,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_flow", "ebof_run_batch", "ebof_set_tuning",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
@@ -267,6 +268,20 @@ def ebof_edt_surface(ctx, p, edge, pyr_out, d2_out=None, stream=None):
     pd = _dev(d2_out, torch.int32, N, "d2_out", optional=True)
     return _check(ctx.handle, ctx.lib.ebof_edt_surface(ctx.handle, ctypes.byref(p), pe, pd, pp,
                                                        _stream(stream)))
+
+
+def ebof_window_surface(ctx, p, x, y, t, t0_us, edge_out, pyr_out, d2_out=None, n_dropped=None, stream=None):
+    n = int(x.numel())
+    N = p.width * p.height
+    px = _dev(x, torch.uint16, n, "x")
+    py = _dev(y, torch.uint16, n, "y")
+    pt = _dev(t, torch.int64, n, "t")
+    pe = _dev(edge_out, torch.uint8, N, "edge_out")
+    pn = _dev(n_dropped, torch.uint64, 1, "n_dropped", optional=True)
+    pd = _dev(d2_out, torch.int32, N, "d2_out", optional=True)
+    pp = _dev(pyr_out, torch.float32, ebof_pyramid_floats(p), "pyr_out")
+    return _check(ctx.handle, ctx.lib.ebof_window_surface(ctx.handle, ctypes.byref(p), px, py, pt, n, int(t0_us),
+                                                          pe, pn, pd, pp, _stream(stream)))
 
 
 def ebof_flow(ctx, p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):

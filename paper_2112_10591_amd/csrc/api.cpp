@@ -951,39 +951,45 @@ int ebof_destroy(ebof_ctx* ctx) {
 
 const char* ebof_last_error(const ebof_ctx*) { return g_err; }
 
-int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
-                    int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, void* hip_stream) {
+// Binning and denoising/filling of one window (Sec. III-A, III-B) on a stage
+// scratch: validates, takes the scratch's next stamp and launches the zeroing
+// (when the stamp wrapped), the scatter and the denoise/fill; with pack, the
+// fill also writes the column masks the distance transform starts from, and
+// the descriptor carries the surface table.  *out: the window's descriptor.
+static int bin_impl(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
+                    int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, hipStream_t st, bool pack,
+                    const char* who, WinDesc* out) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;
     if ((rc = validate(p))) return rc;
     if (n < 0 || (n > 0 && (!x || !y || !t)) || !edge_out) {
-        set_error("ebof_bin_events: NULL buffer or negative n");
+        set_error("%s: NULL buffer or negative n", who);
         return EBOF_E_INVAL;
     }
     if ((n + kEventsPerItem - 1) / kEventsPerItem > INT32_MAX) {
-        set_error("ebof_bin_events: too many events");
+        set_error("%s: too many events", who);
         return EBOF_E_INVAL;
     }
     if (t0_us > INT64_MAX - p->dt_us) {
-        set_error("ebof_bin_events: t0 + dt overflows");
+        set_error("%s: t0 + dt overflows", who);
         return EBOF_E_INVAL;
     }
-    hipStream_t st = (hipStream_t)hip_stream;
     const Geom g = make_geom(*p);
     Scratch scr;
+    Lut lut{p->alpha, 0, nullptr};
     uint32_t stamp;
     bool zero;
     {  // the lock covers the context's maps; launches run outside it
         std::lock_guard<std::mutex> lk(ctx->mu);
         Scratch* s = stage_scratch(ctx, g, st, &rc);
         if (!s) return rc;
+        if (pack && (rc = lut_for(ctx, p->alpha, &lut))) return rc;
         stamp = s->next_stamp();
         zero = s->needs_zero;
         s->needs_zero = false;
         scr = *s;
     }
-    Lut lut{p->alpha, 0, nullptr};
-    WinDesc d;
+    WinDesc& d = *out;
     fill_desc(*p, g, lut, scr, &d);
     d.ex = x;
     d.ey = y;
@@ -997,8 +1003,34 @@ int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
     if (zero) launch_zero(one_launch(&d, stage_items(d, kStZero, false, true, kStageTune), st));
     if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_DENOISE_FILL, st,
-          [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false, kStageTune), st), false); });
-    return launch_status(ctx);
+          [&] { launch_denoise_fill(one_launch(&d, stage_items(d, kStDenoise, false, false, kStageTune), st), pack); });
+    return EBOF_OK;
+}
+
+// The distance transform, surface and pyramid (Sec. III-C) of the edge image
+// d.e_df into d.d2 / d.pyr; the column masks are packed first unless the
+// fill already wrote them.
+static void surface_impl(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d, hipStream_t st, bool packed) {
+    if (!packed)
+        timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
+    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
+    timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
+    if (p->levels > 1)
+        timed(
+            ctx, EBOF_K_PYR_DOWN, st,
+            [&] {
+                for (int from = 0; from < p->levels - 1; from += kPyrChain)
+                    launch_pyr_chain(
+                        one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
+            });
+}
+
+int ebof_bin_events(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
+                    int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, void* hip_stream) {
+    WinDesc d;
+    int rc = bin_impl(ctx, p, x, y, t, n, t0_us, edge_out, n_dropped_dev, (hipStream_t)hip_stream, false,
+                      "ebof_bin_events", &d);
+    return rc ? rc : launch_status(ctx);
 }
 
 int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, int32_t* d2_out, float* pyr_out,
@@ -1026,17 +1058,24 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
     d.e_df = const_cast<uint8_t*>(edge);  // read only by these kernels
     d.d2 = d2_out;
     d.pyr = pyr_out;
-    timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
-    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
-    timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
-    if (p->levels > 1)
-        timed(
-            ctx, EBOF_K_PYR_DOWN, st,
-            [&] {
-                for (int from = 0; from < p->levels - 1; from += kPyrChain)
-                    launch_pyr_chain(
-                        one_launch(&d, stage_items(d, kStPyr + from / kPyrChain, false, false, kStageTune), st), from);
-            });
+    surface_impl(ctx, p, d, st, false);
+    return launch_status(ctx);
+}
+
+int ebof_window_surface(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
+                        int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, int32_t* d2_out,
+                        float* pyr_out, void* hip_stream) {
+    if (ctx && !pyr_out) {
+        set_error("ebof_window_surface: NULL pyr_out");
+        return EBOF_E_INVAL;
+    }
+    const hipStream_t st = (hipStream_t)hip_stream;
+    WinDesc d;
+    int rc = bin_impl(ctx, p, x, y, t, n, t0_us, edge_out, n_dropped_dev, st, true, "ebof_window_surface", &d);
+    if (rc) return rc;
+    d.d2 = d2_out;
+    d.pyr = pyr_out;
+    surface_impl(ctx, p, d, st, true);
     return launch_status(ctx);
 }
 

@@ -82,4 +82,5 @@ def test_stream_signals_reject_null_context():
     assert lib.ebof_signal_read(None, 0, __import__("ctypes").byref(v)) == L.EBOF_E_INVAL
     st = __import__("ctypes").c_void_p()
     assert lib.ebof_stream_create(None, __import__("ctypes").byref(st)) == L.EBOF_E_INVAL
+    assert lib.ebof_window_surface(None, None, None, None, None, 0, 0, None, None, None, None, None) == L.EBOF_E_INVAL
 

@@ -73,6 +73,38 @@ def alone(ctx, p, evs):
     return res
 
 
+def test_window_surface_equals_two_stage_calls(ctx):
+    """ebof_window_surface (binning, fill with the column masks formed on the
+    way, distance transform, surface, pyramid in one call) gives the bits of
+    ebof_bin_events followed by ebof_edt_surface, also for a window with no
+    events, and counts the same dropped events."""
+    for p, evs in mixed_streams(n_low=1, n_hd=1, windows=3):
+        ref = alone(ctx, p, evs)
+        W, H = p.width, p.height
+        P = L.ebof_pyramid_floats(p)
+        empty = dict(x=evs[0]["x"][:0], y=evs[0]["y"][:0], t=evs[0]["t"][:0], t0=evs[0]["t0"])
+        e0 = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+        pr0 = torch.empty(P, dtype=torch.float32, device="cuda")
+        L.ebof_bin_events(ctx, p, empty["x"], empty["y"], empty["t"], empty["t0"], e0)
+        L.ebof_edt_surface(ctx, p, e0, pr0)
+        for k, ev in enumerate(evs + [empty]):
+            e = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+            d2 = torch.empty(W * H, dtype=torch.int32, device="cuda")
+            pr = torch.empty(P, dtype=torch.float32, device="cuda")
+            nd = torch.zeros(1, dtype=torch.uint64, device="cuda")
+            L.ebof_window_surface(ctx, p, ev["x"], ev["y"], ev["t"], ev["t0"], e, pr, d2_out=d2, n_dropped=nd)
+            nd_ref = torch.zeros(1, dtype=torch.uint64, device="cuda")
+            L.ebof_bin_events(ctx, p, ev["x"], ev["y"], ev["t"], ev["t0"], torch.empty_like(e), n_dropped=nd_ref)
+            torch.cuda.synchronize()
+            assert int(nd.item()) == int(nd_ref.item()), (W, k)
+            if k < len(evs):
+                assert torch.equal(e, ref[k][0]) and torch.equal(d2, ref[k][2]) and torch.equal(pr, ref[k][1]), (W, k)
+            else:
+                assert torch.equal(e, e0) and torch.equal(pr, pr0), (W, "no events")
+                assert int((d2 != 2**31 - 1).sum()) == 0
+        _say(f"window_surface {W}x{H}: {len(evs) + 1} windows")
+
+
 def test_batch_equals_alone_and_graph_replays(ctx):
     streams = mixed_streams()
     ref = [alone(ctx, p, evs) for p, evs in streams]
