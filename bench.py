@@ -61,10 +61,8 @@ def parse():
     ap.add_argument("--sequential-only", action="store_true",
                     help="time only the sequential plain form (value = its rate); for counter runs, "
                          "whose per-dispatch serialisation does not mix with cross-stream waits")
-    ap.add_argument("--plain-streams", type=int, default=2,
-                    help="flow streams of the pipelined plain path")
-    ap.add_argument("--plain-pre-streams", type=int, default=2,
-                    help="preprocessing streams of the pipelined plain path (windows taken in turn)")
+    ap.add_argument("--plain-streams", type=int, default=4,
+                    help="streams of the pipelined plain path (windows taken in turn)")
     return ap.parse_args()
 
 
@@ -243,49 +241,50 @@ def dis_flops_window(L, p):
     return tot
 
 
-def pipelined_driver(lib, h, sptrs, NP, NF, NB, slot0, preprocess, flow_of):
-    """The pipelined plain form: window k binned and turned into its pyramid
-    on preprocessing stream k mod NP, the flow k-1 -> k on flow stream
-    k mod NF once both pyramids are ready, buffers in a ring of NB (window k
-    reuses the buffers of window k-NB once the flows that read them are
-    done).  Streams are ordered by the context's stream counters
-    (ebof_stream_signal / ebof_stream_wait), one per stream from slot0 on:
-    window k's preprocessing stores k+1 into its stream's counter, its flow
-    stores k+1 into the flow stream's.  Returns run(k_lo, k_hi), which issues
+def pipelined_driver(lib, h, sptrs, NB, slot0, preprocess, flow_of):
+    """The pipelined plain form: window k binned and turned into its pyramid,
+    then the flow k-1 -> k, all on stream k mod NS (NS = len(sptrs)), the
+    flow once window k-1's pyramid (another stream's work) is ready; buffers
+    in a ring of NB (window k reuses the buffers of window k-NB once the
+    flows that read them are done).  The streams are ordered by the
+    context's stream counters (ebof_stream_signal / ebof_stream_wait), one
+    per stream from slot0 on: window k's preprocessing stores 2k+1 into its
+    stream's counter, its flow 2k+2.  Returns run(k_lo, k_hi), which issues
     windows k_lo .. k_hi-1; work issued before k_lo must be complete."""
     import ctypes
+    NS = len(sptrs)
 
     def check(rc):
         if rc:
             raise RuntimeError(lib.ebof_last_error(h).decode())
 
-    seen = [0] * (NP + NF)
+    seen = [0] * NS
     val = ctypes.c_uint32()
 
     def flow_done(j):  # the host knows flow j has completed
-        f = NP + j % NF
-        if seen[f] < j + 1:
+        f = j % NS
+        if seen[f] < 2 * j + 2:
             check(lib.ebof_signal_read(h, slot0 + f, ctypes.byref(val)))
             seen[f] = val.value
-        return seen[f] >= j + 1
+        return seen[f] >= 2 * j + 2
 
     def run(k_lo, k_hi):
-        for i in range(NP + NF):
+        for i in range(NS):
             seen[i] = 0
         for k in range(k_lo, k_hi):
-            i = k % NP
+            i = k % NS
             for j in (k - NB, k - NB + 1):  # the flows that last read buffer k % NB
                 if j >= max(1, k_lo) and not flow_done(j):
-                    check(lib.ebof_stream_wait(h, slot0 + NP + j % NF, j + 1, sptrs[i]))
+                    check(lib.ebof_stream_wait(h, slot0 + j % NS, 2 * j + 2, sptrs[i]))
             preprocess(k, i)
-            check(lib.ebof_stream_signal(h, slot0 + i, k + 1, sptrs[i]))
             if k > 0:
-                f = NP + k % NF
-                if NP > 1 and k - 1 >= k_lo:  # window k-1 was preprocessed on another stream
-                    check(lib.ebof_stream_wait(h, slot0 + (k - 1) % NP, k, sptrs[f]))
-                check(lib.ebof_stream_wait(h, slot0 + i, k + 1, sptrs[f]))
-                flow_of(k, f)
-                check(lib.ebof_stream_signal(h, slot0 + f, k + 1, sptrs[f]))
+                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 1, sptrs[i]))
+                if k - 1 >= k_lo:  # window k-1's pyramid, from another stream
+                    check(lib.ebof_stream_wait(h, slot0 + (k - 1) % NS, 2 * k - 1, sptrs[i]))
+                flow_of(k, i)
+                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 2, sptrs[i]))
+            else:
+                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 1, sptrs[i]))
 
     return run
 
@@ -382,23 +381,21 @@ def main():
     # only (ebof_window_surface, then ebof_flow from the previous window).
     # Sequential form: everything on one stream, one window at a time.
     # Pipelined form, the paper's blocks (Fig. 1) as concurrent HIP streams
-    # (pipelined_driver): binning and EDT/surface/pyramid of window k on
-    # stream P[k mod NP], the flow k-1 -> k on stream F[k mod NF] once both
-    # pyramids it reads are ready, so consecutive windows' preprocessing and
-    # flows overlap.  Buffers form a ring of NB.  The streams are ordered by
-    # the context's stream counters (a stream wait on an event recorded on
-    # another stream costs far more host time on this runtime), so one host
-    # thread issues everything faster than the GPU completes it.
-    NF = max(1, args.plain_streams)
-    NP = max(1, args.plain_pre_streams)
+    # (pipelined_driver): binning and EDT/surface/pyramid of window k, then
+    # the flow k-1 -> k once window k-1's pyramid is ready, on stream
+    # k mod NS, so consecutive windows' preprocessing and flows overlap.
+    # Buffers form a ring of NB.  The streams are ordered by the context's
+    # stream counters (a stream wait on an event recorded on another stream
+    # costs far more host time on this runtime), so one host thread issues
+    # everything faster than the GPU completes it.
+    NS = max(1, args.plain_streams)
     NB = 16
     pyr = [torch.empty(P, dtype=torch.float32, device=dev) for _ in range(NB)]
     edge = [torch.empty(N, dtype=torch.uint8, device=dev) for _ in range(NB)]
     flows = [torch.empty(2 * N, dtype=torch.float32, device=dev) for _ in range(NB)]
-    # the preprocessing streams, then the flow streams: context-owned, a
-    # hardware queue each (streams sharing a queue would run one after the
-    # other)
-    streams = [L.ebof_stream_create(ctx) for _ in range(NP + NF)]
+    # context-owned streams, a hardware queue each (streams sharing a queue
+    # would run one after the other)
+    streams = [L.ebof_stream_create(ctx) for _ in range(NS)]
     sptrs = [ctypes.c_void_p(st.cuda_stream) for st in streams]
     pp = ctypes.byref(p)
     vp = ctypes.c_void_p
@@ -434,7 +431,7 @@ def main():
         for st in streams:
             st.synchronize()
 
-    run_pipelined = pipelined_driver(lib, h, sptrs, NP, NF, NB, 0, preprocess, flow_of)
+    run_pipelined = pipelined_driver(lib, h, sptrs, NB, 0, preprocess, flow_of)
 
     # ---------------- EPE against the oracle on the sampled pairs ----------
     epe = None
@@ -484,9 +481,9 @@ def main():
     if args.sequential_only:
         fps, issue_ms = fps_seq, None
     else:
-        run_pipelined(Wm + K, Wm + K + 4 * NF)  # untimed: streams warm
+        run_pipelined(Wm + K, Wm + K + 4 * NS)  # untimed: streams warm
         sync_all()
-        k0 = Wm + K + 4 * NF
+        k0 = Wm + K + 4 * NS
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         run_pipelined(k0, k0 + K)
@@ -494,7 +491,7 @@ def main():
         sync_all()
         torch.cuda.synchronize()
         fps = K / (time.perf_counter() - t0)
-        log(f"plain (pipelined, {NP} preprocessing + {NF} flow streams): {fps:.1f} frames/s "
+        log(f"plain (pipelined, {NS} streams): {fps:.1f} frames/s "
             f"({1e3 / fps:.4f} ms/window, host issue {issue_ms:.4f} ms/window)")
     elapsed = K / fps
 
@@ -563,8 +560,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
         "plain_form": "sequential" if args.sequential_only else "pipelined",
-        "plain_flow_streams": NF,
-        "plain_pre_streams": NP,
+        "plain_streams": NS,
         "plain_host_issue_ms_per_window": issue_ms,
         "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
@@ -587,7 +583,7 @@ def main():
                                    iters=p1.iters, lam=float(np.float32(p1.lambda_reg))),
                    rs[0]["Edf"].astype(bool))
     if c1:
-        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, streams, NP, NF, c1_pair)
+        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, streams, c1_pair)
 
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
@@ -600,9 +596,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_c1(L, ctx, c1, steps, dev, streams, NP, NF, oracle_pair):
+def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair):
     """The 346x260 plain path, sequential and pipelined, on the 1280x720
-    section's streams (NP preprocessing, then NF flow streams)."""
+    section's streams."""
     """346x260 plain path (the low-resolution config): sequential and
     pipelined rates over the C1 stream's windows, and the EPE against the
     oracle on its first pair (oracle_pair: (flow, mask) or None)."""
@@ -659,18 +655,19 @@ def bench_c1(L, ctx, c1, steps, dev, streams, NP, NF, oracle_pair):
     k0 = 12 + steps
     # its own counters (slots 16..), so values stored here never fall below
     # those of the 1280x720 section on the same context
-    pipelined = pipelined_driver(lib, h, sp, NP, NF, NB, 16, pre, flw)
+    pipelined = pipelined_driver(lib, h, sp, NB, 16, pre, flw)
+    NS = len(sp)
 
-    pipelined(k0, k0 + 4 * NF)
+    pipelined(k0, k0 + 4 * NS)
     torch.cuda.synchronize()
-    k0 += 4 * NF
+    k0 += 4 * NS
     t0 = time.perf_counter()
     pipelined(k0, k0 + steps)
     torch.cuda.synchronize()
     fps = steps / (time.perf_counter() - t0)
     res = {"workload": "346x260 plain single camera stream, 20k events per window, 40 segments translating "
                        "(+2.5, -1.5) px per window, 5% noise, L=3",
-           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "pre_streams": NP, "flow_streams": NF,
+           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "streams": NS,
            "epe_vs_oracle_px": epe}
     log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined; EPE vs oracle {epe}")
     return res
