@@ -744,7 +744,7 @@ __device__ __forceinline__ double redd(double v) {
 // search region, stays small.  The reference strip (rows oy-1 .. oy+8 of
 // every patch row of the item) is staged in LDS for the template and its
 // gradient; then the region of I1 covering every patch's search window at
-// its initial displacement (plus a margin) is staged, column-major, and the
+// its initial displacement (plus a margin) is staged, row-major, and the
 // iterations read it there (a patch whose window leaves the region reads
 // global memory; both give the same clamped samples).
 template <bool B, int LP>
