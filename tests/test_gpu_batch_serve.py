@@ -105,6 +105,41 @@ def test_window_surface_equals_two_stage_calls(ctx):
         _say(f"window_surface {W}x{H}: {len(evs) + 1} windows")
 
 
+def test_stage_calls_across_stamp_wrap():
+    """A stage scratch marks a window's pixels with a stamp 1..255 and clears
+    its staging image when the stamp wraps: 262 windows on one stream
+    (three windows in turn) give every window the edge image (and, through
+    ebof_window_surface, the pyramid) of its first occurrence, also past the
+    wrap, where stale marks of window 0 would land in window 256 (a
+    different window)."""
+    c = L.ebof_create(arena_bytes=1 << 30)
+    try:
+        s = synth.c1_stream(0)
+        wins = [s.window(k) for k in range(3)]
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+        N, P = s.W * s.H, L.ebof_pyramid_floats(p)
+        evs = [dict(x=dev(w["x"]), y=dev(w["y"]), t=dev(w["t"]), t0=w["t0"]) for w in wins]
+        st = [torch.cuda.Stream() for _ in range(2)]
+        first = {}
+        for k in range(262):
+            ev = evs[k % 3]
+            e1 = torch.empty(N, dtype=torch.uint8, device="cuda")
+            e2 = torch.empty(N, dtype=torch.uint8, device="cuda")
+            pr = torch.empty(P, dtype=torch.float32, device="cuda")
+            L.ebof_bin_events(c, p, ev["x"], ev["y"], ev["t"], ev["t0"], e1, stream=st[0])
+            L.ebof_window_surface(c, p, ev["x"], ev["y"], ev["t"], ev["t0"], e2, pr, stream=st[1])
+            torch.cuda.synchronize()
+            if k < 3:
+                assert torch.equal(e1, e2)
+                first[k] = (e1, pr)
+            else:
+                r = first[k % 3]
+                assert torch.equal(e1, r[0]) and torch.equal(e2, r[0]) and torch.equal(pr, r[1]), k
+        _say("stamp wrap: 262 windows, bin_events and window_surface")
+    finally:
+        c.close()
+
+
 def test_batch_equals_alone_and_graph_replays(ctx):
     streams = mixed_streams()
     ref = [alone(ctx, p, evs) for p, evs in streams]
