@@ -165,9 +165,10 @@ def summarize_traffic(fetch_dir, write_dir):
     wa, wc = load(write_dir, "WRITE_SIZE")
     copy_kib = 256 * 1024
     ff, wf = copy_kib / fc, copy_kib / wc
-    with open(os.path.join(ROOT, "paper_2112_10591_amd", "csrc", "kernels.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    rec = {"workload": "1280x720 plain (bench.py sequential and pipelined forms)", "kernels_hip_sha256": sha,
+    sha = kernel_source_sha()
+    rec = {"workload": "1280x720 plain (bench.py sequential and pipelined forms)",
+           "kernel_sources": ["paper_2112_10591_amd/csrc/" + n for n in KERNEL_SOURCES],
+           "kernel_sources_sha256": sha,
            "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 256 MiB)",
                            "bytes_read": copy_kib * 1024, "bytes_written": copy_kib * 1024,
                            "fetch_kib_measured": fc, "write_kib_measured": wc,
@@ -183,8 +184,9 @@ def summarize_traffic(fetch_dir, write_dir):
           "dispatch reading and writing 262144 KiB), three times. On that dispatch the counters read "
           f"FETCH_SIZE = {fc:.1f} KiB and WRITE_SIZE = {wc:.1f} KiB, so the path's counts are scaled by "
           f"{ff:.4f} (fetch) and {wf:.4f} (write).", "",
-          f"Kernel source: `paper_2112_10591_amd/csrc/kernels.hip` sha256 `{sha[:16]}…` (bench.py reports "
-          "`traffic` only while the source still has this hash).", "",
+          "Kernel sources: " + ", ".join(f"`paper_2112_10591_amd/csrc/{n}`" for n in KERNEL_SOURCES) +
+          f", sha256 of both `{sha[:16]}…` (bench.py reports `traffic` only while the sources still have this "
+          "hash).", "",
           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MB | HBM write MB | total MB / launch |",
           "|---|---:|---:|---:|---:|---:|---:|"]
     for k in fa:
@@ -202,22 +204,33 @@ def summarize_traffic(fetch_dir, write_dir):
     print("wrote profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md")
 
 
+# The device code the counters describe: the kernels and the constants and
+# structures they are built with.
+KERNEL_SOURCES = ("kernels.hip", "ebof_dev.h")
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_10591_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
     the same counters on a plain copy of known size), or None when there is
     none for this kernel or the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2112_10591_amd", "csrc", "kernels.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_sha()
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("kernels_hip_sha256") != sha:
+    if not k or rec.get("kernel_sources_sha256") != sha:
         return None
     return k["hbm_bytes_per_launch"]
 
