@@ -67,7 +67,7 @@ def parse():
 
 
 # ----------------------------------------------------------------------------
-# algorithmic work per kernel ("Measurement")
+# algorithmic work per kernel
 # ----------------------------------------------------------------------------
 def dis_flops_per_patch(iters, init):
     # per iteration and pixel: 9/8 horizontal + 1 vertical lerp (3 flops
@@ -118,7 +118,8 @@ def summarize_trace(trace_dir, bench_json):
     dn, dt = sum(a[0] for a in dis), sum(a[1] for a in dis)
     out = ["# Kernel time, 1280x720 plain path (C2 windows)", "",
            "Command (from the repository root, `TMPDIR=/tmp`):", "", "```",
-           f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o run -- {PROFILE_CMD}",
+           f"rocprofv3 --kernel-trace --stats --output-format csv -d {trace_dir} -o run -- {PROFILE_CMD} "
+           f"> {bench_json}",
            "```", "",
            "| kernel | dispatches | total µs | avg µs | min µs | max µs | % |",
            "|---|---:|---:|---:|---:|---:|---:|"]
@@ -177,9 +178,9 @@ def summarize_traffic(fetch_dir, write_dir):
     cmd = f"{PROFILE_CMD} --copy-calib 256"
     md = ["# HBM traffic per launch, 1280x720 plain path (C2 windows)", "",
           "Commands (from the repository root, `TMPDIR=/tmp`), one counter per run:", "", "```",
-          f"timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- {cmd}",
-          f"timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- {cmd}",
-          "python3 bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write", "```", "",
+          f"timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- {cmd}",
+          f"timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- {cmd}",
+          f"python3 bench.py --summarize-traffic {fetch_dir} {write_dir}", "```", "",
           "`--copy-calib 256` first copies 256 MiB with `torch.Tensor.copy_` (one `__amd_rocclr_copyBuffer` "
           "dispatch reading and writing 262144 KiB), three times. On that dispatch the counters read "
           f"FETCH_SIZE = {fc:.1f} KiB and WRITE_SIZE = {wc:.1f} KiB, so the path's counts are scaled by "
