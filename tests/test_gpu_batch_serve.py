@@ -105,6 +105,54 @@ def test_window_surface_equals_two_stage_calls(ctx):
         _say(f"window_surface {W}x{H}: {len(evs) + 1} windows")
 
 
+def test_pipelined_driver_equals_sequential():
+    """The benchmark's pipelined plain driver (each window's surface call and
+    flow on stream k mod 4, ordered by the context counters, a buffer ring of
+    5 so that slots are reused while earlier flows may still read them)
+    gives every window the flow of the sequential stage calls."""
+    import ctypes
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    c = L.ebof_create(arena_bytes=1 << 30)
+    try:
+        s = synth.c1_stream(0)
+        nwin, NB = 20, 5
+        wins = [s.window(k) for k in range(nwin)]
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+        N, P = s.W * s.H, L.ebof_pyramid_floats(p)
+        evs = [dict(x=dev(w["x"]), y=dev(w["y"]), t=dev(w["t"]), t0=w["t0"]) for w in wins]
+        ref = alone(c, p, evs)
+        streams = [L.ebof_stream_create(c) for _ in range(4)]
+        sp = [ctypes.c_void_p(st.cuda_stream) for st in streams]
+        edge = [torch.empty(N, dtype=torch.uint8, device="cuda") for _ in range(NB)]
+        pyr = [torch.empty(P, dtype=torch.float32, device="cuda") for _ in range(NB)]
+        flows = [torch.full((2 * N,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(nwin)]
+        torch.cuda.synchronize()
+        lib, h, vp, pp = c.lib, c.handle, ctypes.c_void_p, ctypes.byref(p)
+
+        def pre(k, i):
+            e = evs[k]
+            assert lib.ebof_window_surface(h, pp, vp(e["x"].data_ptr()), vp(e["y"].data_ptr()), vp(e["t"].data_ptr()),
+                                           int(e["x"].numel()), int(e["t0"]), vp(edge[k % NB].data_ptr()), None, None,
+                                           vp(pyr[k % NB].data_ptr()), sp[i]) == 0
+
+        def flw(k, i):
+            b, bp = k % NB, (k - 1) % NB
+            assert lib.ebof_flow(h, pp, vp(pyr[bp].data_ptr()), vp(pyr[b].data_ptr()), vp(edge[bp].data_ptr()),
+                                 vp(flows[k].data_ptr()), sp[i]) == 0
+
+        run = bench.pipelined_driver(lib, h, sp, NB, 0, pre, flw)
+        run(0, nwin)
+        torch.cuda.synchronize()
+        for k in range(1, nwin):
+            assert torch.equal(flows[k], ref[k][3]), k
+        _say(f"pipelined driver: {nwin} windows, ring {NB}, 4 streams")
+    finally:
+        c.close()
+
+
 def test_stage_calls_across_stamp_wrap():
     """A stage scratch marks a window's pixels with a stamp 1..255 and clears
     its staging image when the stamp wraps: 262 windows on one stream
