@@ -17,6 +17,12 @@ Parity status (what pins each function; the tests under ``tests/`` hold them):
   pyr_down          (flow pyramid)   pinned: scipy.ndimage mirror convolution
   dis_flow          Sec. III-D       pinned: zero motion, linear-ramp sub-pixel
                                      shifts, integer shifts, known translation
+  densify           (DIS step)       pinned: hand-worked weights (the 255 scale,
+                                     the max(1, .)), cover of clamped patches
+  dis_level         (DIS step)       pinned: reset threshold, norm and target on
+                                     ramps / paraboloid; damped contraction
+  patch_init_*      (DIS step)       pinned: hand-worked start points (patch
+                                     centre, factor 2; warm start scale)
 """
 from __future__ import annotations
 
@@ -67,6 +73,12 @@ def _load():
     lib.oref_pyr_down.argtypes = [i32, i32, P, P]
     lib.oref_dis_flow.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P]
     lib.oref_dis_flow.restype = ctypes.c_int
+    lib.oref_dis_flow_warm.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P, P]
+    lib.oref_dis_flow_warm.restype = ctypes.c_int
+    lib.oref_patch_init_coarser.argtypes = [i32, i32, i32, i32, P, i32, i32, P]
+    lib.oref_patch_init_previous.argtypes = [i32, i32, i32, i32, i32, P, i32, i32, P]
+    lib.oref_dis_level.argtypes = [i32, i32, P, P, i32, i32, i32, f64, P, P]
+    lib.oref_densify.argtypes = [i32, i32, P, P, i32, i32, P, P]
     lib.oref_patch_count.argtypes = [i32, i32, i32, i32]
     lib.oref_patch_count.restype = i64
     _lib = lib
@@ -189,22 +201,82 @@ def patch_count(W, H, ps=8, stride=4):
 
 
 def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=0.3,
-             want_patches=False):
+             want_patches=False, prev_flow=None):
     """Dense inverse search flow from pyr0 (window k-1) to pyr1 (window k).
-    Returns float64 [2,H,W] (u, v), and per-level patch flows if asked."""
+    Returns float64 [2,H,W] (u, v), and per-level patch flows if asked.
+    prev_flow: None, or the previous pair's dense [2,H,W] flow, from which
+    the coarsest level starts (warm start)."""
     pyr0 = np.ascontiguousarray(pyr0, np.float32)
     pyr1 = np.ascontiguousarray(pyr1, np.float32)
     flow = np.empty((2, H, W), np.float64)
     npatch = sum(patch_count(w, h, ps, stride) for w, h in level_sizes(W, H, L))
     pu = np.empty((npatch, 2), np.float64) if want_patches else None
-    rc = _load().oref_dis_flow(W, H, L, _ptr(pyr0), _ptr(pyr1), ps, stride,
-                               iters, float(lam), _ptr(flow),
-                               _ptr(pu) if pu is not None else None)
+    warm = None
+    if prev_flow is not None:
+        warm = np.ascontiguousarray(prev_flow, np.float64)
+        assert warm.shape == (2, H, W)
+    rc = _load().oref_dis_flow_warm(W, H, L, _ptr(pyr0), _ptr(pyr1), ps, stride,
+                                    iters, float(lam), _ptr(warm) if warm is not None else None,
+                                    _ptr(flow), _ptr(pu) if pu is not None else None)
     if rc != 0:
         raise ValueError("oref_dis_flow rejected its arguments")
     if want_patches:
         return flow, pu
     return flow
+
+
+def _patch_grid(W, H, ps, stride):
+    return (W - ps + stride - 1) // stride + 1, (H - ps + stride - 1) // stride + 1
+
+
+def patch_init_coarser(W, H, Uc, ps=8, stride=4):
+    """Initial patch displacements [ny, nx, 2] of a W x H level from the
+    coarser level's dense flow Uc [2, Hc, Wc]."""
+    Uc = np.ascontiguousarray(Uc, np.float64)
+    nx, ny = _patch_grid(W, H, ps, stride)
+    u0 = np.empty((ny, nx, 2), np.float64)
+    _load().oref_patch_init_coarser(W, H, ps, stride, _ptr(Uc), Uc.shape[2], Uc.shape[1], _ptr(u0))
+    return u0
+
+
+def patch_init_previous(W, H, level, Up, ps=8, stride=4):
+    """Initial patch displacements [ny, nx, 2] of level `level` (W x H) from
+    the previous pair's dense level-0 flow Up [2, H0, W0] (warm start)."""
+    Up = np.ascontiguousarray(Up, np.float64)
+    nx, ny = _patch_grid(W, H, ps, stride)
+    u0 = np.empty((ny, nx, 2), np.float64)
+    _load().oref_patch_init_previous(W, H, int(level), ps, stride, _ptr(Up), Up.shape[2], Up.shape[1],
+                                     _ptr(u0))
+    return u0
+
+
+def dis_level(I0, I1, u0=None, ps=8, stride=4, iters=16, lam=0.3):
+    """Patch inverse search on one level (images [H, W] float32) from the
+    initial displacements u0 [ny, nx, 2] (None = 0); returns [ny, nx, 2]."""
+    I0 = np.ascontiguousarray(I0, np.float32)
+    I1 = np.ascontiguousarray(I1, np.float32)
+    H, W = I0.shape
+    nx, ny = _patch_grid(W, H, ps, stride)
+    pu = np.empty((ny, nx, 2), np.float64)
+    if u0 is not None:
+        u0 = np.ascontiguousarray(u0, np.float64)
+        assert u0.shape == (ny, nx, 2)
+    _load().oref_dis_level(W, H, _ptr(I0), _ptr(I1), ps, stride, int(iters), float(lam),
+                           _ptr(u0) if u0 is not None else None, _ptr(pu))
+    return pu
+
+
+def densify(I0, I1, pu, ps=8, stride=4):
+    """Dense flow [2, H, W] from patch displacements pu [ny, nx, 2]."""
+    I0 = np.ascontiguousarray(I0, np.float32)
+    I1 = np.ascontiguousarray(I1, np.float32)
+    H, W = I0.shape
+    nx, ny = _patch_grid(W, H, ps, stride)
+    pu = np.ascontiguousarray(pu, np.float64)
+    assert pu.shape == (ny, nx, 2)
+    U = np.empty((2, H, W), np.float64)
+    _load().oref_densify(W, H, _ptr(I0), _ptr(I1), ps, stride, _ptr(pu), _ptr(U))
+    return U
 
 
 # --------------------------------------------------------------------------

@@ -346,10 +346,13 @@ static int32_t patch_origin(int32_t k, int32_t stride, int32_t n, int32_t ps)
 
 /* Densification: U(x) = sum_i w_i u_i / sum_i w_i over the patches i that
  * contain x, w_i = 1 / max(1, 255 |I1(x + u_i) - I0(x)|).  The 255 puts the
- * [0,1] surface on the 8-bit scale that the weight's unit threshold assumes. */
-static void densify(int32_t W, int32_t H, const float *I0, const float *I1,
-                    int32_t ps, int32_t stride, const double *pu,
-                    double *U /* 2*W*H */)
+ * [0,1] surface on the 8-bit scale that the weight's unit threshold assumes
+ * (the same 8-bit coding eq. (3) takes for its saturation gap).  Every pixel
+ * lies in at least one patch (the last origin of each axis is clamped to the
+ * border), so the denominator is positive. */
+void oref_densify(int32_t W, int32_t H, const float *I0, const float *I1,
+                  int32_t ps, int32_t stride, const double *pu,
+                  double *U /* 2*W*H */)
 {
     int32_t nx = (W - ps + stride - 1) / stride + 1;
     int32_t ny = (H - ps + stride - 1) / stride + 1;
@@ -385,10 +388,135 @@ static void densify(int32_t W, int32_t H, const float *I0, const float *I1,
     free(acc_v);
 }
 
-int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
-                  const float *pyr1, int32_t ps, int32_t stride,
-                  int32_t iters, double lambda, double *flow,
-                  double *patch_uv)
+/* Coarse-to-fine start of a level: a patch starts from twice the coarser
+ * level's dense flow Uc (Wc x Hc, two planes) at the coarser pixel nearest
+ * to the patch centre, i.e. at (floor((o_x + ps/2) / 2), floor((o_y + ps/2)
+ * / 2)), clamped into the coarser image. */
+void oref_patch_init_coarser(int32_t W, int32_t H, int32_t ps, int32_t stride,
+                             const double *Uc, int32_t Wc, int32_t Hc,
+                             double *u0)
+{
+    int32_t nx = (W - ps + stride - 1) / stride + 1;
+    int32_t ny = (H - ps + stride - 1) / stride + 1;
+    for (int32_t ky = 0; ky < ny; ky++)
+        for (int32_t kx = 0; kx < nx; kx++) {
+            int32_t cx = (patch_origin(kx, stride, W, ps) + ps / 2) / 2;
+            int32_t cy = (patch_origin(ky, stride, H, ps) + ps / 2) / 2;
+            if (cx > Wc - 1)
+                cx = Wc - 1;
+            if (cy > Hc - 1)
+                cy = Hc - 1;
+            size_t k = (size_t)ky * nx + kx;
+            u0[2 * k] = 2.0 * Uc[(size_t)cy * Wc + cx];
+            u0[2 * k + 1] = 2.0 * Uc[(size_t)Wc * Hc + (size_t)cy * Wc + cx];
+        }
+}
+
+/* Warm start of the coarsest level (level `level` of a W0 x H0 sensor) from
+ * the previous window pair's dense level-0 flow Up (the temporal
+ * propagation Sec. III-D values in its flow method, reduced to a prediction
+ * of constant motion): a patch starts from Up at the level-0 pixel under
+ * its centre, (o + ps/2) * 2^level clamped into the sensor, divided by
+ * 2^level (a displacement of level 0 spans 2^level times fewer pixels
+ * there). */
+void oref_patch_init_previous(int32_t W, int32_t H, int32_t level, int32_t ps,
+                              int32_t stride, const double *Up, int32_t W0,
+                              int32_t H0, double *u0)
+{
+    int32_t nx = (W - ps + stride - 1) / stride + 1;
+    int32_t ny = (H - ps + stride - 1) / stride + 1;
+    double scale = 1.0;
+    for (int32_t l = 0; l < level; l++)
+        scale *= 2.0;
+    for (int32_t ky = 0; ky < ny; ky++)
+        for (int32_t kx = 0; kx < nx; kx++) {
+            int64_t px = (int64_t)(patch_origin(kx, stride, W, ps) + ps / 2) << level;
+            int64_t py = (int64_t)(patch_origin(ky, stride, H, ps) + ps / 2) << level;
+            if (px > W0 - 1)
+                px = W0 - 1;
+            if (py > H0 - 1)
+                py = H0 - 1;
+            size_t k = (size_t)ky * nx + kx;
+            u0[2 * k] = Up[(size_t)py * W0 + px] / scale;
+            u0[2 * k + 1] = Up[(size_t)W0 * H0 + (size_t)py * W0 + px] / scale;
+        }
+}
+
+/* Patch inverse search on one level: every patch starts from its u0,
+ * takes `iters` inverse-compositional Lucas-Kanade steps (translation only)
+ * with the Hessian regularised by lambda I, and returns to u0 when it moved
+ * more than ps (Euclidean) from it. */
+void oref_dis_level(int32_t W, int32_t H, const float *I0, const float *I1,
+                    int32_t ps, int32_t stride, int32_t iters, double lambda,
+                    const double *u0, double *pu)
+{
+    int32_t nx = (W - ps + stride - 1) / stride + 1;
+    int32_t ny = (H - ps + stride - 1) / stride + 1;
+    double *gx = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+    double *gy = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+    double *T = (double *)malloc(sizeof(double) * (size_t)ps * ps);
+    for (int32_t ky = 0; ky < ny; ky++)
+        for (int32_t kx = 0; kx < nx; kx++) {
+            int32_t ox = patch_origin(kx, stride, W, ps);
+            int32_t oy = patch_origin(ky, stride, H, ps);
+            size_t k = (size_t)ky * nx + kx;
+            double su = u0 ? u0[2 * k] : 0.0, sv = u0 ? u0[2 * k + 1] : 0.0;
+
+            /* template, its gradient (central differences, replicated
+             * border) and the Gauss-Newton Hessian H = sum g g^T */
+            double hxx = 0.0, hxy = 0.0, hyy = 0.0;
+            for (int32_t j = 0; j < ps; j++)
+                for (int32_t i = 0; i < ps; i++) {
+                    int32_t x = ox + i, y = oy + j;
+                    int32_t q = j * ps + i;
+                    T[q] = (double)I0[(size_t)y * W + x];
+                    gx[q] = 0.5 * (at_clamped(I0, W, H, x + 1, y) -
+                                   at_clamped(I0, W, H, x - 1, y));
+                    gy[q] = 0.5 * (at_clamped(I0, W, H, x, y + 1) -
+                                   at_clamped(I0, W, H, x, y - 1));
+                    hxx += gx[q] * gx[q];
+                    hxy += gx[q] * gy[q];
+                    hyy += gy[q] * gy[q];
+                }
+            double a = hxx + lambda, c = hyy + lambda, bb = hxy;
+            double det = a * c - bb * bb;
+
+            /* inverse-compositional iterations, a fixed number of them */
+            double u = su, v = sv;
+            for (int32_t it = 0; it < iters; it++) {
+                double bx = 0.0, by = 0.0;
+                for (int32_t j = 0; j < ps; j++)
+                    for (int32_t i = 0; i < ps; i++) {
+                        int32_t q = j * ps + i;
+                        double r = bilinear(I1, W, H, ox + i + u, oy + j + v) - T[q];
+                        bx += gx[q] * r;
+                        by += gy[q] * r;
+                    }
+                /* (H + lambda I) d = b, solved by the 2x2 inverse */
+                double dx = (c * bx - bb * by) / det;
+                double dy = (a * by - bb * bx) / det;
+                u -= dx;
+                v -= dy;
+            }
+            /* outlier reset: a patch that moved more than its size
+             * returns to its initial displacement */
+            double mu = u - su, mv = v - sv;
+            if (sqrt(mu * mu + mv * mv) > (double)ps) {
+                u = su;
+                v = sv;
+            }
+            pu[2 * k] = u;
+            pu[2 * k + 1] = v;
+        }
+    free(gx);
+    free(gy);
+    free(T);
+}
+
+int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                       const float *pyr1, int32_t ps, int32_t stride,
+                       int32_t iters, double lambda, const double *prev_flow,
+                       double *flow, double *patch_uv)
 {
     if (L < 1 || L > 16 || ps < 1 || stride < 1 || iters < 0)
         return -1;
@@ -412,95 +540,36 @@ int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
     double *Uc = NULL; /* dense flow of the coarser level, 2*Wc*Hc */
     for (int32_t l = L - 1; l >= 0; l--) {
         int32_t Wl = lw[l], Hl = lh[l];
-        const float *I0 = pyr0 + loff[l];
-        const float *I1 = pyr1 + loff[l];
-        int32_t nx = (Wl - ps + stride - 1) / stride + 1;
-        int32_t ny = (Hl - ps + stride - 1) / stride + 1;
-        double *pu = (double *)malloc(sizeof(double) * 2 * (size_t)nx * ny);
-        double *gx = (double *)malloc(sizeof(double) * (size_t)ps * ps);
-        double *gy = (double *)malloc(sizeof(double) * (size_t)ps * ps);
-        double *T = (double *)malloc(sizeof(double) * (size_t)ps * ps);
-
-        for (int32_t ky = 0; ky < ny; ky++)
-            for (int32_t kx = 0; kx < nx; kx++) {
-                int32_t ox = patch_origin(kx, stride, Wl, ps);
-                int32_t oy = patch_origin(ky, stride, Hl, ps);
-
-                /* initial displacement: zero at the coarsest level, else
-                 * twice the coarser dense flow at the pixel nearest to the
-                 * patch centre */
-                double u0 = 0.0, v0 = 0.0;
-                if (l < L - 1) {
-                    int32_t Wc = lw[l + 1], Hc = lh[l + 1];
-                    int32_t cx = (ox + ps / 2) / 2, cy = (oy + ps / 2) / 2;
-                    if (cx > Wc - 1)
-                        cx = Wc - 1;
-                    if (cy > Hc - 1)
-                        cy = Hc - 1;
-                    u0 = 2.0 * Uc[(size_t)cy * Wc + cx];
-                    v0 = 2.0 * Uc[(size_t)Wc * Hc + (size_t)cy * Wc + cx];
-                }
-
-                /* template, its gradient (central differences, replicated
-                 * border) and the Gauss-Newton Hessian H = sum g g^T */
-                double hxx = 0.0, hxy = 0.0, hyy = 0.0;
-                for (int32_t j = 0; j < ps; j++)
-                    for (int32_t i = 0; i < ps; i++) {
-                        int32_t x = ox + i, y = oy + j;
-                        int32_t q = j * ps + i;
-                        T[q] = (double)I0[(size_t)y * Wl + x];
-                        gx[q] = 0.5 * (at_clamped(I0, Wl, Hl, x + 1, y) -
-                                       at_clamped(I0, Wl, Hl, x - 1, y));
-                        gy[q] = 0.5 * (at_clamped(I0, Wl, Hl, x, y + 1) -
-                                       at_clamped(I0, Wl, Hl, x, y - 1));
-                        hxx += gx[q] * gx[q];
-                        hxy += gx[q] * gy[q];
-                        hyy += gy[q] * gy[q];
-                    }
-                double a = hxx + lambda, c = hyy + lambda, bb = hxy;
-                double det = a * c - bb * bb;
-
-                /* inverse-compositional iterations, a fixed number of them */
-                double u = u0, v = v0;
-                for (int32_t it = 0; it < iters; it++) {
-                    double bx = 0.0, by = 0.0;
-                    for (int32_t j = 0; j < ps; j++)
-                        for (int32_t i = 0; i < ps; i++) {
-                            int32_t q = j * ps + i;
-                            double r = bilinear(I1, Wl, Hl, ox + i + u,
-                                                oy + j + v) - T[q];
-                            bx += gx[q] * r;
-                            by += gy[q] * r;
-                        }
-                    /* (H + lambda I) d = b, solved by the 2x2 inverse */
-                    double dx = (c * bx - bb * by) / det;
-                    double dy = (a * by - bb * bx) / det;
-                    u -= dx;
-                    v -= dy;
-                }
-                /* outlier reset: a patch that moved more than its size
-                 * returns to its initial displacement */
-                double mu = u - u0, mv = v - v0;
-                if (sqrt(mu * mu + mv * mv) > (double)ps) {
-                    u = u0;
-                    v = v0;
-                }
-                pu[2 * ((size_t)ky * nx + kx)] = u;
-                pu[2 * ((size_t)ky * nx + kx) + 1] = v;
-            }
+        size_t np = (size_t)oref_patch_count(Wl, Hl, ps, stride);
+        double *u0 = (double *)calloc(2 * np, sizeof(double));
+        double *pu = (double *)malloc(sizeof(double) * 2 * np);
+        /* start: zero (or the previous flow) at the coarsest level, the
+         * coarser level's flow below it */
+        if (l < L - 1)
+            oref_patch_init_coarser(Wl, Hl, ps, stride, Uc, lw[l + 1], lh[l + 1], u0);
+        else if (prev_flow)
+            oref_patch_init_previous(Wl, Hl, l, ps, stride, prev_flow, W, H, u0);
+        oref_dis_level(Wl, Hl, pyr0 + loff[l], pyr1 + loff[l], ps, stride,
+                       iters, lambda, u0, pu);
         if (patch_uv)
-            memcpy(patch_uv + 2 * poff[l], pu, sizeof(double) * 2 * (size_t)nx * ny);
-
+            memcpy(patch_uv + 2 * poff[l], pu, sizeof(double) * 2 * np);
         double *Ul = (double *)malloc(sizeof(double) * 2 * (size_t)Wl * Hl);
-        densify(Wl, Hl, I0, I1, ps, stride, pu, Ul);
+        oref_densify(Wl, Hl, pyr0 + loff[l], pyr1 + loff[l], ps, stride, pu, Ul);
         free(Uc);
         Uc = Ul;
+        free(u0);
         free(pu);
-        free(gx);
-        free(gy);
-        free(T);
     }
     memcpy(flow, Uc, sizeof(double) * 2 * (size_t)W * H);
     free(Uc);
     return 0;
+}
+
+int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                  const float *pyr1, int32_t ps, int32_t stride,
+                  int32_t iters, double lambda, double *flow,
+                  double *patch_uv)
+{
+    return oref_dis_flow_warm(W, H, L, pyr0, pyr1, ps, stride, iters, lambda,
+                              NULL, flow, patch_uv);
 }

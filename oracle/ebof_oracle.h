@@ -78,6 +78,39 @@ int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
                   int32_t iters, double lambda, double *flow,
                   double *patch_uv);
 
+/* The same with a warm start: when prev_flow (2*W*H doubles, the dense
+ * level-0 flow of the previous window pair) is not NULL, the coarsest level
+ * starts from it (oref_patch_init_previous) instead of from zero. */
+int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                       const float *pyr1, int32_t ps, int32_t stride,
+                       int32_t iters, double lambda, const double *prev_flow,
+                       double *flow, double *patch_uv);
+
+/* The steps of one level, as oref_dis_flow composes them.  Patch
+ * displacements u0 / pu are (u, v) interleaved, patches row-major; a flow
+ * U is two planes of doubles.
+ *   oref_patch_init_coarser: u0 of a W x H level from the coarser level's
+ *     dense flow Uc (Wc x Hc): twice Uc at (floor((o+ps/2)/2)) per axis,
+ *     clamped into the coarser image.
+ *   oref_patch_init_previous: u0 of level `level` (W x H) of a W0 x H0
+ *     sensor from a dense level-0 flow Up: Up at ((o+ps/2) << level) per
+ *     axis, clamped into the sensor, divided by 2^level.
+ *   oref_dis_level: the inverse search of every patch from u0 (NULL = 0)
+ *     into pu, with the outlier reset.
+ *   oref_densify: the weighted mean of the covering patches' displacements
+ *     into U (2*W*H). */
+void oref_patch_init_coarser(int32_t W, int32_t H, int32_t ps, int32_t stride,
+                             const double *Uc, int32_t Wc, int32_t Hc,
+                             double *u0);
+void oref_patch_init_previous(int32_t W, int32_t H, int32_t level, int32_t ps,
+                              int32_t stride, const double *Up, int32_t W0,
+                              int32_t H0, double *u0);
+void oref_dis_level(int32_t W, int32_t H, const float *I0, const float *I1,
+                    int32_t ps, int32_t stride, int32_t iters, double lambda,
+                    const double *u0, double *pu);
+void oref_densify(int32_t W, int32_t H, const float *I0, const float *I1,
+                  int32_t ps, int32_t stride, const double *pu, double *U);
+
 /* Number of patches of one level: ceil((W-ps)/stride)+1 by the same in y. */
 int64_t oref_patch_count(int32_t W, int32_t H, int32_t ps, int32_t stride);
 
