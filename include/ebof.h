@@ -254,7 +254,9 @@ int ebof_stream_close(ebof_ctx *ctx, int32_t stream_id);
  * flow_out_dev (2*W*H floats) and mask_out_dev (W*H bytes, the reference
  * window's E_df) are device buffers written when the window completes; they
  * must stay alive until ebof_poll reports completion.  Returns EBOF_E_AGAIN
- * when the queue is full. */
+ * when the event staging is full for now (retry once earlier windows
+ * complete), EBOF_E_NOMEM when the window's host events (12 bytes each) can
+ * never fit the staging rings, whatever completes. */
 int ebof_submit(ebof_ctx *ctx, int32_t stream_id, const uint16_t *x,
                 const uint16_t *y, const int64_t *t, int64_t n, int64_t t0_us,
                 int events_on_device, float *flow_out_dev,

@@ -397,6 +397,12 @@ int ebof_submit(ebof_ctx* ctx, int32_t stream_id, const uint16_t* x, const uint1
         const size_t bx = a256(2 * (size_t)n), bt = a256(8 * (size_t)n);
         const size_t len = 2 * bx + bt;
         size_t doff, poff;
+        if (len > S->dev_ring_bytes || len > kPinnedRing) {
+            set_error("ebof_submit: %lld events (%zu bytes staged) exceed the event ring (%zu bytes device, %zu "
+                      "pinned)",
+                      (long long)n, len, S->dev_ring_bytes, kPinnedRing);
+            return EBOF_E_NOMEM;
+        }
         if (!S->dev_ring_alloc.alloc(len, &doff)) {
             set_error("ebof_submit: device event ring full");
             return EBOF_E_AGAIN;

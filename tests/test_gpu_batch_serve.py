@@ -14,6 +14,7 @@ import pytest
 import torch
 
 from paper_2112_10591_amd import synth
+from flowcheck import assert_flow_matches, masked, oracle_flow, ref_window
 
 pytestmark = pytest.mark.gpu
 
@@ -479,8 +480,9 @@ def test_serving_gap_resets_stream(ctx):
 
 def test_serving_admission_by_arena():
     """A context whose arena cannot hold a 1280x720 stream's resident state
-    refuses the stream (EBOF_E_NOMEM); a window larger than the event ring is
-    refused with EBOF_E_AGAIN."""
+    refuses the stream (EBOF_E_NOMEM); a window larger than the whole event
+    ring can never be admitted and is refused with EBOF_E_NOMEM too (not
+    EBOF_E_AGAIN, which a caller would retry for ever)."""
     c = L.ebof_create(arena_bytes=16 << 20)
     try:
         p_hd = L.ebof_params_default(1280, 720)
@@ -494,8 +496,108 @@ def test_serving_admission_by_arena():
         t = np.zeros(n, np.int64)
         f = torch.empty(2 * 346 * 260, dtype=torch.float32, device="cuda")
         m = torch.empty(346 * 260, dtype=torch.uint8, device="cuda")
-        assert L.ebof_submit(c, sid, p, x, x, t, 0, f, m) is None
+        with pytest.raises(L.EbofError) as ei:
+            L.ebof_submit(c, sid, p, x, x, t, 0, f, m)
+        assert ei.value.code == L.EBOF_E_NOMEM
         L.ebof_stream_close(c, sid)
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+# --------------------------------------------------------------------------
+# the batched and served forms against the CPU oracle
+# --------------------------------------------------------------------------
+def _oracle_check(p, ev0, ev1, out0, out1, tag):
+    """Window k-1 and k of one stream against the oracle: edge image,
+    squared distances (when exported) and pyramid bit for bit, and the
+    masked flow k-1 -> k to the flow bars."""
+    W, H = p.width, p.height
+    r0, r1 = ref_window(p, ev0), ref_window(p, ev1)
+    for r, o, k in ((r0, out0, 0), (r1, out1, 1)):
+        assert np.array_equal(o["edge"].cpu().numpy().reshape(H, W), r["Edf"]), (tag, k, "edge")
+        if o.get("d2") is not None:
+            assert np.array_equal(o["d2"].cpu().numpy().reshape(H, W), r["D2"]), (tag, k, "d2")
+        assert np.array_equal(o["pyr"].cpu().numpy(), r["pyr"]), (tag, k, "pyramid")
+    f = out1["flow"].cpu().numpy().reshape(2, H, W).astype(np.float64)
+    ref = masked(r0, oracle_flow(p, r0, r1))
+    assert np.all(f[:, ~r0["Edf"].astype(bool)] == 0.0), tag
+    assert_flow_matches(f, ref, tag)
+
+
+def test_batch_c3_vs_oracle(ctx):
+    """The 16-stream batch (10 x 346x260, 6 x 1280x720, lognormal event
+    counts, own affine motions): two consecutive windows of every stream, one
+    ebof_run_batch per window index, each window against the oracle."""
+    streams = synth.c3_streams()
+    ps, evs, outs = [], [], []
+    for s in streams:
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+        W, H, P = s.W, s.H, L.ebof_pyramid_floats(p)
+        ps.append(p)
+        evs.append([s.window(k) for k in (0, 1)])
+        outs.append([dict(edge=torch.empty(W * H, dtype=torch.uint8, device="cuda"),
+                          d2=torch.empty(W * H, dtype=torch.int32, device="cuda"),
+                          pyr=torch.empty(P, dtype=torch.float32, device="cuda"),
+                          flow=torch.empty(2 * W * H, dtype=torch.float32, device="cuda")) for _ in (0, 1)])
+    dev_ev = [[dict(x=dev(e["x"]), y=dev(e["y"]), t=dev(e["t"]), t0=e["t0"]) for e in ev] for ev in evs]
+    stream = torch.cuda.Stream()
+    for k in (0, 1):
+        batch = []
+        for i, p in enumerate(ps):
+            e, o = dev_ev[i][k], outs[i][k]
+            w = dict(params=p, x=e["x"], y=e["y"], t=e["t"], t0_us=e["t0"], edge_out=o["edge"], d2_out=o["d2"],
+                     pyr_out=o["pyr"])
+            if k:
+                w.update(pyr_prev=outs[i][0]["pyr"], mask=outs[i][0]["edge"], flow_out=o["flow"])
+            batch.append(w)
+        _say(f"C3 batch, window {k}: {len(batch)} windows")
+        L.ebof_run_batch(ctx, batch, stream=stream)
+    torch.cuda.synchronize()
+    for i, p in enumerate(ps):
+        _oracle_check(p, evs[i][0], evs[i][1], outs[i][0], outs[i][1], f"C3 stream {i} ({p.width}x{p.height})")
+
+
+def test_serving_c4_mix_vs_oracle(ctx):
+    """Six cameras of the serving workload, two per resolution class
+    (346x260, 640x480, 1280x720), three windows each, submitted interleaved
+    (host events for half of them) and batched as they arrive: every flow
+    and mask against the oracle."""
+    cams = [synth.c4_camera(c) for c in range(6)]
+    nwin = 3
+    ps = [L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW) for s in cams]
+    evs = [[s.window(k) for k in range(nwin)] for s in cams]
+    sids = [L.ebof_stream_open(ctx, p) for p in ps]
+    res = {}
+    for k in range(nwin):
+        for c, (s, p) in enumerate(zip(cams, ps)):
+            W, H = s.W, s.H
+            f = torch.full((2 * W * H,), 7.0, dtype=torch.float32, device="cuda")
+            m = torch.full((W * H,), 9, dtype=torch.uint8, device="cuda")
+            ev = evs[c][k]
+            if c % 2:
+                x, y, t = ev["x"], ev["y"], ev["t"]
+            else:
+                x, y, t = dev(ev["x"]), dev(ev["y"]), dev(ev["t"])
+            tk = None
+            while tk is None:
+                tk = L.ebof_submit(ctx, sids[c], p, x, y, t, ev["t0"], f, m)
+            res[(c, k)] = (tk, f, m, (x, y, t))
+    _say(f"C4 mix: served {len(res)} windows")
+    L.ebof_drain(ctx)
+    for c, (s, p) in enumerate(zip(cams, ps)):
+        W, H = s.W, s.H
+        refs = [ref_window(p, evs[c][k]) for k in range(nwin)]
+        for k in range(nwin):
+            tk, f, m, _ = res[(c, k)]
+            st = L.ebof_poll(ctx, tk)
+            if k == 0:
+                assert st == L.EBOF_NO_FLOW
+                continue
+            assert st == L.EBOF_OK
+            r0, r1 = refs[k - 1], refs[k]
+            assert np.array_equal(m.cpu().numpy().reshape(H, W), r0["Edf"]), (c, k, "mask")
+            fl = f.cpu().numpy().reshape(2, H, W).astype(np.float64)
+            assert_flow_matches(fl, masked(r0, oracle_flow(p, r0, r1)), f"C4 camera {c} ({W}x{H}) window {k}")
+    for sid in sids:
+        L.ebof_stream_close(ctx, sid)

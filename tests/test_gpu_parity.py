@@ -3,7 +3,8 @@
 Integer stages (edge image, denoise/fill, squared distances) must be
 bit-exact; the surface is compared bit-exactly too (both sides round the same
 double-precision expression once); pyramid levels within 1e-6 relative; the
-flow within 0.01 px mean endpoint error of the oracle.
+flow within 0.01 px mean endpoint error of the oracle and per pixel within
+the bars of flowcheck.py.
 """
 import numpy as np
 import pytest
@@ -11,6 +12,7 @@ import torch
 
 import oracle
 from paper_2112_10591_amd import synth
+from flowcheck import assert_flow_matches, epe, oracle_flow, ref_window
 
 pytestmark = pytest.mark.gpu
 
@@ -54,11 +56,6 @@ def gpu_window(ctx, p, ev, d2=True):
     out["_pyr_dev"] = pyr
     out["_edge_dev"] = edge
     return out
-
-
-def ref_window(p, ev):
-    return oracle.window(p.width, p.height, ev["x"], ev["y"], ev["t"], ev["t0"], p.dt_us, p.n_d, p.n_f,
-                         float(np.float32(p.alpha)), p.levels)
 
 
 def check_window(g, r, p):
@@ -162,8 +159,17 @@ def gpu_flow(ctx, p, pyr0, pyr1, mask=None):
     return f.cpu().numpy().reshape(2, H, W).astype(np.float64)
 
 
-def epe(a, b):
-    return np.hypot(a[0] - b[0], a[1] - b[1])
+def windows_gpu_and_oracle(ctx, p, evs):
+    """Both sides from the same events: the GPU windows (checked bit for bit
+    against the oracle's edge image, squared distances, surface and pyramid)
+    and the oracle windows."""
+    out = []
+    for ev in evs:
+        g = gpu_window(ctx, p, ev)
+        r = ref_window(p, ev)
+        check_window(g, r, p)
+        out.append((g, r))
+    return out
 
 
 def test_flow_zero_motion_exact(ctx):
@@ -175,17 +181,30 @@ def test_flow_zero_motion_exact(ctx):
     assert np.all(f == 0.0)
 
 
+def test_flow_empty_windows_exact_zero(ctx):
+    """A window with no events has the surface 1.0 everywhere: as the
+    reference its template gradient is 0, so b = 0 and no patch moves; the
+    flow is exactly 0 whatever the other window holds."""
+    p = L.ebof_params_default(346, 260)
+    empty = dict(x=np.zeros(0, np.uint16), y=np.zeros(0, np.uint16), t=np.zeros(0, np.int64), t0=0)
+    s = synth.c1_stream(0)
+    (ge, re), (g1, r1) = windows_gpu_and_oracle(ctx, p, [empty, s.window(1)])
+    assert np.all(re["pyr"] == 1.0)
+    _say("flow empty -> empty, empty -> C1 window")
+    f = gpu_flow(ctx, p, ge["_pyr_dev"], ge["_pyr_dev"])
+    assert np.all(f == 0.0)
+    f = gpu_flow(ctx, p, ge["_pyr_dev"], g1["_pyr_dev"])
+    assert np.all(f == 0.0)
+    assert np.all(oracle_flow(p, re, r1) == 0.0)
+
+
 def test_flow_c1_parity_and_known_translation(ctx):
     s = synth.c1_stream(0)
     p = L.ebof_params_default(s.W, s.H)
-    g0 = gpu_window(ctx, p, s.window(0), d2=False)
-    g1 = gpu_window(ctx, p, s.window(1), d2=False)
-    _say("flow C1 pair")
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(0), s.window(1)])
+    _say("flow C1 pair (346x260, L3)")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-    r = oracle.dis_flow(g0["pyr"], g1["pyr"], s.W, s.H, p.levels, lam=float(np.float32(p.lambda_reg)))
-    e = epe(f, r)
-    _say(f"  C1 EPE vs oracle mean {e.mean():.2e} p99 {np.percentile(e, 99):.2e} max {e.max():.2e}")
-    assert e.mean() <= 0.01
+    assert_flow_matches(f, oracle_flow(p, r0, r1), "C1")
     m = g0["edge"][16:-16, 16:-16].astype(bool)
     assert abs(np.median(f[0][16:-16, 16:-16][m]) - 2.5) <= 0.05
     assert abs(np.median(f[1][16:-16, 16:-16][m]) + 1.5) <= 0.05
@@ -195,7 +214,7 @@ def test_flow_c1_parity_and_known_translation(ctx):
 def test_flow_integer_shift(ctx, d):
     """Two windows with the same sparse random events, the second shifted by
     an integer displacement (no denoise/fill): the flow recovers the shift
-    away from the border, and matches the oracle on the same pyramids."""
+    away from the border, and matches the oracle."""
     H, W = 120, 160
     rng = np.random.default_rng(5)
     n = int(0.03 * W * H)
@@ -206,56 +225,83 @@ def test_flow_integer_shift(ctx, d):
     ev0 = dict(x=x.astype(np.uint16), y=y.astype(np.uint16), t=np.zeros(n, np.int64), t0=0)
     ev1 = dict(x=x1[keep].astype(np.uint16), y=y1[keep].astype(np.uint16),
                t=np.zeros(int(keep.sum()), np.int64), t0=0)
-    g0 = gpu_window(ctx, p, ev0, d2=False)
-    g1 = gpu_window(ctx, p, ev1, d2=False)
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [ev0, ev1])
     _say(f"flow integer shift {d}")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
     inner = (slice(12, H - 12), slice(12, W - 12))
     e = np.hypot(f[0][inner] - d[0], f[1][inner] - d[1])
     assert np.median(e) < 1e-4 and np.mean(e < 0.05) > 0.98
-    r = oracle.dis_flow(g0["pyr"], g1["pyr"], W, H, 3, lam=float(np.float32(p.lambda_reg)))
-    assert epe(f, r).mean() <= 0.01
+    assert_flow_matches(f, oracle_flow(p, r0, r1), f"shift {d}")
+
+
+def test_flow_smooth_texture_damped_bias(ctx):
+    """A smooth texture shifted by (2, -1) px, pyramids uploaded directly.
+    At lambda = 0.3 the 16 damped steps stop short on weakly textured
+    patches (the solver's bias against the true shift, a property of the
+    method as configured); the GPU must reproduce the oracle's flow, bias
+    included, to the per-pixel bar."""
+    ndi = pytest.importorskip("scipy.ndimage")
+    rng = np.random.default_rng(6)
+    H, W, d = 120, 160, (2, -1)
+    big = ndi.gaussian_filter(rng.random((H + 8, W + 8)), 2.0)
+    big = (big - big.min()) / (big.max() - big.min())
+    I0 = big[4:4 + H, 4:4 + W].astype(np.float32)
+    I1 = big[4 - d[1]:4 - d[1] + H, 4 - d[0]:4 - d[0] + W].astype(np.float32)
+    p = L.ebof_params_default(W, H, levels=3)
+    pyr0, _ = oracle.pyramid(I0, 3)
+    pyr1, _ = oracle.pyramid(I1, 3)
+    _say("flow smooth texture, damped")
+    f = gpu_flow(ctx, p, dev(pyr0), dev(pyr1))
+    r = oracle.dis_flow(pyr0, pyr1, W, H, 3, lam=float(np.float32(p.lambda_reg)))
+    assert_flow_matches(f, r, "smooth texture")
+    inner = (slice(12, H - 12), slice(12, W - 12))
+    bias = np.hypot(r[0][inner] - d[0], r[1][inner] - d[1])
+    _say(f"  oracle bias to the true shift: median {np.median(bias):.2e} p90 {np.percentile(bias, 90):.2e} px")
+    assert np.median(bias) < 0.05
 
 
 def test_flow_c2_parity(ctx):
     s = synth.c2_stream(0)
     p = L.ebof_params_default(s.W, s.H)
-    g0 = gpu_window(ctx, p, s.window(4), d2=False)
-    g1 = gpu_window(ctx, p, s.window(5), d2=False)
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(4), s.window(5)])
     _say("flow C2 pair (1280x720, L4)")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-    r = oracle.dis_flow(g0["pyr"], g1["pyr"], s.W, s.H, p.levels, lam=float(np.float32(p.lambda_reg)))
-    e = epe(f, r)
-    _say(f"  C2 EPE vs oracle mean {e.mean():.2e} p99 {np.percentile(e, 99):.2e} max {e.max():.2e}")
-    assert e.mean() <= 0.01
+    assert_flow_matches(f, oracle_flow(p, r0, r1), "C2")
 
 
-def test_flow_mask(ctx):
+def test_flow_c5_parity(ctx):
+    """The stress workload: 1280x720, 2M events per window, 30 % noise, eight
+    polygons moving up to 20 px over an expansion field, 5 levels."""
+    s = synth.c5_stream(0)
+    p = L.ebof_params_default(s.W, s.H, levels=5)
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(0), s.window(1)])
+    _say("flow C5 pair (1280x720, L5, 2M events)")
+    f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
+    assert_flow_matches(f, oracle_flow(p, r0, r1), "C5")
+
+
+def test_flow_mask_vs_oracle(ctx):
+    """EBOF_MASK_FLOW: the flow is the oracle's on the reference window's
+    edge pixels (E_df of window k-1, Sec. III-D) and exactly 0 elsewhere."""
     s = synth.c1_stream(0)
     p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
-    g0 = gpu_window(ctx, p, s.window(0), d2=False)
-    g1 = gpu_window(ctx, p, s.window(1), d2=False)
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(0), s.window(1)])
     _say("flow masked")
     fm = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], mask=g0["_edge_dev"])
-    p2 = L.ebof_params_default(s.W, s.H)
-    fd = gpu_flow(ctx, p2, g0["_pyr_dev"], g1["_pyr_dev"])
-    m = g0["edge"].astype(bool)
+    m = r0["Edf"].astype(bool)
+    ref = np.where(m[None], oracle_flow(p, r0, r1), 0.0)
     assert np.all(fm[:, ~m] == 0.0)
-    assert np.array_equal(fm[:, m], fd[:, m])
+    assert_flow_matches(fm, ref, "masked C1")
+    assert_flow_matches(fm, ref, "masked C1, edge pixels", where=m)
 
 
 def test_flow_odd_sizes_and_strides(ctx):
     for (W, H, lv, st) in [(8, 8, 1, 4), (9, 17, 1, 3), (77, 51, 3, 4), (130, 66, 2, 2), (64, 40, 2, 8),
-                           (520, 400, 5, 4)]:
+                           (520, 400, 5, 4), (10, 10, 1, 4), (18, 26, 1, 3)]:
         _say(f"flow odd W={W} H={H} L={lv} stride={st}")
-        p = L.ebof_params_default(W, H, levels=lv, stride=st)
-        ev0 = random_events(W, H, W * H // 6, 21)
-        ev1 = random_events(W, H, W * H // 6, 22)
-        p_ = dict(n_d=0, n_f=5)
-        for k, v in p_.items():
-            setattr(p, k, v)
-        g0 = gpu_window(ctx, p, ev0, d2=False)
-        g1 = gpu_window(ctx, p, ev1, d2=False)
+        p = L.ebof_params_default(W, H, levels=lv, stride=st, n_d=0, n_f=5)
+        ev0 = random_events(W, H, max(4, W * H // 6), 21)
+        ev1 = random_events(W, H, max(4, W * H // 6), 22)
+        (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [ev0, ev1])
         f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-        r = oracle.dis_flow(g0["pyr"], g1["pyr"], W, H, lv, stride=st, lam=float(np.float32(p.lambda_reg)))
-        assert epe(f, r).mean() <= 0.01, (W, H, lv, st)
+        assert_flow_matches(f, oracle_flow(p, r0, r1), f"{W}x{H} L{lv} s{st}")
