@@ -44,7 +44,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c1", action="store_true", help="skip the 346x260 plain section")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="oracle flows in the CPU sample (~15 s)")
+    ap.add_argument("--cpu-sample", type=int, default=12,
+                    help="oracle flows in the single-thread CPU sample (~8 s)")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="threads of the multi-threaded CPU sample (two flows each)")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--serving-pool", type=int, default=12, help="pre-generated windows per camera")
@@ -69,12 +72,20 @@ def parse():
 # ----------------------------------------------------------------------------
 # algorithmic work per kernel
 # ----------------------------------------------------------------------------
-def dis_flops_per_patch(iters, init):
-    # per iteration and pixel: 9/8 horizontal + 1 vertical lerp (3 flops
-    # each), residual (1), two FMAs into b (4) ~ 11; solve + update 8 per
-    # patch; set-up per pixel: template gradient 4 + Hessian 6; init from the
-    # coarser level ~4 covering patches x 40.
-    return iters * (64 * 11 + 8) + 64 * 10 + (160 if init else 0)
+def dis_flops_per_patch(iters):
+    # the algorithmic count of the inverse search: per iteration and pixel of
+    # the 8x8 patch a bilinear sample, its residual and its two products into
+    # b, about 15 flops; per patch about 640 more for the template gradient,
+    # the Hessian and its inverse
+    return 15 * 64 * iters + 640
+
+
+def path_bytes(E, P, N):
+    """Algorithmic HBM bytes of one window through the whole path, with the
+    previous pyramid resident: its events read (12 B each), its pyramid
+    written (4P), both pyramids read by the flow (8P), the flow (8N) and the
+    mask (N) written."""
+    return 12 * E + 12 * P + 9 * N
 
 
 # The command the committed profiles are taken over (the plain 1280x720 path;
@@ -251,8 +262,68 @@ def dis_flops_window(L, p):
     tot = 0
     for l, (w, h) in enumerate(L.level_sizes(p)):
         n = ((w - 8 + p.stride - 1) // p.stride + 1) * ((h - 8 + p.stride - 1) // p.stride + 1)
-        tot += n * dis_flops_per_patch(p.iters, l < p.levels - 1)
+        tot += n * dis_flops_per_patch(p.iters)
     return tot
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_baseline(p, c2, n_single, n_threads):
+    """The oracle (plain C, one window or one flow per call) on the host
+    cores: the full path of consecutive 1280x720 windows (edge image through
+    pyramid per window, flow per pair), once on one thread and once over
+    n_threads threads (ctypes releases the interpreter lock, so the calls run
+    in parallel: windows first, then the flows of the pairs).  Returns the
+    baseline record and the first flows (for the GPU's endpoint error)."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+
+    def win(k):
+        ev = c2[k]
+        return oracle.window(p.width, p.height, ev["x"], ev["y"], ev["t"], ev["t0"], p.dt_us, p.n_d, p.n_f,
+                             float(np.float32(p.alpha)), p.levels)
+
+    def flow(r0, r1):
+        return oracle.dis_flow(r0["pyr"], r1["pyr"], p.width, p.height, p.levels, stride=p.stride,
+                               iters=p.iters, lam=float(np.float32(p.lambda_reg)))
+
+    ns = max(1, n_single)
+    t0 = time.time()
+    rs = [win(0)]
+    flows = {}
+    for k in range(1, ns + 1):
+        rs.append(win(k))
+        flows[k] = (flow(rs[k - 1], rs[k]), rs[k - 1]["Edf"].astype(bool))
+        rs[k - 1] = None
+    dt1 = time.time() - t0
+    log(f"cpu oracle, 1 thread: {ns / dt1:.3f} frames/s over {dt1:.1f}s")
+    nt = max(1, n_threads)
+    nm = 2 * nt  # flows in the threaded sample: two per thread
+    base = ns + 1
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(nt) as ex:
+        ws = list(ex.map(win, [(base + k) % len(c2) for k in range(nm + 1)]))
+        list(ex.map(lambda k: flow(ws[k], ws[k + 1]), range(nm)))
+    dtn = time.time() - t0
+    log(f"cpu oracle, {nt} threads: {nm / dtn:.3f} frames/s over {dtn:.1f}s")
+    cpu = {"value": nm / dtn, "unit": "frames/s", "cores": nt, "kind": "oracle",
+           "sample": f"{nm + 1} consecutive 1280x720 windows of 300k events (the first primes), full path per "
+                     f"window incl. flow, plain C oracle on {nt} threads (windows, then flows, in parallel), "
+                     f"{dtn:.1f}s",
+           "single_thread": {"value": ns / dt1, "cores": 1,
+                             "sample": f"{ns + 1} consecutive windows, one thread, {dt1:.1f}s"},
+           "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count()}
+    return cpu, flows
 
 
 def pipelined_driver(lib, h, sptrs, NB, slot0, preprocess, flow_of):
@@ -320,7 +391,7 @@ def main():
 
     from paper_2112_10591_amd import synth
     K, Wm = args.steps, args.warmup
-    nwin = min(200, K + Wm + 1)
+    nwin = 200  # the 1280x720 sequence; timed windows run through it in order, wrapping around
     t_gen = time.time()
     c2 = synth.generate("c2", 0, range(nwin), workers=args.workers)
     c3 = []
@@ -343,25 +414,7 @@ def main():
     from paper_2112_10591_amd import _lib as L
     p = L.ebof_params_default(1280, 720, flags=L.EBOF_MASK_FLOW)
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        ns = max(1, args.cpu_sample)
-        t0 = time.time()
-        prev = None
-        for k in range(ns + 1):
-            ev = c2[k]
-            r = oracle.window(p.width, p.height, ev["x"], ev["y"], ev["t"], ev["t0"], p.dt_us, p.n_d,
-                              p.n_f, float(np.float32(p.alpha)), p.levels)
-            if prev is not None:
-                fl = oracle.dis_flow(prev["pyr"], r["pyr"], p.width, p.height, p.levels, stride=p.stride,
-                                     iters=p.iters, lam=float(np.float32(p.lambda_reg)))
-                oracle_flows[k] = (fl, prev["Edf"].astype(bool))
-            prev = r
-        dt = time.time() - t0
-        cpu = {"value": ns / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"{ns + 1} consecutive 1280x720 windows of 300k events (window 0 primes), "
-                         f"full path per window incl. flow, single-threaded plain C, {dt:.1f}s"}
-        log(f"cpu oracle: {cpu['value']:.3f} frames/s over {dt:.1f}s")
+        cpu, oracle_flows = cpu_oracle_baseline(p, c2, args.cpu_sample, args.cpu_threads)
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
@@ -553,6 +606,12 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic({"pyr_down": "k_pyr_chain"}.get(dominant, "k_" + dominant)),
                 **timing}
 
+    # ---------------- the whole path against the HBM roofline ----------------
+    ev_mean = float(np.mean([e["n"] for e in evs]))
+    copy_gbs = measured_copy_gbs(dev)
+    path_roof = path_roofline(path_bytes(ev_mean, P, N), fps, copy_gbs)
+    path_roof["events_per_window_mean"] = ev_mean
+
     out = {
         "metric": METRIC,
         "value": fps,
@@ -566,11 +625,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1280x720 plain single camera stream: 200 windows x 300k events, 300 segments + "
-                               "50 ellipses under a random affine walk, 10% noise, L=4, patch 8 stride 4, "
-                               "16 iterations, flow masked to the reference edge pixels",
-                   "windows": len(c2), "events_per_window": 300_000, "width": W, "height": H,
-                   "levels": p.levels},
+        "config": {"workload": f"1280x720 plain single camera stream: a sequence of {len(c2)} windows x 300k "
+                               "events (300 segments + 50 ellipses under a random affine walk, 10% noise), "
+                               f"timed over {K} consecutive windows of it (wrapping around), L=4, patch 8 "
+                               "stride 4, 16 iterations, flow masked to the reference edge pixels",
+                   "windows": len(c2), "timed_windows": K, "events_per_window": 300_000, "width": W,
+                   "height": H, "levels": p.levels},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "kind": "plain, one window at a time, issue to completion"},
         "plain_form": "sequential" if args.sequential_only else "pipelined",
@@ -580,6 +640,8 @@ def main():
         "epe_vs_oracle_px": epe,
         "kernels_ms_per_window": {k: v["ms_per_window"] for k, v in breakdown.items()},
         "roofline": roof,
+        "path_roofline": path_roof,
+        "hbm_copy_measured_GBs": copy_gbs,
         "cpu_baseline": cpu,
         "paper_context": "77 Hz at 1280x720 and 250 Hz at 346x260 with the paper's filter-flow library on "
                          "an i9-9880H + Quadro RTX 5000 (different flow method and hardware)",
@@ -597,7 +659,7 @@ def main():
                                    iters=p1.iters, lam=float(np.float32(p1.lambda_reg))),
                    rs[0]["Edf"].astype(bool))
     if c1:
-        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, streams, c1_pair)
+        out["c1_plain"] = bench_c1(L, ctx, c1, K, dev, streams, c1_pair, copy_gbs)
 
     # ---------------- batched form: 16 mixed-resolution streams -------------
     if c3:
@@ -610,7 +672,37 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair):
+def measured_copy_gbs(dev, mib=1024, reps=5):
+    """HBM rate of a plain device-to-device copy (torch copy_ of mib MiB):
+    bytes read plus bytes written per second, the best of reps, timed by
+    events on the current stream."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * (mib << 20) / (best * 1e-3) / 1e9
+
+
+def path_roofline(bytes_per_window, fps, copy_gbs):
+    """The window rate against the one the path's algorithmic bytes allow at
+    the HBM peak (and at the measured copy rate)."""
+    gbs = bytes_per_window * fps / 1e9
+    return {"bytes_per_window": bytes_per_window, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
+            "frac": gbs / HBM_PEAK_GBS, "frac_of_measured_copy": gbs / copy_gbs,
+            "roofline_frames_per_s": HBM_PEAK_GBS * 1e9 / bytes_per_window}
+
+
+def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair, copy_gbs):
     """The 346x260 plain path, sequential and pipelined, on the 1280x720
     section's streams."""
     """346x260 plain path (the low-resolution config): sequential and
@@ -679,10 +771,11 @@ def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair):
     pipelined(k0, k0 + steps)
     torch.cuda.synchronize()
     fps = steps / (time.perf_counter() - t0)
-    res = {"workload": "346x260 plain single camera stream, 20k events per window, 40 segments translating "
-                       "(+2.5, -1.5) px per window, 5% noise, L=3",
-           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "streams": NS,
-           "epe_vs_oracle_px": epe}
+    ev_mean = float(np.mean([e["n"] for e in evs]))
+    res = {"workload": f"346x260 plain single camera stream, {len(c1)} windows of 20k events, 40 segments "
+                       "translating (+2.5, -1.5) px per window, 5% noise, L=3",
+           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "streams": NS, "timed_windows": steps,
+           "epe_vs_oracle_px": epe, "path_roofline": path_roofline(path_bytes(ev_mean, P, N), fps, copy_gbs)}
     log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined; EPE vs oracle {epe}")
     return res
 
@@ -926,7 +1019,9 @@ def bench_serving(L, c4, seconds, dev):
            "saturation": {"frames_per_s": n_sat / t_sat, "hd_frames_per_s": hd_sat / t_sat,
                           "latency_ms": _lat_stats(sat_lat), "latency_ms_hd": _lat_stats(sat_lat, True)},
            "pool_windows_per_camera": len(cams[0]["evs"]),
-           "note": "events pre-generated and resident on the device, replayed palindromically"}
+           "note": f"{seconds:g} s of Poisson arrivals (the workload names 60 s; the rates settle within a "
+                   f"second) from a pool of {len(cams[0]['evs'])} pre-generated windows per camera (the "
+                   "workload names 64), resident on the device and replayed palindromically"}
     log(f"serving: offered {res['offered_frames_per_s']:.0f}/s, p50/p99 {res['latency_ms']['p50']:.2f}/"
         f"{res['latency_ms']['p99']:.2f} ms; saturation {res['saturation']['frames_per_s']:.0f} frames/s")
     for cam in cams:

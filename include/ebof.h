@@ -65,6 +65,9 @@ extern "C" {
                                 stream's previous window, whatever its t0 (by
                                 default a t0 other than previous t0 + dt_us
                                 starts the stream over, EBOF_NO_FLOW)       */
+#define EBOF_WARM_START 4u  /* served stream: the coarsest level starts from
+                                the stream's previous flow (kept resident),
+                                as ebof_flow_warm does, instead of from 0   */
 
 typedef struct ebof_ctx ebof_ctx; /* opaque, library-owned */
 
@@ -82,7 +85,7 @@ typedef struct {
     int32_t stride;        /* patch grid stride, 1..8                        */
     int32_t iters;         /* inverse-search iterations per patch, 0..1024   */
     float lambda_reg;      /* Tikhonov term added to the patch Hessian, > 0  */
-    uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS             */
+    uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START */
 } ebof_params;
 
 /* Defaults of Sec. IV-A for a sensor of the given size: N_d = 1, N_f = 4 up to
@@ -184,6 +187,23 @@ int ebof_flow(ebof_ctx *ctx, const ebof_params *p, const float *pyr_prev,
               const float *pyr_curr, const uint8_t *mask, float *flow_out,
               void *hip_stream);
 
+/* Sec. III-D (the temporal propagation the paper values in its flow method,
+ * reduced to a prediction of constant motion): ebof_flow with the coarsest
+ * level warm-started from the previous window pair's flow.  flow_init: NULL
+ * (then exactly ebof_flow) or device 2*width*height floats, the dense flow
+ * k-2 -> k-1 before masking; a patch of the coarsest level l = L-1 starts
+ * from flow_init at the level-0 pixel under its centre,
+ * (min((o_x + 4) * 2^l, width-1), min((o_y + 4) * 2^l, height-1)), divided
+ * by 2^l (a level-0 displacement spans 2^l times fewer pixels there); finer
+ * levels start from the coarser level as in ebof_flow.  flow_dense_out: NULL
+ * or device 2*width*height floats receiving the flow before masking (what a
+ * later call takes as its flow_init; equal to flow_out without
+ * EBOF_MASK_FLOW).  Same errors as ebof_flow. */
+int ebof_flow_warm(ebof_ctx *ctx, const ebof_params *p, const float *pyr_prev,
+                   const float *pyr_curr, const uint8_t *mask,
+                   const float *flow_init, float *flow_out,
+                   float *flow_dense_out, void *hip_stream);
+
 /* ---- batched form ---------------------------------------------------------
  * One descriptor per window; every stage of every window of the batch runs
  * in one kernel launch per stage (one per pyramid level for the pyramid and
@@ -202,6 +222,9 @@ typedef struct {
     const uint8_t *mask;    /* E_df of window k-1 for EBOF_MASK_FLOW      */
     float *flow_out;        /* device 2*W*H floats, used if pyr_prev      */
     uint64_t *n_dropped_dev;/* NULL or device counter (added to)          */
+    const float *flow_init; /* NULL, or the previous pair's flow: warm start
+                               of the coarsest level as in ebof_flow_warm  */
+    float *flow_dense_out;  /* NULL, or device 2*W*H: flow before masking  */
 } ebof_window;
 
 /* Runs n (1..EBOF_MAX_BATCH) windows on the caller's stream.  Window i's
@@ -238,8 +261,10 @@ int ebof_run_batch(ebof_ctx *ctx, const ebof_window *w, int32_t n,
 int ebof_set_tuning(ebof_ctx *ctx, int mode, const char *cache_path);
 
 /* ---- serving ----------------------------------------------------------------
- * A served stream keeps its previous window's pyramid and edge image in the
- * arena.  Windows are admitted while their arena bytes fit, batched as they
+ * A served stream keeps its previous window's pyramid, edge image and flow
+ * (before masking) in the arena; with EBOF_WARM_START in its parameters the
+ * coarsest level of each flow starts from that previous flow (ebof_flow_warm),
+ * from the stream's third window on (the second has no previous flow).  Windows are admitted while their arena bytes fit, batched as they
  * arrive, and run on the context's own HIP stream; each submitted window
  * yields the flow from the stream's previous window (EBOF_NO_FLOW for the
  * first window after open). */

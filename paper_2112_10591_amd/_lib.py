@@ -26,6 +26,7 @@ EBOF_E_DEVICE = -5
 EBOF_E_STATE = -6
 EBOF_MASK_FLOW = 1
 EBOF_CHAIN_ALWAYS = 2
+EBOF_WARM_START = 4
 EBOF_MAX_BATCH = 1024
 EBOF_TUNE_OFF = 0
 EBOF_TUNE_AUTO = 1
@@ -80,6 +81,8 @@ class ebof_window(ctypes.Structure):
         ("mask", ctypes.c_void_p),
         ("flow_out", ctypes.c_void_p),
         ("n_dropped_dev", ctypes.c_void_p),
+        ("flow_init", ctypes.c_void_p),
+        ("flow_dense_out", ctypes.c_void_p),
     ]
 
 
@@ -108,6 +111,7 @@ def load():
         "ebof_edt_surface": ([P, pp, P, P, P, P], ctypes.c_int),
         "ebof_window_surface": ([P, pp, P, P, P, i64, i64, P, P, P, P, P], ctypes.c_int),
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
+        "ebof_flow_warm": ([P, pp, P, P, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
         "ebof_set_tuning": ([P, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "ebof_stream_open": ([P, pp, ctypes.POINTER(i32)], ctypes.c_int),
@@ -136,7 +140,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_run_batch", "ebof_set_tuning",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
@@ -295,6 +299,23 @@ def ebof_flow(ctx, p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
                                                 _stream(stream)))
 
 
+def ebof_flow_warm(ctx, p, pyr_prev, pyr_curr, flow_out, flow_init=None, flow_dense_out=None, mask=None,
+                   stream=None):
+    """ebof_flow with the coarsest level started from flow_init (the previous
+    pair's flow before masking); flow_dense_out receives this flow before
+    masking."""
+    P = ebof_pyramid_floats(p)
+    N = p.width * p.height
+    a = _dev(pyr_prev, torch.float32, P, "pyr_prev")
+    b = _dev(pyr_curr, torch.float32, P, "pyr_curr")
+    m = _dev(mask, torch.uint8, N, "mask", optional=True)
+    fi = _dev(flow_init, torch.float32, 2 * N, "flow_init", optional=True)
+    f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
+    fd = _dev(flow_dense_out, torch.float32, 2 * N, "flow_dense_out", optional=True)
+    return _check(ctx.handle, ctx.lib.ebof_flow_warm(ctx.handle, ctypes.byref(p), a, b, m, fi, f, fd,
+                                                     _stream(stream)))
+
+
 def ebof_set_tuning(ctx, mode=EBOF_TUNE_AUTO, cache_path=None):
     """Launch-shape tuning of the batched form (EBOF_TUNE_AUTO / EBOF_TUNE_OFF),
     optionally with a cache file of tuned layouts."""
@@ -314,7 +335,7 @@ def batch_layout_key(windows):
 
 def ebof_run_batch(ctx, windows, stream=None):
     """windows: list of dicts with keys params, x, y, t, t0_us, edge_out, pyr_out and
-    optionally d2_out, pyr_prev, mask, flow_out, n_dropped."""
+    optionally d2_out, pyr_prev, mask, flow_out, n_dropped, flow_init, flow_dense_out."""
     n = len(windows)
     if not 1 <= n <= EBOF_MAX_BATCH:
         raise ValueError("batch size out of range")
@@ -341,6 +362,8 @@ def ebof_run_batch(ctx, windows, stream=None):
         need_flow = w.get("pyr_prev") is not None
         a.flow_out = _dev(w.get("flow_out"), torch.float32, 2 * N, "flow_out", optional=not need_flow)
         a.n_dropped_dev = _dev(w.get("n_dropped"), torch.uint64, 1, "n_dropped", optional=True)
+        a.flow_init = _dev(w.get("flow_init"), torch.float32, 2 * N, "flow_init", optional=True)
+        a.flow_dense_out = _dev(w.get("flow_dense_out"), torch.float32, 2 * N, "flow_dense_out", optional=True)
     return _check(ctx.handle, ctx.lib.ebof_run_batch(ctx.handle, arr, n, _stream(stream)))
 
 

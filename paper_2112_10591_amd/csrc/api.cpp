@@ -95,7 +95,7 @@ static int validate(const ebof_params* p) {
         set_error("dt_us %lld must be > 0", (long long)p->dt_us);
         return EBOF_E_INVAL;
     }
-    if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS)) {
+    if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START)) {
         set_error("unknown flags 0x%x", p->flags);
         return EBOF_E_INVAL;
     }
@@ -658,6 +658,8 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
         d.pyr_prev = w[i].pyr_prev;
         d.mask = w[i].mask;
         d.flow = w[i].flow_out;
+        d.flow_init = w[i].pyr_prev ? w[i].flow_init : nullptr;
+        d.flow_keep = w[i].pyr_prev ? w[i].flow_dense_out : nullptr;
         d.n_dropped = (unsigned long long*)w[i].n_dropped_dev;
         if (extra) {
             d.mask_out = extra[i].mask_out;
@@ -1079,8 +1081,35 @@ int ebof_window_surface(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, 
     return launch_status(ctx);
 }
 
+// The inverse search, level by level, and the densification of window
+// descriptor d (timed per kernel when ctx has timing on).
+static void flow_launches(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d, hipStream_t st) {
+    Tune tune = kStageTune;
+    resolve_dis_lanes(tune, &d, 1);
+    auto dis = [&] {
+        for (int l = p->levels - 1; l >= 0; --l)
+            launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l, tune.dis_lanes[l]);
+    };
+    auto dens = [&] {
+        launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw);
+    };
+    if (ctx) {
+        timed(ctx, EBOF_K_DIS_LEVEL, st, dis);
+        timed(ctx, EBOF_K_DENSIFY, st, dens);
+    } else {
+        dis();
+        dens();
+    }
+}
+
 int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const float* pyr_curr, const uint8_t* mask,
               float* flow_out, void* hip_stream) {
+    return ebof_flow_warm(ctx, p, pyr_prev, pyr_curr, mask, nullptr, flow_out, nullptr, hip_stream);
+}
+
+int ebof_flow_warm(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const float* pyr_curr,
+                   const uint8_t* mask, const float* flow_init, float* flow_out, float* flow_dense_out,
+                   void* hip_stream) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;
     if ((rc = validate(p))) return rc;
@@ -1104,16 +1133,9 @@ int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const 
     d.pyr_prev = pyr_prev;
     d.mask = mask;
     d.flow = flow_out;
-    Tune tune = kStageTune;
-    resolve_dis_lanes(tune, &d, 1);
-    timed(
-        ctx, EBOF_K_DIS_LEVEL, st,
-        [&] {
-            for (int l = p->levels - 1; l >= 0; --l)
-                launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l,
-                                 tune.dis_lanes[l]);
-        });
-    timed(ctx, EBOF_K_DENSIFY, st, [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw); });
+    d.flow_init = flow_init;
+    d.flow_keep = flow_dense_out;
+    flow_launches(ctx, p, d, st);
     return launch_status(ctx);
 }
 

@@ -71,6 +71,9 @@ struct WinDesc {
     uint32_t zero_out;      // no reference window: flow and mask_out written as 0
     uint32_t pad1;
     float2* puv;            // patch displacements (u, v), all levels
+    const float* flow_init; // level-0 flow of the previous pair (2*W*H): the
+                            // coarsest level's start, or null (start at 0)
+    float* flow_keep;       // 2*W*H copy of the flow before masking, or null
     unsigned long long* n_dropped;  // optional counter
     LevelGeom lv[kMaxLevels];
 };

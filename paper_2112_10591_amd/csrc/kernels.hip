@@ -798,7 +798,18 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         // level's patch displacements as in the densification (every lane of
         // the patch forms the same sums, so the lane count changes no bit)
         double u0x = 0.0, u0y = 0.0;
-        if (level < d->L - 1) {
+        if (level == d->L - 1 && d->flow_init) {
+            // warm start: the previous pair's level-0 flow at the pixel under
+            // the patch centre, in pixels of this level (a power-of-two
+            // scale, exact)
+            const int W0 = d->W, H0 = d->H;
+            const int px = min((ox + kPatch / 2) << level, W0 - 1);
+            const int py = min((oy + kPatch / 2) << level, H0 - 1);
+            const double sc = 1.0 / (double)(1 << level);
+            const size_t q = (size_t)py * W0 + px;
+            u0x = (double)d->flow_init[q] * sc;
+            u0y = (double)d->flow_init[(size_t)W0 * H0 + q] * sc;
+        } else if (level < d->L - 1) {
             const LevelGeom gc = d->lv[level + 1];
             const float* __restrict__ C0 = d->pyr_prev + gc.off;
             const float* __restrict__ C1 = d->pyr + gc.off;
@@ -1045,6 +1056,10 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
         float sw, su, sv;
         dens_sums(I1, W, H, x, y, i0, pu, g.pnx, cx, cy, sw, su, sv);
         float fu = su / sw, fv = sv / sw;
+        if (d->flow_keep) {
+            d->flow_keep[pix] = fu;
+            d->flow_keep[(size_t)W * H + pix] = fv;
+        }
         const uint8_t m = d->mask ? d->mask[pix] : 1;
         if ((d->flags & EBOF_MASK_FLOW) && !m) fu = fv = 0.f;
         d->flow[pix] = fu;

@@ -1,7 +1,8 @@
 // serve.cpp -- serving runtime.
 //
-// A served stream keeps its last window's pyramid and edge image resident in
-// the arena (two of each, swapped per window) plus its own scratch; opening a
+// A served stream keeps its last window's pyramid, edge image and flow
+// (before masking) resident in the arena (two of each, swapped per window)
+// plus its own scratch; opening a
 // stream is admitted only while the arena can hold that state.  Submitted
 // windows are queued; their host events are copied into a pinned ring and
 // sent asynchronously (copy stream) into a device ring in the arena.  A
@@ -37,8 +38,10 @@ struct ServeStream {
     Scratch scr;
     float* pyr[2] = {nullptr, nullptr};
     uint8_t* edge[2] = {nullptr, nullptr};
+    float* flow[2] = {nullptr, nullptr};  // dense flow ending at the window of the same buffer
     int cur = 0;  // buffer of the newest window taken into a batch
     bool has_prev = false;
+    bool has_flow = false;  // the newest window computed a flow (flow[cur] is valid)
     int64_t last_t0 = 0;
     bool closing = false;
     int queued = 0;  // submitted and not completed
@@ -134,7 +137,7 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             const Pending& q = take[i];
             ServeStream& s = S->streams[q.sid];
             if (s.has_prev && !(s.p.flags & EBOF_CHAIN_ALWAYS) && q.t0 != s.last_t0 + s.p.dt_us)
-                s.has_prev = false;  // gap in time: start over
+                s.has_prev = s.has_flow = false;  // gap in time: start over
             const int nb = s.has_prev ? (s.cur ^ 1) : s.cur;
             ebof_window& w = win[i];
             std::memset(&w, 0, sizeof w);
@@ -149,6 +152,8 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             w.pyr_prev = s.has_prev ? s.pyr[s.cur] : nullptr;
             w.mask = s.has_prev ? s.edge[s.cur] : nullptr;
             w.flow_out = q.flow_out;
+            w.flow_dense_out = s.has_prev ? s.flow[nb] : nullptr;
+            w.flow_init = (s.has_prev && s.has_flow && (s.p.flags & EBOF_WARM_START)) ? s.flow[s.cur] : nullptr;
             ext[i].mask_out = q.mask_out;
             ext[i].zero_out = !s.has_prev;
             scr[i] = &s.scr;
@@ -157,6 +162,7 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             b.sids.push_back(q.sid);
             if (q.dev_ring) b.dev_offs.push_back(q.dev_off);
             if (q.copied) b.copy_events.push_back(q.copied);
+            s.has_flow = s.has_prev;
             s.cur = nb;
             s.has_prev = true;
             s.last_t0 = q.t0;
@@ -274,8 +280,10 @@ static void free_stream(ebof_ctx* ctx, ServeStream& s) {
     for (int i = 0; i < 2; ++i) {
         ctx->arena.free(s.pyr[i]);
         ctx->arena.free(s.edge[i]);
+        ctx->arena.free(s.flow[i]);
         s.pyr[i] = nullptr;
         s.edge[i] = nullptr;
+        s.flow[i] = nullptr;
     }
     scratch_free(ctx, &s.scr);
 }
@@ -308,17 +316,19 @@ int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
         for (int i = 0; i < 2; ++i) {
             s.pyr[i] = (float*)ctx->arena.alloc(s.g.pyr_floats * sizeof(float));
             s.edge[i] = (uint8_t*)ctx->arena.alloc(N);
-            ok = ok && s.pyr[i] && s.edge[i];
+            s.flow[i] = (float*)ctx->arena.alloc(2 * N * sizeof(float));
+            ok = ok && s.pyr[i] && s.edge[i] && s.flow[i];
         }
         if (ok) ok = scratch_alloc(ctx, s.g, &s.scr, S->stream) == EBOF_OK;
         if (!ok) {
             for (int i = 0; i < 2; ++i) {
                 ctx->arena.free(s.pyr[i]);
                 ctx->arena.free(s.edge[i]);
+                ctx->arena.free(s.flow[i]);
             }
             scratch_free(ctx, &s.scr);
             set_error("arena full: a %dx%d stream needs %zu bytes of resident state, %zu free", p->width, p->height,
-                      2 * (size_t)s.g.pyr_floats * 4 + 2 * N + (size_t)ebof_window_scratch_bytes(p),
+                      2 * (size_t)s.g.pyr_floats * 4 + 2 * N + 16 * N + (size_t)ebof_window_scratch_bytes(p),
                       ctx->arena.bytes_free());
             return EBOF_E_NOMEM;
         }

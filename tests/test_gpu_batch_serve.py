@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from paper_2112_10591_amd import synth
-from flowcheck import assert_flow_matches, masked, oracle_flow, ref_window
+from flowcheck import OracleFlow, assert_flow_matches, ref_window
 
 pytestmark = pytest.mark.gpu
 
@@ -520,7 +520,7 @@ def _oracle_check(p, ev0, ev1, out0, out1, tag):
             assert np.array_equal(o["d2"].cpu().numpy().reshape(H, W), r["D2"]), (tag, k, "d2")
         assert np.array_equal(o["pyr"].cpu().numpy(), r["pyr"]), (tag, k, "pyramid")
     f = out1["flow"].cpu().numpy().reshape(2, H, W).astype(np.float64)
-    ref = masked(r0, oracle_flow(p, r0, r1))
+    ref = OracleFlow(p, r0, r1, mask=True)
     assert np.all(f[:, ~r0["Edf"].astype(bool)] == 0.0), tag
     assert_flow_matches(f, ref, tag)
 
@@ -598,6 +598,69 @@ def test_serving_c4_mix_vs_oracle(ctx):
             r0, r1 = refs[k - 1], refs[k]
             assert np.array_equal(m.cpu().numpy().reshape(H, W), r0["Edf"]), (c, k, "mask")
             fl = f.cpu().numpy().reshape(2, H, W).astype(np.float64)
-            assert_flow_matches(fl, masked(r0, oracle_flow(p, r0, r1)), f"C4 camera {c} ({W}x{H}) window {k}")
+            assert_flow_matches(fl, OracleFlow(p, r0, r1, mask=True), f"C4 camera {c} ({W}x{H}) window {k}")
+    for sid in sids:
+        L.ebof_stream_close(ctx, sid)
+
+
+def test_serving_warm_start_vs_oracle(ctx):
+    """EBOF_WARM_START through ebof_submit: three cameras (one per resolution
+    class), four windows each.  The second window's flow starts cold, every
+    later one from the stream's resident previous flow (kept before masking);
+    each is checked against the oracle's chain fed with its own previous
+    flow.  A gap in time starts the stream over (cold again)."""
+    cams = [synth.c4_camera(c) for c in range(3)]
+    nwin = 4
+    ps = [L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW | L.EBOF_WARM_START) for s in cams]
+    evs = [[s.window(k) for k in range(nwin)] for s in cams]
+    sids = [L.ebof_stream_open(ctx, p) for p in ps]
+    res = {}
+    for k in range(nwin):
+        for c, (s, p) in enumerate(zip(cams, ps)):
+            W, H = s.W, s.H
+            f = torch.full((2 * W * H,), 7.0, dtype=torch.float32, device="cuda")
+            m = torch.full((W * H,), 9, dtype=torch.uint8, device="cuda")
+            ev = evs[c][k]
+            x, y, t = dev(ev["x"]), dev(ev["y"]), dev(ev["t"])
+            tk = None
+            while tk is None:
+                tk = L.ebof_submit(ctx, sids[c], p, x, y, t, ev["t0"], f, m)
+            res[(c, k)] = (tk, f, m, (x, y, t))
+    _say(f"warm-started serving: {len(res)} windows")
+    L.ebof_drain(ctx)
+    for c, (s, p) in enumerate(zip(cams, ps)):
+        W, H = s.W, s.H
+        refs = [ref_window(p, evs[c][k]) for k in range(nwin)]
+        prev = None
+        for k in range(nwin):
+            tk, f, m, _ = res[(c, k)]
+            st = L.ebof_poll(ctx, tk)
+            if k == 0:
+                assert st == L.EBOF_NO_FLOW
+                continue
+            assert st == L.EBOF_OK
+            r0, r1 = refs[k - 1], refs[k]
+            o = OracleFlow(p, r0, r1, prev_flow=prev, mask=True)
+            fl = f.cpu().numpy().reshape(2, H, W).astype(np.float64)
+            assert_flow_matches(fl, o, f"warm camera {c} ({W}x{H}) window {k}")
+            prev = o.raw
+    # a gap in time: the stream starts over, and its next flow is cold again
+    c, s, p = 0, cams[0], ps[0]
+    W, H = s.W, s.H
+    outs = []
+    for j, k in enumerate((nwin + 3, nwin + 4)):
+        ev = s.window(k)
+        f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+        m = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+        tk = None
+        while tk is None:
+            tk = L.ebof_submit(ctx, sids[c], p, dev(ev["x"]), dev(ev["y"]), dev(ev["t"]), ev["t0"], f, m)
+        outs.append((tk, f, ev))
+    L.ebof_drain(ctx)
+    assert L.ebof_poll(ctx, outs[0][0]) == L.EBOF_NO_FLOW
+    assert L.ebof_poll(ctx, outs[1][0]) == L.EBOF_OK
+    r0, r1 = ref_window(p, outs[0][2]), ref_window(p, outs[1][2])
+    fl = outs[1][1].cpu().numpy().reshape(2, H, W).astype(np.float64)
+    assert_flow_matches(fl, OracleFlow(p, r0, r1, mask=True), "after a gap: cold")
     for sid in sids:
         L.ebof_stream_close(ctx, sid)

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2112_10591_amd import synth
-from flowcheck import assert_flow_matches, epe, oracle_flow, ref_window
+from flowcheck import OracleFlow, assert_flow_matches, epe, oracle_flow, ref_window
 
 pytestmark = pytest.mark.gpu
 
@@ -204,7 +204,7 @@ def test_flow_c1_parity_and_known_translation(ctx):
     (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(0), s.window(1)])
     _say("flow C1 pair (346x260, L3)")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-    assert_flow_matches(f, oracle_flow(p, r0, r1), "C1")
+    assert_flow_matches(f, OracleFlow(p, r0, r1), "C1")
     m = g0["edge"][16:-16, 16:-16].astype(bool)
     assert abs(np.median(f[0][16:-16, 16:-16][m]) - 2.5) <= 0.05
     assert abs(np.median(f[1][16:-16, 16:-16][m]) + 1.5) <= 0.05
@@ -231,7 +231,7 @@ def test_flow_integer_shift(ctx, d):
     inner = (slice(12, H - 12), slice(12, W - 12))
     e = np.hypot(f[0][inner] - d[0], f[1][inner] - d[1])
     assert np.median(e) < 1e-4 and np.mean(e < 0.05) > 0.98
-    assert_flow_matches(f, oracle_flow(p, r0, r1), f"shift {d}")
+    assert_flow_matches(f, OracleFlow(p, r0, r1), f"shift {d}")
 
 
 def test_flow_smooth_texture_damped_bias(ctx):
@@ -266,7 +266,7 @@ def test_flow_c2_parity(ctx):
     (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(4), s.window(5)])
     _say("flow C2 pair (1280x720, L4)")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-    assert_flow_matches(f, oracle_flow(p, r0, r1), "C2")
+    assert_flow_matches(f, OracleFlow(p, r0, r1), "C2")
 
 
 def test_flow_c5_parity(ctx):
@@ -277,7 +277,7 @@ def test_flow_c5_parity(ctx):
     (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [s.window(0), s.window(1)])
     _say("flow C5 pair (1280x720, L5, 2M events)")
     f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-    assert_flow_matches(f, oracle_flow(p, r0, r1), "C5")
+    assert_flow_matches(f, OracleFlow(p, r0, r1), "C5")
 
 
 def test_flow_mask_vs_oracle(ctx):
@@ -289,7 +289,7 @@ def test_flow_mask_vs_oracle(ctx):
     _say("flow masked")
     fm = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], mask=g0["_edge_dev"])
     m = r0["Edf"].astype(bool)
-    ref = np.where(m[None], oracle_flow(p, r0, r1), 0.0)
+    ref = OracleFlow(p, r0, r1, mask=True)
     assert np.all(fm[:, ~m] == 0.0)
     assert_flow_matches(fm, ref, "masked C1")
     assert_flow_matches(fm, ref, "masked C1, edge pixels", where=m)
@@ -304,4 +304,64 @@ def test_flow_odd_sizes_and_strides(ctx):
         ev1 = random_events(W, H, max(4, W * H // 6), 22)
         (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, [ev0, ev1])
         f = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
-        assert_flow_matches(f, oracle_flow(p, r0, r1), f"{W}x{H} L{lv} s{st}")
+        assert_flow_matches(f, OracleFlow(p, r0, r1), f"{W}x{H} L{lv} s{st}")
+
+
+# --------------------------------------------------------------------------
+# warm start of the coarsest level from the previous pair's flow
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_flow_warm_start_chain_vs_oracle(ctx, cfg):
+    """Three consecutive windows: the pair (0, 1) cold, then (1, 2) started
+    from the first pair's flow before masking (ebof_flow_warm), against the
+    oracle's own chain (its cold flow fed to its warm start).  The dense copy
+    equals the unmasked flow, the masked output is 0 off the reference edge
+    pixels, and the warm start does change the flow."""
+    s = synth.c1_stream(0) if cfg == "c1" else synth.c2_stream(0)
+    p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+    W, H = s.W, s.H
+    (g0, r0), (g1, r1), (g2, r2) = windows_gpu_and_oracle(ctx, p, [s.window(k) for k in (0, 1, 2)])
+    _say(f"warm start chain {cfg} ({W}x{H}, L{p.levels})")
+    f01 = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    d01 = torch.full((2 * W * H,), float("nan"), dtype=torch.float32, device="cuda")
+    f12 = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    d12 = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    cold = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    L.ebof_flow_warm(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], f01, flow_dense_out=d01, mask=g0["_edge_dev"])
+    L.ebof_flow_warm(ctx, p, g1["_pyr_dev"], g2["_pyr_dev"], f12, flow_init=d01, flow_dense_out=d12,
+                     mask=g1["_edge_dev"])
+    L.ebof_flow(ctx, p, g1["_pyr_dev"], g2["_pyr_dev"], cold, mask=g1["_edge_dev"])
+    torch.cuda.synchronize()
+    sh = (2, H, W)
+    f01, d01, f12, d12, cold = (a.cpu().numpy().reshape(sh).astype(np.float64) for a in (f01, d01, f12, d12, cold))
+    o01 = OracleFlow(p, r0, r1)
+    o12 = OracleFlow(p, r1, r2, prev_flow=o01.raw)
+    assert_flow_matches(d01, o01, f"{cfg} pair (0,1) cold, dense")
+    assert_flow_matches(d12, o12, f"{cfg} pair (1,2) warm, dense")
+    m1 = r1["Edf"].astype(bool)
+    assert np.array_equal(f12, np.where(m1[None], d12, 0.0))
+    assert not np.array_equal(f12, cold), "the warm start changed nothing"
+    o12c = oracle_flow(p, r1, r2)
+    _say(f"  warm vs cold oracle flows differ at {np.mean(epe(o12.raw, o12c) > 1e-3):.1%} of pixels")
+
+
+def test_flow_warm_start_constant_velocity(ctx):
+    """A constant previous flow v seeds every coarsest-level patch with
+    v / 2^(L-1) exactly: on a zero-motion pair (I1 = I0) whose reference is
+    flat (an empty window: every gradient 0, so no step moves a patch), the
+    coarsest level keeps that start and every finer level doubles it back,
+    so the flow is v everywhere, exactly, on both sides."""
+    p = L.ebof_params_default(200, 120, levels=3)
+    W, H = 200, 120
+    empty = dict(x=np.zeros(0, np.uint16), y=np.zeros(0, np.uint16), t=np.zeros(0, np.int64), t0=0)
+    (g, r), = windows_gpu_and_oracle(ctx, p, [empty])
+    v = (2.5, -1.5)
+    prev = np.stack([np.full((H, W), v[0]), np.full((H, W), v[1])])
+    f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    _say("warm start, constant velocity on a flat reference")
+    L.ebof_flow_warm(ctx, p, g["_pyr_dev"], g["_pyr_dev"], f, flow_init=dev(prev.astype(np.float32)))
+    torch.cuda.synchronize()
+    f = f.cpu().numpy().reshape(2, H, W)
+    assert np.all(f[0] == v[0]) and np.all(f[1] == v[1])
+    o = oracle_flow(p, r, r, prev_flow=prev)
+    assert np.all(o[0] == v[0]) and np.all(o[1] == v[1])
