@@ -204,6 +204,27 @@ int ebof_flow_warm(ebof_ctx *ctx, const ebof_params *p, const float *pyr_prev,
                    const float *flow_init, float *flow_out,
                    float *flow_dense_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and results as ebof_flow, with no context.  It allocates
+ * nothing: the patch displacements live in a fixed device array of
+ * EBOF_NOALLOC_MAX_PATCHES (float2, 8 MiB) that each GPU the library runs on
+ * holds until the process ends; its address on a device is looked up on the
+ * first call made with that device current.  The call runs on the current
+ * HIP device; hip_stream must belong to it.  Every call on one GPU shares
+ * that GPU's array, which keeps the last call's contents (nothing in it needs
+ * clearing: each level writes its patches before the next reads them), so
+ * calls that overlap on one GPU (other streams, other threads) race; order
+ * them.  The pyramid's patch count summed over levels must not exceed
+ * EBOF_NOALLOC_MAX_PATCHES (3840x2160 at stride 4 with 4 levels fits):
+ * EBOF_E_NOMEM otherwise.  EBOF_E_INVAL for bad parameters or NULL buffers,
+ * EBOF_E_DEVICE when a HIP call fails.  Errors are read with
+ * ebof_last_error(NULL). */
+#define EBOF_NOALLOC_MAX_PATCHES (1 << 20)
+int ebof_flow_noalloc(const ebof_params *p, const float *pyr_prev,
+                      const float *pyr_curr, const uint8_t *mask,
+                      float *flow_out, void *hip_stream);
+
 /* ---- batched form ---------------------------------------------------------
  * One descriptor per window; every stage of every window of the batch runs
  * in one kernel launch per stage (one per pyramid level for the pyramid and

@@ -111,6 +111,7 @@ def load():
         "ebof_edt_surface": ([P, pp, P, P, P, P], ctypes.c_int),
         "ebof_window_surface": ([P, pp, P, P, P, i64, i64, P, P, P, P, P], ctypes.c_int),
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
+        "ebof_flow_noalloc": ([pp, P, P, P, P, P], ctypes.c_int),
         "ebof_flow_warm": ([P, pp, P, P, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
         "ebof_set_tuning": ([P, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
@@ -140,7 +141,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_run_batch", "ebof_set_tuning",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
@@ -314,6 +315,18 @@ def ebof_flow_warm(ctx, p, pyr_prev, pyr_curr, flow_out, flow_init=None, flow_de
     fd = _dev(flow_dense_out, torch.float32, 2 * N, "flow_dense_out", optional=True)
     return _check(ctx.handle, ctx.lib.ebof_flow_warm(ctx.handle, ctypes.byref(p), a, b, m, fi, f, fd,
                                                      _stream(stream)))
+
+
+def ebof_flow_noalloc(p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
+    """ebof_flow without a context, on the current device (scratch in a
+    fixed device array: nothing is allocated)."""
+    P = ebof_pyramid_floats(p)
+    N = p.width * p.height
+    a = _dev(pyr_prev, torch.float32, P, "pyr_prev")
+    b = _dev(pyr_curr, torch.float32, P, "pyr_curr")
+    m = _dev(mask, torch.uint8, N, "mask", optional=True)
+    f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
+    return _check(None, load().ebof_flow_noalloc(ctypes.byref(p), a, b, m, f, _stream(stream)))
 
 
 def ebof_set_tuning(ctx, mode=EBOF_TUNE_AUTO, cache_path=None):

@@ -1139,6 +1139,37 @@ int ebof_flow_warm(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, c
     return launch_status(ctx);
 }
 
+int ebof_flow_noalloc(const ebof_params* p, const float* pyr_prev, const float* pyr_curr, const uint8_t* mask,
+                      float* flow_out, void* hip_stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!pyr_prev || !pyr_curr || !flow_out) {
+        set_error("ebof_flow_noalloc: NULL pyramid or flow_out");
+        return EBOF_E_INVAL;
+    }
+    const Geom g = make_geom(*p);
+    if (g.patches > kNoAllocPatches) {
+        set_error("ebof_flow_noalloc: %lld patches exceed the fixed scratch of %lld", (long long)g.patches,
+                  (long long)kNoAllocPatches);
+        return EBOF_E_NOMEM;
+    }
+    Scratch scr;
+    if ((rc = noalloc_scratch(&scr.puv))) return rc;
+    scr.W = g.W;
+    scr.H = g.H;
+    scr.L = g.L;
+    scr.stride = g.stride;
+    Lut lut{p->alpha, 0, nullptr};
+    WinDesc d;
+    fill_desc(*p, g, lut, scr, &d);
+    d.pyr = const_cast<float*>(pyr_curr);  // read only by these kernels
+    d.pyr_prev = pyr_prev;
+    d.mask = mask;
+    d.flow = flow_out;
+    flow_launches(nullptr, p, d, (hipStream_t)hip_stream);
+    return check_hip(nullptr, hipGetLastError(), "kernel launch");
+}
+
 int ebof_set_tuning(ebof_ctx* ctx, int mode, const char* cache_path) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;

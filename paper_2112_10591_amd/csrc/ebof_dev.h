@@ -33,6 +33,12 @@ constexpr int kRowReach = 64;         // EDT row pass: columns staged each side 
 constexpr int kRowUnroll = 4;         // EDT row pass: radii per search step (divides kRowReach)
 constexpr int kLutLds = 1024;         // EDT row pass: surface tables up to this size sit in LDS
 
+// Allocation-free flow call: its patch displacements live in a fixed device
+// array of this many float2 (8 MiB; 3840x2160 at stride 4 with 4 levels needs
+// about 690k).
+constexpr int64_t kNoAllocPatches = EBOF_NOALLOC_MAX_PATCHES;
+constexpr int kNoAllocMaxDevices = 64;
+
 struct LevelGeom {
     int32_t w, h;      // level size
     int32_t pnx, pny;  // patch grid
@@ -165,5 +171,11 @@ void launch_edt_rows(const Launch& L, int rows_nr);
 void launch_pyr_chain(const Launch& L, int from);
 void launch_dis_level(const Launch& L, int level, int lanes);
 void launch_densify(const Launch& L, int tile_w);
+
+// Device address, on the current HIP device, of the fixed patch-displacement
+// array of the allocation-free flow call (kNoAllocPatches float2); looked up
+// once per device.  EBOF_OK, or EBOF_E_DEVICE with the error set.
+int noalloc_scratch(float2** out);
+void set_error(const char* fmt, ...);
 
 }  // namespace ebof

@@ -8,8 +8,15 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ebof_dev.h"
+
+// Patch displacements of the allocation-free flow call (ebof_flow_noalloc):
+// a fixed array that each GPU the library runs on holds until the process
+// ends.  In host code this name is a host-side stand-in, not a device
+// address: host code passes the address noalloc_scratch() returns instead.
+static __device__ __align__(256) float2 scratch[ebof::kNoAllocPatches];
 
 namespace ebof {
 
@@ -1145,6 +1152,36 @@ void launch_densify(const Launch& L, int tile_w) {
         case 256: EBOF_LAUNCH_T(k_densify, 256, L); break;
         default: EBOF_LAUNCH_T(k_densify, 64, L); break;
     }
+}
+
+// --------------------------------------------------------------------------
+// the fixed scratch array's device address, per device
+// --------------------------------------------------------------------------
+int noalloc_scratch(float2** out) {
+    static std::mutex mu;
+    static float2* addr[kNoAllocMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(e));
+        return EBOF_E_DEVICE;
+    }
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("device %d out of range for the fixed scratch", dev);
+        return EBOF_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+            return EBOF_E_DEVICE;
+        }
+        addr[dev] = (float2*)p;
+    }
+    *out = addr[dev];
+    return EBOF_OK;
 }
 
 // --------------------------------------------------------------------------

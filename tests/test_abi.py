@@ -85,3 +85,18 @@ def test_stream_signals_reject_null_context():
     assert lib.ebof_window_surface(None, None, None, None, None, 0, 0, None, None, None, None, None) == L.EBOF_E_INVAL
 
 
+
+def test_flow_noalloc_host_checks():
+    """The allocation-free flow call checks its arguments on the host, before
+    any device work: NULL buffers, bad parameters, and a pyramid with more
+    patches than the fixed scratch holds."""
+    lib = L.load()
+    p = L.ebof_params_default(346, 260)
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    assert lib.ebof_flow_noalloc(ctypes.byref(p), None, dummy, None, dummy, None) == L.EBOF_E_INVAL
+    assert lib.ebof_flow_noalloc(ctypes.byref(p), dummy, dummy, None, None, None) == L.EBOF_E_INVAL
+    bad = L.ebof_params_default(346, 260, stride=0)
+    assert lib.ebof_flow_noalloc(ctypes.byref(bad), dummy, dummy, None, dummy, None) == L.EBOF_E_INVAL
+    big = L.ebof_params_default(8192, 8192, stride=1, levels=1)
+    assert lib.ebof_flow_noalloc(ctypes.byref(big), dummy, dummy, None, dummy, None) == L.EBOF_E_NOMEM
+    assert "fixed scratch" in lib.ebof_last_error(None).decode()
