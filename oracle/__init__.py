@@ -71,6 +71,11 @@ def _load():
     lib.oref_edt_separable.argtypes = [i32, i32, P, P]
     lib.oref_surface.argtypes = [i64, P, f64, P]
     lib.oref_pyr_down.argtypes = [i32, i32, P, P]
+    lib.oref_surface_kind.argtypes = [i64, P, f64, i32, P]
+    lib.oref_flow_errors.argtypes = [i64, P, P, P, P, P]
+    lib.oref_flow_errors.restype = i64
+    lib.oref_fwl.argtypes = [i32, i32, P, P, P, P, i64, i64, i64, P, P, P]
+    lib.oref_fwl.restype = f64
     lib.oref_dis_flow.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P]
     lib.oref_dis_flow.restype = ctypes.c_int
     lib.oref_dis_flow_warm.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P, P]
@@ -162,6 +167,44 @@ def surface(D2, alpha):
     S = np.empty(D2.shape, np.float32)
     _load().oref_surface(D2.size, _ptr(D2), float(alpha), _ptr(S))
     return S
+
+
+SURFACE_EXP, SURFACE_LINEAR, SURFACE_BOUNDED, SURFACE_LOG = 0, 1, 2, 3
+
+
+def surface_kind(D2, alpha, kind):
+    """The ablation surfaces of Sec. IV-B on squared distances (float32):
+    0 eq. (1), 1 DS_L (d), 2 DS_LB (min(d, alpha ln 255)), 3 DS_Log (ln(d+1))."""
+    D2 = np.ascontiguousarray(D2, np.int32)
+    S = np.empty(D2.shape, np.float32)
+    _load().oref_surface_kind(D2.size, _ptr(D2), float(alpha), int(kind), _ptr(S))
+    return S
+
+
+def flow_errors(u, v, mask=None):
+    """(AEE, outlier fraction, pixels counted) of flow u against ground
+    truth v ([2, H, W] each) over mask (all pixels when None), Sec. IV."""
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    m = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+    aee, out = ctypes.c_double(), ctypes.c_double()
+    n = _load().oref_flow_errors(u[0].size, _ptr(u), _ptr(v), _ptr(m) if m is not None else None,
+                                 ctypes.byref(aee), ctypes.byref(out))
+    return aee.value, out.value, int(n)
+
+
+def fwl(W, H, x, y, t, t0, dt, flow, pol=None):
+    """Flow warp loss of one window's events under flow ([2, H, W], pixels
+    per dt), Sec. IV: (fwl, variance compensated, variance uncompensated)."""
+    x = np.ascontiguousarray(x, np.uint16)
+    y = np.ascontiguousarray(y, np.uint16)
+    t = np.ascontiguousarray(t, np.int64)
+    f = np.ascontiguousarray(flow, np.float64)
+    pp = None if pol is None else np.ascontiguousarray(pol, np.int8)
+    vc, vu = ctypes.c_double(), ctypes.c_double()
+    r = _load().oref_fwl(int(W), int(H), _ptr(x), _ptr(y), _ptr(t), _ptr(pp) if pp is not None else None,
+                         x.size, int(t0), int(dt), _ptr(f), ctypes.byref(vc), ctypes.byref(vu))
+    return r, vc.value, vu.value
 
 
 def alpha_from_dsat(d_sat, eps=1.0 / 255.0):

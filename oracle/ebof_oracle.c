@@ -247,6 +247,99 @@ void oref_surface(int64_t n, const int32_t *D2, double alpha, float *S)
     }
 }
 
+/* Ablation surfaces (Sec. IV-B): the proposed inverse exponential, the plain
+ * distance, the distance bounded at d_sat (6 px in the paper, which equals
+ * alpha ln 255 by eq. 3) and its logarithm. */
+void oref_surface_kind(int64_t n, const int32_t *D2, double alpha, int32_t kind,
+                       float *S)
+{
+    double d_sat = alpha * log(255.0);
+    for (int64_t i = 0; i < n; i++) {
+        double d = sqrt((double)D2[i]);
+        double v;
+        if (kind == 1)
+            v = d;
+        else if (kind == 2)
+            v = d < d_sat ? d : d_sat;
+        else if (kind == 3)
+            v = log(d + 1.0);
+        else
+            v = 1.0 - exp(-d / alpha);
+        S[i] = (float)v;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Evaluation metrics (Sec. IV): average endpoint error, outliers, and the   */
+/* flow warp loss.                                                           */
+/* ------------------------------------------------------------------------ */
+int64_t oref_flow_errors(int64_t n, const double *u, const double *v,
+                         const uint8_t *mask, double *aee, double *outliers)
+{
+    int64_t cnt = 0, out = 0;
+    double sum = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        if (mask && !mask[i])
+            continue;
+        double ex = v[i] - u[i], ey = v[n + i] - u[n + i];
+        double e = sqrt(ex * ex + ey * ey);
+        double m = sqrt(v[i] * v[i] + v[n + i] * v[n + i]);
+        sum += e;
+        if (e > 3.0 && e > 0.05 * m)
+            out++;
+        cnt++;
+    }
+    *aee = cnt ? sum / (double)cnt : 0.0;
+    *outliers = cnt ? (double)out / (double)cnt : 0.0;
+    return cnt;
+}
+
+static double image_variance(const double *I, int64_t N)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < N; i++)
+        s += I[i];
+    double m = s / (double)N, q = 0.0;
+    for (int64_t i = 0; i < N; i++)
+        q += (I[i] - m) * (I[i] - m);
+    return q / (double)N;
+}
+
+double oref_fwl(int32_t W, int32_t H, const uint16_t *x, const uint16_t *y,
+                const int64_t *t, const int8_t *pol, int64_t n, int64_t t0,
+                int64_t dt, const double *flow, double *var_comp,
+                double *var_uncomp)
+{
+    size_t N = (size_t)W * H;
+    double *Ic = (double *)calloc(N, sizeof(double));
+    double *Iu = (double *)calloc(N, sizeof(double));
+    for (int64_t e = 0; e < n; e++) {
+        if (t[e] < t0 || t[e] >= t0 + dt || x[e] >= W || y[e] >= H)
+            continue;
+        double w = pol ? (pol[e] < 0 ? -1.0 : 1.0) : 1.0;
+        size_t p = (size_t)y[e] * W + x[e];
+        Iu[p] += w;
+        double tau = (double)(t[e] - t0) / (double)dt;
+        double sx = x[e] - flow[p] * tau, sy = y[e] - flow[N + p] * tau;
+        double fx = floor(sx), fy = floor(sy);
+        double ax = sx - fx, ay = sy - fy;
+        for (int32_t j = 0; j < 2; j++)
+            for (int32_t i = 0; i < 2; i++) {
+                double X = fx + i, Y = fy + j;
+                if (X < 0 || X >= W || Y < 0 || Y >= H)
+                    continue;
+                double b = (i ? ax : 1.0 - ax) * (j ? ay : 1.0 - ay);
+                Ic[(size_t)Y * W + (size_t)X] += w * b;
+            }
+    }
+    double vc = image_variance(Ic, (int64_t)N), vu = image_variance(Iu, (int64_t)N);
+    free(Ic);
+    free(Iu);
+    *var_comp = vc;
+    *var_uncomp = vu;
+    return vu > 0.0 ? vc / vu : 0.0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gaussian pyramid of a surface: binomial 5-tap blur then keep every second */
 /* pixel, reflect-101 border.                                               */

@@ -63,6 +63,38 @@ void oref_edt_separable(int32_t W, int32_t H, const uint8_t *E, int32_t *D2);
 /* Equation (1): S = 1 - exp(-sqrt(D2) / alpha), rounded once to float. */
 void oref_surface(int64_t n, const int32_t *D2, double alpha, float *S);
 
+/* The distance-surface alternatives of the ablation study (Sec. IV-B), from
+ * the squared distance D2 with d = sqrt(D2), each rounded once to float:
+ *   kind 0, eq. (1):       1 - exp(-d / alpha)
+ *   kind 1, DS_L:          d
+ *   kind 2, DS_LB:         min(d, d_sat) with d_sat = alpha ln 255 (eq. 3)
+ *   kind 3, DS_Log:        ln(d + 1)
+ * The no-edge sentinel D2 = INT32_MAX goes through the same formula. */
+void oref_surface_kind(int64_t n, const int32_t *D2, double alpha, int32_t kind,
+                       float *S);
+
+/* Sec. IV, evaluation metrics, of flow u against ground truth v (both two
+ * planes of n values) over the pixels where mask != 0 (every pixel when mask
+ * is NULL): *aee = mean |v - u| (Euclidean), *outliers = fraction of those
+ * pixels with |v - u| > 3 px and > 5 % of |v|.  Returns the number of pixels
+ * counted (0: both outputs 0). */
+int64_t oref_flow_errors(int64_t n, const double *u, const double *v,
+                         const uint8_t *mask, double *aee, double *outliers);
+
+/* Sec. IV, flow warp loss.  The events of one window (t0 <= t < t0 + dt, on
+ * the W x H sensor) are accumulated into two images: at their own pixel
+ * (uncompensated), and moved back to the window start by the flow at their
+ * pixel scaled by their time in the window, x' = x - u(x, y) (t - t0) / dt
+ * (likewise y), voting bilinearly into the four pixels around x' (votes off
+ * the sensor are lost).  Each event votes its polarity (+1 / -1) when pol is
+ * given, else 1.  flow: two planes of W*H doubles, pixels per dt.
+ * var_comp / var_uncomp get the variances of the two images over all W*H
+ * pixels; returns var_comp / var_uncomp (0 when var_uncomp is 0). */
+double oref_fwl(int32_t W, int32_t H, const uint16_t *x, const uint16_t *y,
+                const int64_t *t, const int8_t *pol, int64_t n, int64_t t0,
+                int64_t dt, const double *flow, double *var_comp,
+                double *var_uncomp);
+
 /* One pyramid reduction: out(X,Y) = sum_{i,j=-2..2} k_i k_j in(2X+i, 2Y+j),
  * k = [1 4 6 4 1]/16, reflect-101 border.  out is ((W+1)/2) x ((H+1)/2). */
 void oref_pyr_down(int32_t W, int32_t H, const float *in, float *out);
