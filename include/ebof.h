@@ -86,20 +86,33 @@ typedef struct {
     int32_t iters;         /* inverse-search iterations per patch, 0..1024   */
     float lambda_reg;      /* Tikhonov term added to the patch Hessian, > 0  */
     uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START */
+    int32_t surface;       /* EBOF_SURFACE_*: the distance surface (Sec. IV-B) */
 } ebof_params;
+
+/* Distance surfaces of ebof_params.surface, from the squared distance D2 with
+ * d = sqrt(D2), each rounded once to float (the ablations of Sec. IV-B):
+ * eq. (1), the proposed one, 1 - exp(-d / alpha); DS_L, d; DS_LB, min(d,
+ * d_sat) with d_sat = alpha ln 255 (eq. 3: 6 px in the paper); DS_Log,
+ * ln(d + 1).  The no-edge value D2 = INT32_MAX goes through the same
+ * formula. */
+#define EBOF_SURFACE_EXP 0
+#define EBOF_SURFACE_LINEAR 1
+#define EBOF_SURFACE_BOUNDED 2
+#define EBOF_SURFACE_LOG 3
 
 /* Defaults of Sec. IV-A for a sensor of the given size: N_d = 1, N_f = 4 up to
  * 100k pixels (the 346x260 setting), N_d = 2, N_f = 3 above (1280x720);
  * alpha = 1.08 (d_sat = 6 px, eq. 3); dt = 10 ms; levels = 3 up to 100k
  * pixels, else 4 (each level at least 8 px); patch 8, stride 4, 16 iterations,
- * lambda_reg 0.3, no flags.  Returns EBOF_E_INVAL for a size out of range. */
+ * lambda_reg 0.3, no flags, surface EBOF_SURFACE_EXP.  Returns EBOF_E_INVAL for a size out of range. */
 int ebof_params_default(int32_t width, int32_t height, ebof_params *out);
 
 /* EBOF_OK when the parameters are usable, else EBOF_E_INVAL.  Checks: sizes
  * in [EBOF_MIN_DIM, EBOF_MAX_DIM], every pyramid level at least the patch
  * size, n_d and n_f in [0, 5], alpha and lambda_reg finite and > 0, alpha
  * small enough for a squared-distance lookup table of at most 2^22 entries,
- * patch == 8, stride in [1, 8], iters in [0, 1024], dt_us > 0. */
+ * patch == 8, stride in [1, 8], iters in [0, 1024], dt_us > 0, surface one
+ * of EBOF_SURFACE_*. */
 int ebof_validate(const ebof_params *p);
 
 /* Length P (in floats) of the pyramid of p, or -1 if p is invalid. */

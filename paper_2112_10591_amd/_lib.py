@@ -27,6 +27,7 @@ EBOF_E_STATE = -6
 EBOF_MASK_FLOW = 1
 EBOF_CHAIN_ALWAYS = 2
 EBOF_WARM_START = 4
+EBOF_SURFACE_EXP, EBOF_SURFACE_LINEAR, EBOF_SURFACE_BOUNDED, EBOF_SURFACE_LOG = 0, 1, 2, 3
 EBOF_MAX_BATCH = 1024
 EBOF_TUNE_OFF = 0
 EBOF_TUNE_AUTO = 1
@@ -60,6 +61,7 @@ class ebof_params(ctypes.Structure):
         ("iters", ctypes.c_int32),
         ("lambda_reg", ctypes.c_float),
         ("flags", ctypes.c_uint32),
+        ("surface", ctypes.c_int32),
     ]
 
     def as_dict(self):

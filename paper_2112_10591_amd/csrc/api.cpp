@@ -28,13 +28,25 @@ int check_hip(ebof_ctx* ctx, hipError_t e, const char* what) {
 }
 
 // ---------------------------------------------------------------- params
-static int64_t lut_entries(float alpha, std::vector<float>* out) {
-    // squared distances whose surface value is below 1.0f in float
+// The value a saturating surface takes from some squared distance on: 1 for
+// eq. (1), d_sat = alpha ln 255 for the bounded distance; the others grow
+// without bound and use no table.
+static bool surface_saturates(int32_t kind) { return kind == EBOF_SURFACE_EXP || kind == EBOF_SURFACE_BOUNDED; }
+static float surface_sat(float alpha, int32_t kind) {
+    return kind == EBOF_SURFACE_BOUNDED ? (float)((double)alpha * std::log(255.0)) : 1.0f;
+}
+
+static int64_t lut_entries(float alpha, int32_t kind, std::vector<float>* out) {
+    // squared distances whose surface value is below the saturation value
+    if (!surface_saturates(kind)) return 0;
     const double a = (double)alpha;
+    const float sat = surface_sat(alpha, kind);
     const int64_t cap = int64_t(1) << 22;
     for (int64_t i = 0; i < cap; ++i) {
-        const float s = (float)(1.0 - std::exp(-std::sqrt((double)i) / a));
-        if (s == 1.0f) return i;
+        const double d = std::sqrt((double)i);
+        const float s = kind == EBOF_SURFACE_BOUNDED ? (float)std::min(d, (double)a * std::log(255.0))
+                                                     : (float)(1.0 - std::exp(-d / a));
+        if (s == sat) return i;
         if (out) out->push_back(s);
     }
     return -1;
@@ -95,6 +107,10 @@ static int validate(const ebof_params* p) {
         set_error("dt_us %lld must be > 0", (long long)p->dt_us);
         return EBOF_E_INVAL;
     }
+    if (p->surface < EBOF_SURFACE_EXP || p->surface > EBOF_SURFACE_LOG) {
+        set_error("surface %d is not one of EBOF_SURFACE_*", p->surface);
+        return EBOF_E_INVAL;
+    }
     if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START)) {
         set_error("unknown flags 0x%x", p->flags);
         return EBOF_E_INVAL;
@@ -141,20 +157,22 @@ static size_t scratch_bytes(const Geom& g) {
 }
 
 // ---------------------------------------------------------------- ctx helpers
-int lut_for(ebof_ctx* ctx, float alpha, Lut* out) {
+int lut_for(ebof_ctx* ctx, float alpha, int32_t kind, Lut* out) {
     for (const Lut& l : ctx->luts)
-        if (std::memcmp(&l.alpha, &alpha, sizeof(float)) == 0) {
+        if (std::memcmp(&l.alpha, &alpha, sizeof(float)) == 0 && l.kind == kind) {
             *out = l;
             return EBOF_OK;
         }
     std::vector<float> v;
-    const int64_t n = lut_entries(alpha, &v);
+    const int64_t n = lut_entries(alpha, kind, &v);
     if (n < 0) {
         set_error("alpha %g needs a lookup table over 2^22 entries", (double)alpha);
         return EBOF_E_INVAL;
     }
     Lut l;
     l.alpha = alpha;
+    l.kind = kind;
+    l.sat = surface_sat(alpha, kind);
     l.n = (int32_t)n;
     l.dev = (float*)ctx->arena.alloc(std::max<size_t>(4, v.size() * 4));
     if (!l.dev) {
@@ -217,6 +235,8 @@ void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratc
     d->lut_r = 0;
     while ((int64_t)d->lut_r * d->lut_r < lut.n) ++d->lut_r;
     d->lut = lut.dev;
+    d->surf_kind = p.surface;
+    d->lut_sat = lut.sat;
     d->e_raw = s.e_raw;
     d->colmask = s.colmask;
     d->g = s.g;
@@ -639,7 +659,7 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
         const ebof_params& p = *w[i].params;
         const Geom g = make_geom(p);
         Lut lut;
-        if ((rc = lut_for(ctx, p.alpha, &lut))) return rc;
+        if ((rc = lut_for(ctx, p.alpha, p.surface, &lut))) return rc;
         Scratch& s = *scr[i];
         WinDesc& d = descs[i];
         fill_desc(p, g, lut, s, &d);
@@ -785,6 +805,7 @@ int ebof_params_default(int32_t width, int32_t height, ebof_params* out) {
     p.iters = 16;
     p.lambda_reg = 0.3f;
     p.flags = 0;
+    p.surface = EBOF_SURFACE_EXP;
     // fewer levels for small sensors so that every level holds a patch
     while (p.levels > 1) {
         int32_t w = width, h = height;
@@ -978,14 +999,14 @@ static int bin_impl(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
     }
     const Geom g = make_geom(*p);
     Scratch scr;
-    Lut lut{p->alpha, 0, nullptr};
+    Lut lut{p->alpha, p->surface, 0, 1.0f, nullptr};
     uint32_t stamp;
     bool zero;
     {  // the lock covers the context's maps; launches run outside it
         std::lock_guard<std::mutex> lk(ctx->mu);
         Scratch* s = stage_scratch(ctx, g, st, &rc);
         if (!s) return rc;
-        if (pack && (rc = lut_for(ctx, p->alpha, &lut))) return rc;
+        if (pack && (rc = lut_for(ctx, p->alpha, p->surface, &lut))) return rc;
         stamp = s->next_stamp();
         zero = s->needs_zero;
         s->needs_zero = false;
@@ -1052,7 +1073,7 @@ int ebof_edt_surface(ebof_ctx* ctx, const ebof_params* p, const uint8_t* edge, i
         std::lock_guard<std::mutex> lk(ctx->mu);
         Scratch* s = stage_scratch(ctx, g, st, &rc);
         if (!s) return rc;
-        if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+        if ((rc = lut_for(ctx, p->alpha, p->surface, &lut))) return rc;
         scr = *s;
     }
     WinDesc d;
@@ -1126,7 +1147,7 @@ int ebof_flow_warm(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, c
         if (!s) return rc;
         scr = *s;
     }
-    Lut lut{p->alpha, 0, nullptr};
+    Lut lut{p->alpha, p->surface, 0, 1.0f, nullptr};
     WinDesc d;
     fill_desc(*p, g, lut, scr, &d);
     d.pyr = const_cast<float*>(pyr_curr);  // read only by these kernels
@@ -1159,7 +1180,7 @@ int ebof_flow_noalloc(const ebof_params* p, const float* pyr_prev, const float* 
     scr.H = g.H;
     scr.L = g.L;
     scr.stride = g.stride;
-    Lut lut{p->alpha, 0, nullptr};
+    Lut lut{p->alpha, p->surface, 0, 1.0f, nullptr};
     WinDesc d;
     fill_desc(*p, g, lut, scr, &d);
     d.pyr = const_cast<float*>(pyr_curr);  // read only by these kernels

@@ -53,7 +53,9 @@ struct Scratch {
 
 struct Lut {
     float alpha;
-    int32_t n;
+    int32_t kind;  // EBOF_SURFACE_*
+    int32_t n;     // entries (0: the surface does not saturate, no table)
+    float sat;     // value from squared distance n on
     float* dev;
 };
 
@@ -125,7 +127,7 @@ struct ebof_ctx {
 
 namespace ebof {
 // helpers shared by api.cpp and serve.cpp
-int lut_for(ebof_ctx* ctx, float alpha, Lut* out);
+int lut_for(ebof_ctx* ctx, float alpha, int32_t kind, Lut* out);
 int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t stream);
 void scratch_free(ebof_ctx* ctx, Scratch* s);
 void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratch& s, WinDesc* d);

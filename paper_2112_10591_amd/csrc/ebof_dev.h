@@ -52,9 +52,10 @@ struct WinDesc {
     int32_t stride, iters;
     uint32_t flags;
     float lambda;
-    int32_t lut_n;      // squared distances below lut_n read lut[], others 1.0f
+    int32_t lut_n;      // squared distances below lut_n read lut[], others lut_sat
     int32_t lut_r;      // smallest r with r*r >= lut_n
-    int32_t pad2;
+    int32_t surf_kind;  // EBOF_SURFACE_*: LINEAR and LOG are computed, not looked up
+    float lut_sat;
     const float* lut;
     // events of the window, SoA, and the half-open window [t0, t1)
     const uint16_t* ex;

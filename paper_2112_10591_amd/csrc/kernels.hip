@@ -403,7 +403,11 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         const bool exp_d2 = d->d2 != nullptr;
         const int lut_n = d->lut_n;
         const bool lut_lds = lut_n <= kLutLds;
-        const uint32_t cap = exp_d2 ? 0xffffffffu : (uint32_t)lut_n;
+        const int kind = d->surf_kind;
+        const bool computed = kind == EBOF_SURFACE_LINEAR || kind == EBOF_SURFACE_LOG;
+        const float sat = d->lut_sat;
+        // (a surface that never saturates needs the exact distance everywhere)
+        const uint32_t cap = (exp_d2 || computed) ? 0xffffffffu : (uint32_t)lut_n;
         const int lo = max(0, x0 - R), hi = min(W, x0 + kRowSeg + R);
         const int ww = hi - lo;
         const uint16_t* __restrict__ g = d->g + (size_t)y0 * W;
@@ -482,7 +486,14 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
                     const size_t pix = (size_t)(y0 + k) * W + x;
                     const uint32_t b = best[k];
                     if (exp_d2) d->d2[pix] = b >= 0x7fffffffu ? 0x7fffffff : (int32_t)b;
-                    d->pyr[pix] = b < (uint32_t)lut_n ? (lut_lds ? sLut[b] : lut[b]) : 1.0f;
+                    if (computed) {
+                        // in double, rounded once, as the squared distance's
+                        // table would hold it
+                        const double dd = sqrt((double)b);
+                        d->pyr[pix] = (float)(kind == EBOF_SURFACE_LINEAR ? dd : log(dd + 1.0));
+                    } else {
+                        d->pyr[pix] = b < (uint32_t)lut_n ? (lut_lds ? sLut[b] : lut[b]) : sat;
+                    }
                 }
             }
         }
@@ -755,7 +766,7 @@ __device__ __forceinline__ double redd(double v) {
 // iterations read it there (a patch whose window leaves the region reads
 // global memory; both give the same clamped samples).
 template <bool B, int LP>
-__global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                       int level) {
     constexpr int CPL = kPatch / LP;                   // patch columns per lane
     constexpr int PR = kBlock / kPatchesPerItem / LP;  // patch rows per item
@@ -836,13 +847,12 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         __syncthreads();
         // The residual sum of an iteration, sum_j g_j (I1(x_j + u) - T_j), is
         // split as sum_j g_j I1(x_j + u) - c with c = sum_j g_j T_j fixed for
-        // the patch, and the bilinear sample of row j as h_j + ay (h_{j+1} -
-        // h_j) (h = the row interpolated along x), so that per lane
-        // sum_j g_j I1 = P + ay (Q - P), P = sum_j g_j h_j, Q = sum_j g_j h_{j+1}.
-        // Every sum over the patch is formed per patch column (rows in order),
-        // then the columns are added as a binary tree (a lane's two columns
-        // first, then the lanes by DPP), so both lane counts give the same
-        // bits and the launch shape never changes a result.
+        // the patch; the first part is formed from the corner sums of u's
+        // integer cell (below).  Every sum over the patch is formed per patch
+        // column (rows in order), then the columns are added as a binary
+        // tree (a lane's two columns first, then the lanes by DPP), so both
+        // lane counts give the same bits and the launch shape never changes
+        // a result.
         float fgx[CPL][kPatch], fgy[CPL][kPatch], tf[CPL][kPatch];
         double hxx = 0.0, hxy = 0.0, hyy = 0.0;
         {
@@ -874,9 +884,10 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         const double det = ha * hc - hxy * hxy;
         const double idet = 1.0 / det;
         const float fia = (float)(hc * idet), fib = (float)(-hxy * idet), fic = (float)(ha * idet);
-        // c by the same single-precision chain, in the same order, as P at
-        // u = 0: where I1 equals the template the residual is exactly 0, so
-        // a patch that does not move stays exactly in place
+        // c by the same single-precision chain, in the same order, as the
+        // corner sum SA: at an integer u where I1 equals the template the
+        // residual is exactly 0, so a patch that does not move stays exactly
+        // in place
         float fcx = 0.f, fcy = 0.f;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -932,83 +943,77 @@ __global__ __launch_bounds__(kBlock) void k_dis_level(const WinDesc one, const B
         lds_load_wait();
         __syncthreads();
 
-        // ---- inverse-compositional iterations (single precision)
+        // ---- inverse-compositional iterations (single precision).  The
+        // residual sum is bilinear in the fraction (ax, ay) of u within its
+        // integer cell n = floor(u): with the cell's corner sums
+        // SA = sum_j g_j I1(x_j + n), SB at n + (1, 0), SC at n + (0, 1),
+        // SD at n + (1, 1), it is (SA + ax (SB - SA)) + ay ((SC + ax (SD -
+        // SC)) - (SA + ax (SB - SA))) - c.  The corner sums depend on the
+        // cell only, so a patch forms them when u enters a cell and reuses
+        // them while u stays there (the usual case once it converges).
         const float flim = (float)lim;
         float ux = (float)u0x, uy = (float)u0y;
         const int iters = d->iters;
+        float S[8] = {};  // SA, SB, SC, SD for the x gradient, then for the y gradient
+        int cix = INT32_MIN, ciy = INT32_MIN;
         for (int it = 0; it < iters; ++it) {
             const float sxu = fminf(fmaxf(ux, -flim), flim), syu = fminf(fmaxf(uy, -flim), flim);
             const float fx = floorf(sxu), fy = floorf(syu);
             const float ax = sxu - fx, ay = syu - fy;
             const int ix = (int)fx, iy = (int)fy;
-            const int rx = x + ix - RX0, ry = oy + iy - RY0;
-            float px[CPL], qx[CPL], py[CPL], qy[CPL];  // per patch column
+            if (ix != cix || iy != ciy) {  // the same for every lane of a patch
+                cix = ix;
+                ciy = iy;
+                float A[kPatch + 1][CPL + 1];  // samples rows 0..8, columns 0..CPL
+                const int rx = x + ix - RX0, ry = oy + iy - RY0;
+                if ((unsigned)rx < (unsigned)(RW - CPL) && (unsigned)ry < (unsigned)(RH - kPatch)) {
+                    const float* q = sR + ry * kDisRP + rx;
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) px[c] = qx[c] = py[c] = qy[c] = 0.f;
-            if ((unsigned)rx < (unsigned)(RW - CPL) && (unsigned)ry < (unsigned)(RH - kPatch)) {
-                const float* q = sR + ry * kDisRP + rx;
-                // all samples read before any is used (one LDS round trip)
-                float A[kPatch + 1][CPL + 1];
+                    for (int j = 0; j <= kPatch; ++j)
 #pragma unroll
-                for (int j = 0; j <= kPatch; ++j)
+                        for (int c = 0; c <= CPL; ++c) A[j][c] = q[j * kDisRP + c];
+                } else {
+                    // off the staged region: clamped samples from global
+                    // memory, all loaded before the first is used
+                    int xs[CPL + 1];
 #pragma unroll
-                    for (int c = 0; c <= CPL; ++c) A[j][c] = q[j * kDisRP + c];
+                    for (int c = 0; c <= CPL; ++c) xs[c] = clampi(x + ix + c, 0, Wl - 1);
+#pragma unroll
+                    for (int j = 0; j <= kPatch; ++j) {
+                        const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
+#pragma unroll
+                        for (int c = 0; c <= CPL; ++c) A[j][c] = row[xs[c]];
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
+                // per patch column, rows in order; then the columns as one
+                // binary tree (a lane's columns, then the lanes)
 #pragma unroll
-                for (int j = 0; j <= kPatch; ++j) {
-                    const float* a = A[j];
+                for (int k = 0; k < 8; ++k) S[k] = 0.f;
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const float h = a[c] + ax * (a[c + 1] - a[c]);
-                        if (j < kPatch) {
-                            px[c] += fgx[c][j] * h;
-                            py[c] += fgy[c][j] * h;
-                        }
-                        if (j > 0) {
-                            qx[c] += fgx[c][j - 1] * h;
-                            qy[c] += fgy[c][j - 1] * h;
-                        }
+                for (int c = 0; c < CPL; ++c) {
+                    float t[8] = {};
+#pragma unroll
+                    for (int j = 0; j < kPatch; ++j) {
+                        t[0] += fgx[c][j] * A[j][c];
+                        t[1] += fgx[c][j] * A[j][c + 1];
+                        t[2] += fgx[c][j] * A[j + 1][c];
+                        t[3] += fgx[c][j] * A[j + 1][c + 1];
+                        t[4] += fgy[c][j] * A[j][c];
+                        t[5] += fgy[c][j] * A[j][c + 1];
+                        t[6] += fgy[c][j] * A[j + 1][c];
+                        t[7] += fgy[c][j] * A[j + 1][c + 1];
                     }
-                }
-            } else {
-                // every sample is loaded before the first is used, so the
-                // loads overlap
-                int xs[CPL + 1];
 #pragma unroll
-                for (int c = 0; c <= CPL; ++c) xs[c] = clampi(x + ix + c, 0, Wl - 1);
-                float A[kPatch + 1][CPL + 1];
-#pragma unroll
-                for (int j = 0; j <= kPatch; ++j) {
-                    const float* row = I1 + (size_t)clampi(oy + j + iy, 0, Hl - 1) * Wl;
-#pragma unroll
-                    for (int c = 0; c <= CPL; ++c) A[j][c] = row[xs[c]];
+                    for (int k = 0; k < 8; ++k) S[k] = c ? S[k] + t[k] : t[k];
                 }
 #pragma unroll
-                for (int j = 0; j <= kPatch; ++j) {
-                    const float* a = A[j];
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const float h = a[c] + ax * (a[c + 1] - a[c]);
-                        if (j < kPatch) {
-                            px[c] += fgx[c][j] * h;
-                            py[c] += fgy[c][j] * h;
-                        }
-                        if (j > 0) {
-                            qx[c] += fgx[c][j - 1] * h;
-                            qy[c] += fgy[c][j - 1] * h;
-                        }
-                    }
-                }
+                for (int k = 0; k < 8; ++k) S[k] = redf<LP>(S[k]);
             }
-            float bx = 0.f, by = 0.f;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const float bxc = px[c] + ay * (qx[c] - px[c]), byc = py[c] + ay * (qy[c] - py[c]);
-                bx = c ? bx + bxc : bxc;
-                by = c ? by + byc : byc;
-            }
-            bx = redf<LP>(bx) - fcx;
-            by = redf<LP>(by) - fcy;
+            const float px_ = S[0] + ax * (S[1] - S[0]), qx_ = S[2] + ax * (S[3] - S[2]);
+            const float py_ = S[4] + ax * (S[5] - S[4]), qy_ = S[6] + ax * (S[7] - S[6]);
+            const float bx = (px_ + ay * (qx_ - px_)) - fcx;
+            const float by = (py_ + ay * (qy_ - py_)) - fcy;
             ux -= fia * bx + fib * by;
             uy -= fib * bx + fic * by;
         }

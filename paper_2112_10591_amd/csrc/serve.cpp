@@ -310,7 +310,7 @@ int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
     {
         std::lock_guard<std::mutex> g(ctx->mu);
         Lut lut;
-        if ((rc = lut_for(ctx, p->alpha, &lut))) return rc;
+        if ((rc = lut_for(ctx, p->alpha, p->surface, &lut))) return rc;
         const size_t N = (size_t)p->width * p->height;
         bool ok = true;
         for (int i = 0; i < 2; ++i) {

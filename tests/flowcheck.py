@@ -53,11 +53,14 @@ def _stats(e):
     return float(np.percentile(e, 99.9)), float((e > FLOW_FAR).mean())
 
 
-def assert_flow_matches(f, r, tag, where=None):
+def assert_flow_matches(f, r, tag, where=None, scale=1.0):
     """GPU flow f against the oracle's flow r ([2, H, W] array, or an
     OracleFlow): the mean bar, then the per-pixel bars over the pixels
     `where` selects (default all), relaxed to twice the oracle's own
-    one-ulp spread when r is an OracleFlow and a fixed bar is missed."""
+    one-ulp spread when r is an OracleFlow and a fixed bar is missed.
+    scale: the largest surface value over that of eq. (1) (1): single
+    precision rounds relative to the values summed, so the p99.9 bar grows
+    with it (the ablation surfaces reach d_sat or more)."""
     ref = r.flow if isinstance(r, OracleFlow) else r
     e = epe(f, ref)
     if where is not None:
@@ -66,7 +69,7 @@ def assert_flow_matches(f, r, tag, where=None):
     say(f"  {tag}: EPE vs oracle mean {e.mean():.2e} p99.9 {p999:.2e} max {e.max():.2e} "
         f"beyond {FLOW_FAR} px {far:.2e} over {e.size} px")
     assert e.mean() <= FLOW_MEAN, tag
-    if p999 <= FLOW_P999 and far <= FLOW_FAR_FRAC:
+    if p999 <= FLOW_P999 * scale and far <= FLOW_FAR_FRAC:
         return
     assert isinstance(r, OracleFlow), f"{tag}: per-pixel bar missed"
     es = epe(ref, r.perturbed())
@@ -75,7 +78,7 @@ def assert_flow_matches(f, r, tag, where=None):
     sp999, sfar = _stats(es)
     say(f"  {tag}: oracle vs itself with a one-ulp input change: p99.9 {sp999:.2e} "
         f"beyond {FLOW_FAR} px {sfar:.2e} (max {es.max():.2e})")
-    assert p999 <= max(FLOW_P999, SELF_FACTOR * sp999), tag
+    assert p999 <= max(FLOW_P999 * scale, SELF_FACTOR * sp999), tag
     assert far <= max(FLOW_FAR_FRAC, SELF_FACTOR * sfar), tag
 
 

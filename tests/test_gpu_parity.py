@@ -365,3 +365,46 @@ def test_flow_warm_start_constant_velocity(ctx):
     assert np.all(f[0] == v[0]) and np.all(f[1] == v[1])
     o = oracle_flow(p, r, r, prev_flow=prev)
     assert np.all(o[0] == v[0]) and np.all(o[1] == v[1])
+
+
+# --------------------------------------------------------------------------
+# the distance-surface alternatives of the ablation study (Sec. IV-B)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_surface_kinds_vs_oracle(ctx, kind):
+    """DS_L, DS_LB and DS_Log in place of eq. (1): the surface bit for bit
+    against the oracle's formula on the same squared distances (an empty
+    window included: the no-edge sentinel), the pyramid within 1e-6."""
+    for W, H, n, lv in [(346, 260, 20_000, 3), (1280, 720, 300_000, 4), (100, 70, 0, 2)]:
+        _say(f"surface kind {kind} {W}x{H} n={n}")
+        p = L.ebof_params_default(W, H, levels=lv, surface=kind)
+        ev = random_events(W, H, n, 40 + kind)
+        g = gpu_window(ctx, p, ev)
+        r = ref_window(p, ev)
+        assert np.array_equal(g["edge"], r["Edf"]) and np.array_equal(g["d2"], r["D2"])
+        S = oracle.surface_kind(r["D2"], float(np.float32(p.alpha)), kind)
+        assert np.array_equal(g["pyr"][:W * H], S.ravel()), "surface differs"
+        ref, _ = oracle.pyramid(S, lv)
+        rel = np.abs(g["pyr"].astype(np.float64) - ref) / np.maximum(np.abs(ref), 1e-30)
+        assert rel.max() <= 1e-6
+
+
+def test_flow_on_bounded_surface_vs_oracle(ctx):
+    """The whole path on the DS_LB surface (C1 pair): the flow against the
+    oracle's flow between the oracle's DS_LB pyramids."""
+    s = synth.c1_stream(0)
+    p = L.ebof_params_default(s.W, s.H, surface=L.EBOF_SURFACE_BOUNDED)
+    rs, gs = [], []
+    for k in (0, 1):
+        ev = s.window(k)
+        g = gpu_window(ctx, p, ev)
+        r = ref_window(p, ev)
+        S = oracle.surface_kind(r["D2"], float(np.float32(p.alpha)), L.EBOF_SURFACE_BOUNDED)
+        r["pyr"], _ = oracle.pyramid(S, p.levels)
+        assert np.array_equal(g["pyr"][:s.W * s.H], S.ravel())
+        rs.append(r)
+        gs.append(g)
+    _say("flow on the DS_LB surface (C1)")
+    f = gpu_flow(ctx, p, gs[0]["_pyr_dev"], gs[1]["_pyr_dev"])
+    d_sat = float(np.float32(p.alpha)) * np.log(255.0)
+    assert_flow_matches(f, OracleFlow(p, rs[0], rs[1]), "C1 DS_LB", scale=d_sat)
