@@ -370,6 +370,38 @@ int ebof_signal_read(ebof_ctx *ctx, int32_t slot, uint32_t *value);
 #define EBOF_MAX_OWNED_STREAMS 16
 int ebof_stream_create(ebof_ctx *ctx, void **hip_stream);
 
+/* ---- evaluation (Sec. IV, evaluation metrics) -----------------------------------
+ * Asynchronous on hip_stream; results land in device memory (out_dev) when
+ * the stream reaches them.  Scratch comes from the context's arena, one per
+ * image size and stream. */
+
+/* Average endpoint error and outlier rate of flow against a ground truth gt
+ * (both device, 2*width*height floats, u plane then v plane) over the pixels
+ * where mask != 0 (device width*height bytes; NULL = every pixel): AEE =
+ * mean |gt - flow|; a pixel is an outlier when |gt - flow| > 3 px and > 5 %
+ * of |gt|.  Per-pixel arithmetic in double.  out_dev: device 3 doubles, AEE,
+ * outlier fraction, pixels counted (0 and 0 when none).  EBOF_E_INVAL for
+ * NULL buffers or a size outside [1, EBOF_MAX_DIM]. */
+int ebof_flow_errors(ebof_ctx *ctx, int32_t width, int32_t height,
+                     const float *flow, const float *gt, const uint8_t *mask,
+                     double *out_dev, void *hip_stream);
+
+/* Flow warp loss (Sec. IV) of the events of the window [t0_us, t0_us +
+ * p->dt_us) on the sensor of p under flow (device 2*W*H floats, pixels per
+ * dt_us): the events are accumulated at their own pixel (uncompensated) and,
+ * moved back to the window start by the flow at their pixel scaled by their
+ * time in the window (x - u (t - t0) / dt), bilinearly into the four pixels
+ * around the moved position (compensated; votes off the sensor are lost).
+ * Each event votes its polarity (pol: device n int8, <0 is -1, else +1) or
+ * 1 when pol is NULL.  Votes are summed in fixed point (2^-32), so the
+ * result does not depend on scheduling.  out_dev: device 3 doubles, the FWL
+ * var(compensated) / var(uncompensated) (0 when the latter is 0), and the
+ * two variances over all W*H pixels. */
+int ebof_fwl(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
+             const uint16_t *y, const int64_t *t, const int8_t *pol, int64_t n,
+             int64_t t0_us, const float *flow, double *out_dev,
+             void *hip_stream);
+
 /* ---- measurement -------------------------------------------------------------
  * Kernel timing: when enabled, every launch of a selected kernel is
  * bracketed by a pair of HIP events recorded on its stream right before and

@@ -114,6 +114,8 @@ def load():
         "ebof_window_surface": ([P, pp, P, P, P, i64, i64, P, P, P, P, P], ctypes.c_int),
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
         "ebof_flow_noalloc": ([pp, P, P, P, P, P], ctypes.c_int),
+        "ebof_flow_errors": ([P, i32, i32, P, P, P, P, P], ctypes.c_int),
+        "ebof_fwl": ([P, pp, P, P, P, P, i64, i64, P, P, P], ctypes.c_int),
         "ebof_flow_warm": ([P, pp, P, P, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
         "ebof_set_tuning": ([P, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
@@ -143,7 +145,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_run_batch", "ebof_set_tuning",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_flow_errors", "ebof_fwl", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
@@ -329,6 +331,42 @@ def ebof_flow_noalloc(p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
     m = _dev(mask, torch.uint8, N, "mask", optional=True)
     f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
     return _check(None, load().ebof_flow_noalloc(ctypes.byref(p), a, b, m, f, _stream(stream)))
+
+
+def _sync(stream):
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+
+
+def ebof_flow_errors(ctx, width, height, flow, gt, mask=None, stream=None):
+    """(AEE, outlier fraction, pixels counted) of flow against gt over mask
+    (Sec. IV); waits for the stream."""
+    N = int(width) * int(height)
+    f = _dev(flow, torch.float32, 2 * N, "flow")
+    g = _dev(gt, torch.float32, 2 * N, "gt")
+    m = _dev(mask, torch.uint8, N, "mask", optional=True)
+    out = torch.empty(3, dtype=torch.float64, device=flow.device)
+    _check(ctx.handle, ctx.lib.ebof_flow_errors(ctx.handle, int(width), int(height), f, g, m,
+                                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    _sync(stream)
+    a, o, n = out.cpu().tolist()
+    return a, o, int(n)
+
+
+def ebof_fwl(ctx, p, x, y, t, t0_us, flow, pol=None, stream=None):
+    """(FWL, variance compensated, variance uncompensated) of the window's
+    events under flow (Sec. IV); waits for the stream."""
+    ne = int(x.numel())
+    N = p.width * p.height
+    a = _dev(x, torch.uint16, ne, "x")
+    b = _dev(y, torch.uint16, ne, "y")
+    c = _dev(t, torch.int64, ne, "t")
+    q = _dev(pol, torch.int8, ne, "pol", optional=True)
+    f = _dev(flow, torch.float32, 2 * N, "flow")
+    out = torch.empty(3, dtype=torch.float64, device=flow.device)
+    _check(ctx.handle, ctx.lib.ebof_fwl(ctx.handle, ctypes.byref(p), a, b, c, q, ne, int(t0_us), f,
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    _sync(stream)
+    return tuple(out.cpu().tolist())
 
 
 def ebof_set_tuning(ctx, mode=EBOF_TUNE_AUTO, cache_path=None):

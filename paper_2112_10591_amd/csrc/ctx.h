@@ -80,6 +80,12 @@ struct BatchRunner {
     std::map<std::string, Tune> tunes;  // launch shapes per batch layout (autotuner)
 };
 
+// Scratch of the evaluation calls: two int64 images and the partial sums.
+struct EvalScratch {
+    long long* img = nullptr;
+    char* part = nullptr;
+};
+
 // Extra per-window outputs of the served form.
 struct WinExtra {
     uint8_t* mask_out = nullptr;
@@ -102,6 +108,8 @@ struct ebof_ctx {
     // stage-call scratch per (W, H, levels, stride, HIP stream): calls on
     // different streams may overlap, calls on one stream are ordered by it
     std::map<std::tuple<int, int, int, int, uintptr_t>, ebof::Scratch> stage_scratch;
+    // evaluation-call scratch per (pixels, HIP stream)
+    std::map<std::pair<int64_t, uintptr_t>, ebof::EvalScratch> eval_scratch;
 
     // batched form
     std::vector<ebof::Scratch> batch_slots;
