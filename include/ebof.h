@@ -183,6 +183,34 @@ int ebof_window_surface(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
                         uint64_t *n_dropped_dev, int32_t *d2_out,
                         float *pyr_out, void *hip_stream);
 
+/* Adaptive windows (the Conclusion proposes an accumulation time that adapts
+ * to the scene instead of a fixed Delta-T; the rule here is the area event
+ * count): the sensor of width x height is tiled from (0, 0) by squares of
+ * `area` pixels; scanning the time-ordered events x, y (device, n each) from
+ * index i0, every event on the sensor counts for its square, and the window
+ * ends right after the event that brings some square to k_events (or at n
+ * when none does).  A square as large as the sensor makes windows of
+ * k_events events.  range_dev: device int64[2] receiving [i0, end) on the
+ * stream, for ebof_window_surface_range.  EBOF_E_INVAL for bad sizes, area
+ * < 1, k_events < 1, i0 outside [0, n], more than 8192 squares or NULL
+ * arrays.  Scratch (32 MiB per HIP stream) comes from the arena. */
+int ebof_window_end(ebof_ctx *ctx, int32_t width, int32_t height,
+                    const uint16_t *x, const uint16_t *y, int64_t n, int64_t i0,
+                    int32_t area, int32_t k_events, int64_t *range_dev,
+                    void *hip_stream);
+
+/* ebof_window_surface for the events of the index range range_dev (device
+ * int64[2], [i0, i1), e.g. from ebof_window_end, read on the stream): every
+ * event of the range is binned, with no time test; x, y: device arrays of n
+ * events (indices at or past n are never read, whatever the range holds;
+ * the launch covers n events from i0).  Outputs and errors as
+ * ebof_window_surface. */
+int ebof_window_surface_range(ebof_ctx *ctx, const ebof_params *p,
+                              const uint16_t *x, const uint16_t *y, int64_t n,
+                              const int64_t *range_dev, uint8_t *edge_out,
+                              uint64_t *n_dropped_dev, int32_t *d2_out,
+                              float *pyr_out, void *hip_stream);
+
 /* Sec. III-D: dense flow from the surface pyramid of window k-1 (pyr_prev,
  * the reference) to that of window k (pyr_curr), both device, P floats, by
  * dense inverse search: for levels L-1 .. 0, a grid of 8x8 patches at the

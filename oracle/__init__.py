@@ -76,6 +76,8 @@ def _load():
     lib.oref_flow_errors.restype = i64
     lib.oref_fwl.argtypes = [i32, i32, P, P, P, P, i64, i64, i64, P, P, P]
     lib.oref_fwl.restype = f64
+    lib.oref_window_end_area.argtypes = [i32, i32, P, P, i64, i64, i32, i32]
+    lib.oref_window_end_area.restype = i64
     lib.oref_dis_flow.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P]
     lib.oref_dis_flow.restype = ctypes.c_int
     lib.oref_dis_flow_warm.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P, P]
@@ -205,6 +207,14 @@ def fwl(W, H, x, y, t, t0, dt, flow, pol=None):
     r = _load().oref_fwl(int(W), int(H), _ptr(x), _ptr(y), _ptr(t), _ptr(pp) if pp is not None else None,
                          x.size, int(t0), int(dt), _ptr(f), ctypes.byref(vc), ctypes.byref(vu))
     return r, vc.value, vu.value
+
+
+def window_end_area(W, H, x, y, i0, area, k):
+    """End (exclusive) of the adaptive window starting at event i0: one past
+    the event that brings some area x area square to k events, or len(x)."""
+    x = np.ascontiguousarray(x, np.uint16)
+    y = np.ascontiguousarray(y, np.uint16)
+    return int(_load().oref_window_end_area(int(W), int(H), _ptr(x), _ptr(y), x.size, int(i0), int(area), int(k)))
 
 
 def alpha_from_dsat(d_sat, eps=1.0 / 255.0):

@@ -340,6 +340,33 @@ double oref_fwl(int32_t W, int32_t H, const uint16_t *x, const uint16_t *y,
     return vu > 0.0 ? vc / vu : 0.0;
 }
 
+/* Adaptive windows (the Conclusion's adaptive accumulation time, with the
+ * area event count as the rule): the sensor is tiled by squares of side
+ * `area` pixels from (0, 0); scanning a time-ordered stream from event i0,
+ * each on-sensor event counts for its square, and the window ends right after
+ * the event that brings some square to k_events.  Returns that end (one past
+ * the event), or n when no square reaches k_events.  Events off the sensor
+ * are skipped (they count for no square). */
+int64_t oref_window_end_area(int32_t W, int32_t H, const uint16_t *x,
+                             const uint16_t *y, int64_t n, int64_t i0,
+                             int32_t area, int32_t k_events)
+{
+    int32_t ax = (W + area - 1) / area, ay = (H + area - 1) / area;
+    int32_t *cnt = (int32_t *)calloc((size_t)ax * ay, sizeof(int32_t));
+    int64_t end = n;
+    for (int64_t e = i0; e < n; e++) {
+        if (x[e] >= W || y[e] >= H)
+            continue;
+        int32_t m = (y[e] / area) * ax + x[e] / area;
+        if (++cnt[m] >= k_events) {
+            end = e + 1;
+            break;
+        }
+    }
+    free(cnt);
+    return end;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gaussian pyramid of a surface: binomial 5-tap blur then keep every second */
 /* pixel, reflect-101 border.                                               */

@@ -95,6 +95,15 @@ double oref_fwl(int32_t W, int32_t H, const uint16_t *x, const uint16_t *y,
                 int64_t dt, const double *flow, double *var_comp,
                 double *var_uncomp);
 
+/* Adaptive windows (the adaptive accumulation time the Conclusion proposes,
+ * with the area event count as the rule): scanning a time-ordered stream from
+ * event i0, each on-sensor event counts for its square of the area x area
+ * tiling from (0, 0); returns one past the event that brings some square to
+ * k_events, or n when none does. */
+int64_t oref_window_end_area(int32_t W, int32_t H, const uint16_t *x,
+                             const uint16_t *y, int64_t n, int64_t i0,
+                             int32_t area, int32_t k_events);
+
 /* One pyramid reduction: out(X,Y) = sum_{i,j=-2..2} k_i k_j in(2X+i, 2Y+j),
  * k = [1 4 6 4 1]/16, reflect-101 border.  out is ((W+1)/2) x ((H+1)/2). */
 void oref_pyr_down(int32_t W, int32_t H, const float *in, float *out);

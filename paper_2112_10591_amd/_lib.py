@@ -115,6 +115,8 @@ def load():
         "ebof_flow": ([P, pp, P, P, P, P, P], ctypes.c_int),
         "ebof_flow_noalloc": ([pp, P, P, P, P, P], ctypes.c_int),
         "ebof_flow_errors": ([P, i32, i32, P, P, P, P, P], ctypes.c_int),
+        "ebof_window_end": ([P, i32, i32, P, P, i64, i64, i32, i32, P, P], ctypes.c_int),
+        "ebof_window_surface_range": ([P, pp, P, P, i64, P, P, P, P, P, P], ctypes.c_int),
         "ebof_fwl": ([P, pp, P, P, P, P, i64, i64, P, P, P], ctypes.c_int),
         "ebof_flow_warm": ([P, pp, P, P, P, P, P, P, P], ctypes.c_int),
         "ebof_run_batch": ([P, ctypes.POINTER(ebof_window), i32, P], ctypes.c_int),
@@ -145,7 +147,7 @@ def load():
 def exported_symbols():
     return ["ebof_params_default", "ebof_validate", "ebof_pyramid_floats",
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
-            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_flow_errors", "ebof_fwl", "ebof_run_batch", "ebof_set_tuning",
+            "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_flow_errors", "ebof_fwl", "ebof_window_end", "ebof_window_surface_range", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
@@ -331,6 +333,38 @@ def ebof_flow_noalloc(p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):
     m = _dev(mask, torch.uint8, N, "mask", optional=True)
     f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
     return _check(None, load().ebof_flow_noalloc(ctypes.byref(p), a, b, m, f, _stream(stream)))
+
+
+def ebof_window_end(ctx, width, height, x, y, i0, area, k_events, range_out=None, stream=None):
+    """End of the adaptive window from event i0 (area event count rule).
+    With range_out (a device int64[2] tensor) the call is asynchronous and
+    fills it; without, returns (i0, end) after waiting for the stream."""
+    n = int(x.numel())
+    a = _dev(x, torch.uint16, n, "x")
+    b = _dev(y, torch.uint16, n, "y")
+    out = range_out if range_out is not None else torch.empty(2, dtype=torch.int64, device=x.device)
+    r = _dev(out, torch.int64, 2, "range_out")
+    _check(ctx.handle, ctx.lib.ebof_window_end(ctx.handle, int(width), int(height), a, b, n, int(i0), int(area),
+                                               int(k_events), r, _stream(stream)))
+    if range_out is not None:
+        return None
+    _sync(stream)
+    return tuple(int(v) for v in out.cpu().tolist())
+
+
+def ebof_window_surface_range(ctx, p, x, y, range_dev, edge_out, pyr_out, d2_out=None, n_dropped=None, stream=None):
+    """ebof_window_surface of the events in the device index range range_dev."""
+    n = int(x.numel())
+    N = p.width * p.height
+    a = _dev(x, torch.uint16, n, "x")
+    b = _dev(y, torch.uint16, n, "y")
+    r = _dev(range_dev, torch.int64, 2, "range_dev")
+    e = _dev(edge_out, torch.uint8, N, "edge_out")
+    pr = _dev(pyr_out, torch.float32, ebof_pyramid_floats(p), "pyr_out")
+    d2 = _dev(d2_out, torch.int32, N, "d2_out", optional=True)
+    nd = _dev(n_dropped, torch.uint64, 1, "n_dropped", optional=True)
+    return _check(ctx.handle, ctx.lib.ebof_window_surface_range(ctx.handle, ctypes.byref(p), a, b, n, r, e, nd, d2,
+                                                                pr, _stream(stream)))
 
 
 def _sync(stream):

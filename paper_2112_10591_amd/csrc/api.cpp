@@ -342,6 +342,8 @@ void runner_release(BatchRunner& br) {
     for (auto& kv : br.graphs)
         if (kv.second) (void)hipGraphExecDestroy(kv.second);
     br.graphs.clear();
+    if (br.capture) (void)hipStreamDestroy(br.capture);
+    br.capture = nullptr;
     for (auto& pb : br.pinned) {
         if (pb.host) (void)hipHostFree(pb.host);
         if (pb.done) (void)hipEventDestroy(pb.done);
@@ -357,6 +359,8 @@ static int runner_init(ebof_ctx* ctx, BatchRunner& br) {
         set_error("arena full (batch table of %zu bytes)", br.table_bytes);
         return EBOF_E_NOMEM;
     }
+    int rc0 = check_hip(ctx, hipStreamCreateWithFlags(&br.capture, hipStreamNonBlocking), "hipStreamCreate(capture)");
+    if (rc0) return rc0;
     br.pinned.resize(4);
     for (auto& pb : br.pinned) {
         int rc = check_hip(ctx, hipHostMalloc((void**)&pb.host, br.table_bytes, hipHostMallocDefault), "hipHostMalloc");
@@ -542,7 +546,7 @@ static int autotune(ebof_ctx* ctx, BatchRunner& br, const std::vector<WinDesc>& 
         const bool dis = s >= kStDis && s < kStDensify;
         std::vector<int> shapes{0};
         if (s == kStRows) shapes = {1, 2, 4, 8};
-        if (s == kStDensify) shapes = {64, 128, 256};
+        if (s == kStDensify) shapes = {16, 64, 128, 256};
         if (dis) shapes = {8, 4};
         float best_ms = -1.f;
         Tune win = best;
@@ -625,7 +629,8 @@ static int load_tunes(const char* path, std::map<std::string, Tune>* out) {
 // with fixed persistent grids, valid for any batch (every count is read from
 // the uploaded table).
 int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const WinExtra* extra, int32_t n,
-                   hipStream_t st, Scratch* const* scr, int graph_mode) {
+                   hipStream_t st, Scratch* const* scr, int graph_mode,
+                   const std::function<int(hipStream_t)>* between) {
     if (!w || n < 1 || n > EBOF_MAX_BATCH) {
         set_error("batch of %d windows outside [1, %d]", n, EBOF_MAX_BATCH);
         return EBOF_E_INVAL;
@@ -709,10 +714,13 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
         }
     }
     // One universal graph serves batches of any composition, so its launch
-    // shapes must not depend on the batch: 8 lanes per patch at every level
-    // (a layout's shapes are fixed by the layout itself).
-    if (universal)
-        for (int l = 0; l < kMaxLevels; ++l) tune.dis_lanes[l] = 8;
+    // shapes must not depend on the batch: by level only, 4 lanes per patch
+    // at level 0 (many patches: throughput) and 8 above (a layout's shapes
+    // are fixed by the layout itself).
+    if (universal) {
+        for (int l = 0; l < kMaxLevels; ++l) tune.dis_lanes[l] = l == 0 ? 4 : 8;
+        tune.dens_tw = 16;  // square tiles: waves off the mask skip their sums
+    }
     resolve_dis_lanes(tune, descs.data(), n);
     std::vector<int32_t> prefix;
     int32_t totals[kNumStages];
@@ -721,12 +729,14 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
     if ((rc = upload_table(ctx, br, descs, prefix, st))) return rc;
 
     const int mode = (ctx->timing_mask == 0 && ctx->use_graphs) ? graph_mode : kGraphNone;
-    auto run_all = [&](bool all) {
+    // part: 0 every stage, 1 the preprocessing stages, 2 the flow stages;
+    // ls: the stream the launches go to (the capture stream while capturing)
+    auto run_all = [&](bool all, int part, hipStream_t ls) {
         // consecutive launches of one kernel (pyramid chains, search levels)
         // form one group
         std::vector<int> order;
         for (int s : pipeline_order(lmax))
-            if (all || totals[s]) order.push_back(s);
+            if ((all || totals[s]) && (part == 0 || (part == 1) == (s < kStDis))) order.push_back(s);
         for (size_t i = 0; i < order.size();) {
             const int kid = stage_kernel_id(order[i]);
             size_t j = i + 1;
@@ -734,7 +744,7 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
             auto launch_group = [&] {
                 for (size_t q = i; q < j; ++q) {
                     const int s = order[q];
-                    launch_stage(batch_launch(br, &descs[0], s, totals[s], stage_grid(s, totals[s], tune, mode), st),
+                    launch_stage(batch_launch(br, &descs[0], s, totals[s], stage_grid(s, totals[s], tune, mode), ls),
                                  s, tune);
                 }
             };
@@ -745,35 +755,56 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
             i = j;
         }
     };
-    if (mode == kGraphNone) {
-        run_all(false);
-        return launch_status(ctx);
-    }
-    auto it = br.graphs.find(key);
-    if (it == br.graphs.end()) {
-        hipStreamCaptureStatus cst;
-        if ((rc = check_hip(ctx, hipStreamIsCapturing(st, &cst), "hipStreamIsCapturing"))) return rc;
-        if (cst != hipStreamCaptureStatusNone || st == nullptr) {
-            // the stream cannot be captured here: launch directly
-            run_all(false);
-            return launch_status(ctx);
+    const int parts[2] = {between ? 1 : 0, 2};
+    for (int pi = 0; pi < (between ? 2 : 1); ++pi) {
+        const int part = parts[pi];
+        if (part == 2 && (rc = (*between)(st))) return rc;
+        if (mode == kGraphNone) {
+            run_all(false, part, st);
+            if ((rc = launch_status(ctx))) return rc;
+            continue;
         }
-        hipGraph_t graph;
-        if ((rc = check_hip(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
-                            "hipStreamBeginCapture")))
-            return rc;
-        run_all(universal || mode == kGraphLayout);
-        if ((rc = check_hip(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture"))) return rc;
-        hipGraphExec_t exec = nullptr;
-        rc = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-        (void)hipGraphDestroy(graph);
-        if (rc) return rc;
-        it = br.graphs.emplace(key, exec).first;
+        const std::string gkey = key + (part == 0 ? "" : part == 1 ? "/pre" : "/flow");
+        auto it = br.graphs.find(gkey);
+        if (it == br.graphs.end()) {
+            hipStreamCaptureStatus cst;
+            if ((rc = check_hip(ctx, hipStreamIsCapturing(st, &cst), "hipStreamIsCapturing"))) return rc;
+            if (cst != hipStreamCaptureStatusNone || st == nullptr) {
+                // the stream cannot be captured here: launch directly
+                run_all(false, part, st);
+                if ((rc = launch_status(ctx))) return rc;
+                continue;
+            }
+            hipGraph_t graph;
+            if ((rc = check_hip(ctx, hipStreamBeginCapture(br.capture, hipStreamCaptureModeThreadLocal),
+                                "hipStreamBeginCapture")))
+                return rc;
+            run_all(universal || mode == kGraphLayout, part, br.capture);
+            if ((rc = check_hip(ctx, hipStreamEndCapture(br.capture, &graph), "hipStreamEndCapture"))) return rc;
+            hipGraphExec_t exec = nullptr;
+            rc = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            (void)hipGraphDestroy(graph);
+            if (rc) return rc;
+            it = br.graphs.emplace(gkey, exec).first;
+        }
+        if ((rc = check_hip(ctx, hipGraphLaunch(it->second, st), "hipGraphLaunch"))) return rc;
     }
-    return check_hip(ctx, hipGraphLaunch(it->second, st), "hipGraphLaunch");
+    return EBOF_OK;
 }
 
 int validate_params(const ebof_params* p) { return validate(p); }
+
+// A stream with a CU mask covering every compute unit, which the HIP runtime
+// backs with a hardware queue of its own.
+int queue_stream_create(ebof_ctx* ctx, hipStream_t* out) {
+    int ncu = 0;
+    int rc = check_hip(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device),
+                       "hipDeviceGetAttribute");
+    if (rc) return rc;
+    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0xffffffffu);
+    return check_hip(ctx, hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data()),
+                     "hipExtStreamCreateWithCUMask");
+}
 
 }  // namespace ebof
 
@@ -933,15 +964,8 @@ int ebof_stream_create(ebof_ctx* ctx, void** hip_stream) {
         set_error("ebof_stream_create: the context owns the maximum number of streams");
         return EBOF_E_STATE;
     }
-    int ncu = 0;
-    if ((rc = check_hip(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device),
-                        "hipDeviceGetAttribute")))
-        return rc;
-    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0xffffffffu);
     hipStream_t st = nullptr;
-    if ((rc = check_hip(ctx, hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()),
-                        "hipExtStreamCreateWithCUMask")))
-        return rc;
+    if ((rc = queue_stream_create(ctx, &st))) return rc;
     ctx->owned_streams.push_back(st);
     *hip_stream = (void*)st;
     return EBOF_OK;
@@ -981,11 +1005,11 @@ const char* ebof_last_error(const ebof_ctx*) { return g_err; }
 // the descriptor carries the surface table.  *out: the window's descriptor.
 static int bin_impl(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, const int64_t* t,
                     int64_t n, int64_t t0_us, uint8_t* edge_out, uint64_t* n_dropped_dev, hipStream_t st, bool pack,
-                    const char* who, WinDesc* out) {
+                    const char* who, WinDesc* out, const int64_t* range = nullptr) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;
     if ((rc = validate(p))) return rc;
-    if (n < 0 || (n > 0 && (!x || !y || !t)) || !edge_out) {
+    if (n < 0 || (n > 0 && (!x || !y || (!t && !range))) || !edge_out) {
         set_error("%s: NULL buffer or negative n", who);
         return EBOF_E_INVAL;
     }
@@ -1023,6 +1047,7 @@ static int bin_impl(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
     d.stamp = stamp;
     d.e_df = edge_out;
     d.n_dropped = (unsigned long long*)n_dropped_dev;
+    d.range = range;
     if (zero) launch_zero(one_launch(&d, stage_items(d, kStZero, false, true, kStageTune), st));
     if (n > 0) timed(ctx, EBOF_K_SCATTER, st, [&] { launch_scatter(one_launch(&d, stage_items(d, kStScatter, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_DENOISE_FILL, st,
@@ -1111,9 +1136,11 @@ static void flow_launches(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d,
         for (int l = p->levels - 1; l >= 0; --l)
             launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l, tune.dis_lanes[l]);
     };
-    auto dens = [&] {
-        launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, kStageTune), st), kStageTune.dens_tw);
-    };
+    // masked output without the flow before masking: square 16x16 tiles, so
+    // that whole waves (16x4 pixels) lie off the edge pixels and skip the sums
+    Tune dt = kStageTune;
+    if ((d.flags & EBOF_MASK_FLOW) && d.mask && !d.flow_keep) dt.dens_tw = 16;
+    auto dens = [&] { launch_densify(one_launch(&d, stage_items(d, kStDensify, true, false, dt), st), dt.dens_tw); };
     if (ctx) {
         timed(ctx, EBOF_K_DIS_LEVEL, st, dis);
         timed(ctx, EBOF_K_DENSIFY, st, dens);
@@ -1121,6 +1148,25 @@ static void flow_launches(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d,
         dis();
         dens();
     }
+}
+
+int ebof_window_surface_range(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, const uint16_t* y, int64_t n,
+                              const int64_t* range_dev, uint8_t* edge_out, uint64_t* n_dropped_dev, int32_t* d2_out,
+                              float* pyr_out, void* hip_stream) {
+    if (ctx && (!pyr_out || !range_dev)) {
+        set_error("ebof_window_surface_range: NULL pyr_out or range_dev");
+        return EBOF_E_INVAL;
+    }
+    const hipStream_t st = (hipStream_t)hip_stream;
+    WinDesc d;
+    // (no time test: t0 = 0 and every event reads as t = 0, inside [0, dt))
+    int rc = bin_impl(ctx, p, x, y, nullptr, n, 0, edge_out, n_dropped_dev, st, true, "ebof_window_surface_range", &d,
+                      range_dev);
+    if (rc) return rc;
+    d.d2 = d2_out;
+    d.pyr = pyr_out;
+    surface_impl(ctx, p, d, st, true);
+    return launch_status(ctx);
 }
 
 int ebof_flow(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, const float* pyr_curr, const uint8_t* mask,

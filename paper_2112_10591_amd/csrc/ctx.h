@@ -7,6 +7,7 @@
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -69,6 +70,10 @@ struct TimedPair {
 struct BatchRunner {
     char* table_dev = nullptr;
     size_t table_bytes = 0;
+    // graphs are captured on this non-blocking stream and launched on the
+    // caller's: a capture on a blocking stream would fail other threads'
+    // work on the legacy stream meanwhile
+    hipStream_t capture = nullptr;
     struct Pinned {
         char* host = nullptr;
         hipEvent_t done = nullptr;
@@ -110,6 +115,8 @@ struct ebof_ctx {
     std::map<std::tuple<int, int, int, int, uintptr_t>, ebof::Scratch> stage_scratch;
     // evaluation-call scratch per (pixels, HIP stream)
     std::map<std::pair<int64_t, uintptr_t>, ebof::EvalScratch> eval_scratch;
+    // adaptive-window scratch per HIP stream
+    std::map<uintptr_t, void*> window_scratch;
 
     // batched form
     std::vector<ebof::Scratch> batch_slots;
@@ -139,10 +146,15 @@ int lut_for(ebof_ctx* ctx, float alpha, int32_t kind, Lut* out);
 int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t stream);
 void scratch_free(ebof_ctx* ctx, Scratch* s);
 void fill_desc(const ebof_params& p, const Geom& g, const Lut& lut, const Scratch& s, WinDesc* d);
+// between: when not null, called with the stream after the batch's
+// preprocessing stages and before its flow stages (to order the flow after
+// other work); the two parts are then launched (or captured) separately.
 int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const WinExtra* extra, int32_t n,
-                   hipStream_t stream, Scratch* const* scr, int graph_mode);
+                   hipStream_t stream, Scratch* const* scr, int graph_mode,
+                   const std::function<int(hipStream_t)>* between = nullptr);
 void runner_release(BatchRunner& br);
 int validate_params(const ebof_params* p);
+int queue_stream_create(ebof_ctx* ctx, hipStream_t* out);
 int check_hip(ebof_ctx* ctx, hipError_t e, const char* what);
 void serve_shutdown(ebof_ctx* ctx);
 }  // namespace ebof

@@ -62,6 +62,7 @@ struct WinDesc {
     const uint16_t* ey;
     const int64_t* et;
     int64_t n_ev, t0, t1;
+    const int64_t* range;  // device [i0, i1): bin these events, no time test (n_ev: the arrays' length)
     uint32_t stamp;     // value marking this window's pixels in e_raw
     uint32_t pad0;
     // buffers
@@ -129,13 +130,13 @@ struct Launch {
 // blocks a batched launch runs.
 struct Tune {
     int32_t rows_nr = 4;    // k_edt_rows: rows per item (1, 2, 4 or 8)
-    int32_t dens_tw = 64;   // k_densify: tile width (64, 128 or 256), kBlock / dens_tw rows
+    int32_t dens_tw = 64;   // k_densify: tile width (16, 64, 128 or 256), kBlock / dens_tw rows
     int32_t dis_lanes[kMaxLevels] = {};  // k_dis_level: lanes per patch (8 or 4; 0: by size)
     int32_t grid[kNumStages] = {};       // batched launch blocks per stage (0: the default)
 };
 inline bool tune_valid(const Tune& t) {
     const bool nr = t.rows_nr == 1 || t.rows_nr == 2 || t.rows_nr == 4 || t.rows_nr == 8;
-    const bool tw = t.dens_tw == 64 || t.dens_tw == 128 || t.dens_tw == 256;
+    const bool tw = t.dens_tw == 16 || t.dens_tw == 64 || t.dens_tw == 128 || t.dens_tw == 256;
     for (int l = 0; l < kMaxLevels; ++l)
         if (t.dis_lanes[l] != 0 && t.dis_lanes[l] != 4 && t.dis_lanes[l] != 8) return false;
     for (int s = 0; s < kNumStages; ++s)

@@ -147,17 +147,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const WinDesc one, const Bat
     for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
-        const int64_t n = d->n_ev, t0 = d->t0, t1 = d->t1;
+        const int64_t t0 = d->t0, t1 = d->t1;
         const uint32_t W = (uint32_t)d->W, H = (uint32_t)d->H;
         const uint8_t stamp = (uint8_t)d->stamp;
         uint8_t* __restrict__ er = d->e_raw;
-        const int64_t base = (int64_t)local * kEventsPerItem;
+        // a window by time, or an index range read from device memory (every
+        // event in it belongs to the window)
+        const bool by_range = d->range != nullptr;
+        const int64_t r0 = by_range ? d->range[0] : 0;
+        const int64_t n = by_range ? min(d->range[1], d->n_ev) : d->n_ev;  // n_ev: the arrays' length
+        const int64_t base = r0 + (int64_t)local * kEventsPerItem;
         uint32_t dropped = 0;
 #pragma unroll
         for (int k = 0; k < kEventsPerItem / kBlock; ++k) {
             const int64_t e = base + k * kBlock + threadIdx.x;
             if (e < n) {
-                const int64_t t = __builtin_nontemporal_load(d->et + e);
+                const int64_t t = by_range ? t0 : __builtin_nontemporal_load(d->et + e);
                 const uint32_t x = __builtin_nontemporal_load(d->ex + e);
                 const uint32_t y = __builtin_nontemporal_load(d->ey + e);
                 if (t >= t0 && t < t1 && x < W && y < H)
@@ -520,7 +525,13 @@ __device__ __forceinline__ int reflect101(int i, int n) {
 // intermediate level over the region the next one needs, writing only its own
 // part of every level.  Regions: R(deepest) = 8, R(k-1) = 2 R(k) + 3, origin
 // o(k-1) = 2 o(k) - 2.
-
+//
+// Borders: a level's outputs read its source only within two pixels of the
+// source image (positions -2 .. w+1), and reflect-101 maps those positions
+// into the image.  So every region position in that band holds the value of
+// its reflected position (staged from it, or computed at it), positions
+// further out are never read, and every output takes its 25 taps at fixed
+// offsets from one address.
 template <int NT>
 __device__ __forceinline__ void rc_init(int n, int& r, int& cc, int& dr, int& dc) {
     r = threadIdx.x / n;
@@ -535,6 +546,20 @@ __device__ __forceinline__ void rc_step(int n, int& r, int& cc, int dr, int dc) 
         cc -= n;
         ++r;
     }
+}
+
+// 5x5 binomial at q (top-left tap) of a region with row pitch P, in double
+template <int P>
+__device__ __forceinline__ float binom25(const float* q) {
+    double acc = 0.0;
+    constexpr double kw[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const float* a = q + j * P;
+        const double h = (double)a[0] + 4.0 * (double)a[1] + 6.0 * (double)a[2] + 4.0 * (double)a[3] + (double)a[4];
+        acc += kw[j] * h;
+    }
+    return (float)(acc * (1.0 / 256.0));
 }
 
 template <bool B>
@@ -564,18 +589,21 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
         for (int k = 0; k <= nlev; ++k)
             buf[k] = (nlev - k == 1) ? 85 * 85 + 41 * 41 : (nlev - k == 2) ? 85 * 85 : 0;
         {
+            // every position takes the value of its reflected position
+            // (clamped as well: positions beyond the band are never read)
             const LevelGeom g0 = d->lv[from];
             const float* __restrict__ src = d->pyr + g0.off;
             const int oxs = ox[0], oys = oy[0];
             auto at = [&](int r, int cc) {
-                const int X = oxs + cc, Y = oys + r;
-                return (X >= 0 && X < g0.w && Y >= 0 && Y < g0.h) ? src[(size_t)Y * g0.w + X] : 0.f;
+                const int X = clampi(reflect101(oxs + cc, g0.w), 0, g0.w - 1);
+                const int Y = clampi(reflect101(oys + r, g0.h), 0, g0.h - 1);
+                return src[(size_t)Y * g0.w + X];
             };
             stage_window<8, float, decltype(at), kPyrBlock>(sP + buf[0], R[0], R[0], at);
         }
         __syncthreads();
         for (int k = 1; k <= nlev; ++k) {
-            const LevelGeom gs = d->lv[from + k - 1], gt = d->lv[from + k];
+            const LevelGeom gt = d->lv[from + k];
             const int in = buf[k - 1], outb = buf[k];
             const int Rin = R[k - 1], oxi = ox[k - 1], oyi = oy[k - 1];
             const int n = R[k];
@@ -586,29 +614,16 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
             rc_init<kPyrBlock>(n, r, cc, dr, dc);
             for (; r < n; rc_step(n, r, cc, dr, dc)) {
                 const int X = ox[k] + cc, Y = oy[k] + r;
-                if (X < 0 || X >= gt.w || Y < 0 || Y >= gt.h) {
-                    if (k < nlev) sP[outb + r * n + cc] = 0.f;
-                    continue;
-                }
-                int xs[5], ys[5];
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    xs[t] = reflect101(2 * X + t - 2, gs.w) - oxi;
-                    ys[t] = reflect101(2 * Y + t - 2, gs.h) - oyi;
-                }
-                double acc = 0.0;
-                constexpr double kw[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    const int row = in + ys[j] * Rin;
-                    const double h = (double)sP[row + xs[0]] + 4.0 * (double)sP[row + xs[1]] +
-                                     6.0 * (double)sP[row + xs[2]] + 4.0 * (double)sP[row + xs[3]] +
-                                     (double)sP[row + xs[4]];
-                    acc += kw[j] * h;
-                }
-                const float v = (float)(acc * (1.0 / 256.0));
+                // the band around the image feeds the next level; the deepest
+                // level built here needs its image pixels only
+                const int band = k < nlev ? 2 : 0;
+                if (X < -band || X >= gt.w + band || Y < -band || Y >= gt.h + band) continue;
+                const int Xr = reflect101(X, gt.w), Yr = reflect101(Y, gt.h);
+                const float* q = sP + in + (2 * Yr - 2 - oyi) * Rin + (2 * Xr - 2 - oxi);
+                const float v = Rin == 85 ? binom25<85>(q) : Rin == 41 ? binom25<41>(q) : binom25<19>(q);
                 if (k < nlev) sP[outb + r * n + cc] = v;
-                if (X >= cx0 && X < cx0 + span && Y >= cy0 && Y < cy0 + span) dst[(size_t)Y * gt.w + X] = v;
+                if (X == Xr && Y == Yr && X >= cx0 && X < cx0 + span && Y >= cy0 && Y < cy0 + span)
+                    dst[(size_t)Y * gt.w + X] = v;
             }
             __syncthreads();
         }
@@ -1058,6 +1073,16 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
             if (d->mask_out) d->mask_out[pix] = 0;
             continue;
         }
+        // a pixel off the mask gets 0 without its sums, unless the flow
+        // before masking is wanted too
+        const uint8_t m = d->mask ? d->mask[pix] : 1;
+        const bool off = (d->flags & EBOF_MASK_FLOW) && !m;
+        if (off && !d->flow_keep) {
+            d->flow[pix] = 0.f;
+            d->flow[(size_t)W * H + pix] = 0.f;
+            if (d->mask_out) d->mask_out[pix] = m;
+            continue;
+        }
         const int s = d->stride;
         const float* __restrict__ I0 = d->pyr_prev;
         const float* __restrict__ I1 = d->pyr;
@@ -1072,8 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_densify(const WinDesc one, const Bat
             d->flow_keep[pix] = fu;
             d->flow_keep[(size_t)W * H + pix] = fv;
         }
-        const uint8_t m = d->mask ? d->mask[pix] : 1;
-        if ((d->flags & EBOF_MASK_FLOW) && !m) fu = fv = 0.f;
+        if (off) fu = fv = 0.f;
         d->flow[pix] = fu;
         d->flow[(size_t)W * H + pix] = fv;
         if (d->mask_out) d->mask_out[pix] = m;
@@ -1153,6 +1177,7 @@ void launch_dis_level(const Launch& L, int level, int lanes) {
 }
 void launch_densify(const Launch& L, int tile_w) {
     switch (tile_w) {
+        case 16: EBOF_LAUNCH_T(k_densify, 16, L); break;
         case 128: EBOF_LAUNCH_T(k_densify, 128, L); break;
         case 256: EBOF_LAUNCH_T(k_densify, 256, L); break;
         default: EBOF_LAUNCH_T(k_densify, 64, L); break;

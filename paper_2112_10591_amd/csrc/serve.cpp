@@ -1,16 +1,22 @@
 // serve.cpp -- serving runtime.
 //
-// A served stream keeps its last window's pyramid, edge image and flow
-// (before masking) resident in the arena (two of each, swapped per window)
-// plus its own scratch; opening a
-// stream is admitted only while the arena can hold that state.  Submitted
-// windows are queued; their host events are copied into a pinned ring and
-// sent asynchronously (copy stream) into a device ring in the arena.  A
-// batch-former thread takes whatever is queued (at most one window per
-// stream per batch, in submission order) as soon as fewer than two batches
-// are on the GPU, and runs it as one launch per stage on the compute stream
-// (one captured graph, replayed for every batch).  A completion thread waits
-// for each batch and timestamps its windows.
+// A served stream keeps its recent windows' pyramids and edge images
+// resident in the arena (three of each, in turn), two preprocessing scratches
+// (in turn) and, with EBOF_WARM_START, its previous flow before masking;
+// opening a stream is admitted only while the arena can hold that state.
+// Submitted windows are queued; their host events are copied into a pinned
+// ring and sent asynchronously (copy stream) into a device ring in the arena.
+// A batch-former thread takes whatever is queued (at most one window per
+// stream per batch, in submission order) as soon as a compute lane is free,
+// and runs it as one launch per stage (two captured graphs, replayed for
+// every batch: the preprocessing stages, then the flow stages) on that lane's
+// HIP stream.  Batches alternate between two lanes: a batch's preprocessing
+// runs while the previous batch's flow does, and its flow stages wait for the
+// previous batch to complete (a stream's window k+1 reads window k's pyramid
+// and follows its flow).  Three pyramid buffers per stream keep the windows
+// being written and read apart: window k+1's preprocessing writes the buffer
+// that neither window k's flow nor its own reads.  A completion thread waits
+// for each batch (they complete in order) and timestamps its windows.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -25,7 +31,9 @@ static int64_t now_ns() {
         .count();
 }
 
-constexpr int kMaxInflight = 2;       // batches on the GPU at once
+constexpr int kLanes = 2;             // compute streams; batches alternate between them
+constexpr int kMaxInflight = kLanes;  // batches on the GPU at once
+constexpr int kPyrBufs = 3;           // resident pyramids and edge images per stream
 constexpr int kServeMaxBatch = 256;   // windows per batch
 constexpr size_t kPinnedRing = size_t(128) << 20;
 constexpr size_t kDevRingMax = size_t(1) << 30;
@@ -35,13 +43,14 @@ static size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 struct ServeStream {
     ebof_params p;
     Geom g;
-    Scratch scr;
-    float* pyr[2] = {nullptr, nullptr};
-    uint8_t* edge[2] = {nullptr, nullptr};
-    float* flow[2] = {nullptr, nullptr};  // dense flow ending at the window of the same buffer
+    Scratch scr[2];  // preprocessing scratch of consecutive windows, in turn
+    int scr_next = 0;
+    float* pyr[kPyrBufs] = {};
+    uint8_t* edge[kPyrBufs] = {};
+    float* flow = nullptr;  // EBOF_WARM_START: the newest flow before masking
     int cur = 0;  // buffer of the newest window taken into a batch
     bool has_prev = false;
-    bool has_flow = false;  // the newest window computed a flow (flow[cur] is valid)
+    bool has_flow = false;  // the newest window computed a flow (flow is valid)
     int64_t last_t0 = 0;
     bool closing = false;
     int queued = 0;  // submitted and not completed
@@ -81,7 +90,7 @@ struct ServeState {
     std::condition_variable cv_work, cv_done;
     std::thread former, reaper;
     bool stop = false;
-    hipStream_t stream = nullptr, copy_stream = nullptr;
+    hipStream_t copy_stream = nullptr;
     std::map<int32_t, ServeStream> streams;
     int32_t next_sid = 1;
     std::deque<Pending> queue;
@@ -95,7 +104,11 @@ struct ServeState {
     Ring dev_ring_alloc;
     std::vector<hipEvent_t> event_pool;
     std::deque<Batch> inflight;
-    BatchRunner runner;
+    hipStream_t lane[kLanes] = {};
+    BatchRunner runner[kLanes];
+    int next_lane = 0;
+    hipEvent_t last_done = nullptr;  // completion of the newest batch issued
+    int forming = 0;                 // batches taken from the queue, not yet in flight
     int32_t error = EBOF_OK;
 };
 
@@ -138,7 +151,8 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             ServeStream& s = S->streams[q.sid];
             if (s.has_prev && !(s.p.flags & EBOF_CHAIN_ALWAYS) && q.t0 != s.last_t0 + s.p.dt_us)
                 s.has_prev = s.has_flow = false;  // gap in time: start over
-            const int nb = s.has_prev ? (s.cur ^ 1) : s.cur;
+            const int nb = s.has_prev ? (s.cur + 1) % kPyrBufs : s.cur;
+            const bool warm = (s.p.flags & EBOF_WARM_START) != 0;
             ebof_window& w = win[i];
             std::memset(&w, 0, sizeof w);
             w.params = &s.p;
@@ -152,11 +166,14 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             w.pyr_prev = s.has_prev ? s.pyr[s.cur] : nullptr;
             w.mask = s.has_prev ? s.edge[s.cur] : nullptr;
             w.flow_out = q.flow_out;
-            w.flow_dense_out = s.has_prev ? s.flow[nb] : nullptr;
-            w.flow_init = (s.has_prev && s.has_flow && (s.p.flags & EBOF_WARM_START)) ? s.flow[s.cur] : nullptr;
+            // (the coarsest search level reads the previous flow before the
+            // densification overwrites it: one buffer serves both)
+            w.flow_dense_out = (warm && s.has_prev) ? s.flow : nullptr;
+            w.flow_init = (warm && s.has_prev && s.has_flow) ? s.flow : nullptr;
             ext[i].mask_out = q.mask_out;
             ext[i].zero_out = !s.has_prev;
-            scr[i] = &s.scr;
+            scr[i] = &s.scr[s.scr_next];
+            s.scr_next ^= 1;
             b.tickets.push_back(q.ticket);
             b.status.push_back(s.has_prev ? EBOF_OK : EBOF_NO_FLOW);
             b.sids.push_back(q.sid);
@@ -167,22 +184,42 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             s.has_prev = true;
             s.last_t0 = q.t0;
         }
+        // launched without the serving lock, so that submissions and polls
+        // are not held up behind the launches (this thread alone forms and
+        // launches batches, in order)
+        const int li = S->next_lane;
+        S->next_lane = (li + 1) % kLanes;
+        hipStream_t st = S->lane[li];
+        const hipEvent_t prev = S->last_done;
+        b.done = get_event(S);
+        S->last_done = b.done;
+        ++S->forming;
+        lk.unlock();
         // the batch's event copies were queued in order on the copy stream:
         // waiting for the last one covers all of them
         int rc = EBOF_OK;
         if (!b.copy_events.empty())
-            rc = check_hip(ctx, hipStreamWaitEvent(S->stream, b.copy_events.back(), 0), "hipStreamWaitEvent");
+            rc = check_hip(ctx, hipStreamWaitEvent(st, b.copy_events.back(), 0), "hipStreamWaitEvent");
+        // the flow stages after the previous batch (issued on the other
+        // lane), unless it has completed already
+        const std::function<int(hipStream_t)> after_prev = [&](hipStream_t s_) {
+            if (!prev || hipEventQuery(prev) == hipSuccess) return (int)EBOF_OK;
+            return check_hip(ctx, hipStreamWaitEvent(s_, prev, 0), "hipStreamWaitEvent");
+        };
         if (rc == EBOF_OK) {
             std::lock_guard<std::mutex> g(ctx->mu);
-            rc = run_batch_impl(ctx, S->runner, win.data(), ext.data(), n, S->stream, scr.data(), kGraphUniversal);
+            rc = run_batch_impl(ctx, S->runner[li], win.data(), ext.data(), n, st, scr.data(), kGraphUniversal,
+                                &after_prev);
         }
-        b.done = get_event(S);
-        if (rc == EBOF_OK && b.done) rc = check_hip(ctx, hipEventRecord(b.done, S->stream), "hipEventRecord");
-        if (rc != EBOF_OK) {
-            for (auto& st : b.status) st = rc;
+        if (rc == EBOF_OK && b.done) rc = check_hip(ctx, hipEventRecord(b.done, st), "hipEventRecord");
+        lk.lock();
+        if (rc != EBOF_OK || !b.done) {
+            if (rc == EBOF_OK) rc = EBOF_E_DEVICE;
+            for (auto& st_ : b.status) st_ = rc;
             S->error = rc;
         }
         S->inflight.push_back(std::move(b));
+        --S->forming;
         S->cv_done.notify_all();
     }
 }
@@ -224,7 +261,8 @@ static void reaper_loop(ServeState* S) {
 static int serve_init(ebof_ctx* ctx) {
     if (ctx->serve) return EBOF_OK;
     auto* S = new ServeState();
-    int rc = check_hip(ctx, hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "hipStreamCreate");
+    int rc = EBOF_OK;
+    for (int i = 0; i < kLanes && !rc; ++i) rc = queue_stream_create(ctx, &S->lane[i]);
     if (!rc) rc = check_hip(ctx, hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking), "hipStreamCreate");
     if (!rc) rc = check_hip(ctx, hipHostMalloc((void**)&S->pinned, kPinnedRing, hipHostMallocDefault), "hipHostMalloc");
     if (!rc) {
@@ -237,7 +275,8 @@ static int serve_init(ebof_ctx* ctx) {
         }
     }
     if (rc) {
-        if (S->stream) (void)hipStreamDestroy(S->stream);
+        for (hipStream_t l : S->lane)
+            if (l) (void)hipStreamDestroy(l);
         if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
         if (S->pinned) (void)hipHostFree(S->pinned);
         delete S;
@@ -256,19 +295,19 @@ void serve_shutdown(ebof_ctx* ctx) {
     if (!S) return;
     {
         std::unique_lock<std::mutex> lk(S->mu);
-        S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty(); });
+        S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty() && S->forming == 0; });
         S->stop = true;
     }
     S->cv_work.notify_all();
     S->cv_done.notify_all();
     S->former.join();
     S->reaper.join();
-    (void)hipStreamSynchronize(S->stream);
+    for (hipStream_t l : S->lane) (void)hipStreamSynchronize(l);
     (void)hipStreamSynchronize(S->copy_stream);
-    runner_release(S->runner);
+    for (BatchRunner& r : S->runner) runner_release(r);
     for (auto& pl : S->pin_live) (void)hipEventDestroy(pl.second);
     for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
-    (void)hipStreamDestroy(S->stream);
+    for (hipStream_t l : S->lane) (void)hipStreamDestroy(l);
     (void)hipStreamDestroy(S->copy_stream);
     (void)hipHostFree(S->pinned);
     delete S;
@@ -277,15 +316,15 @@ void serve_shutdown(ebof_ctx* ctx) {
 
 static void free_stream(ebof_ctx* ctx, ServeStream& s) {
     std::lock_guard<std::mutex> g(ctx->mu);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kPyrBufs; ++i) {
         ctx->arena.free(s.pyr[i]);
         ctx->arena.free(s.edge[i]);
-        ctx->arena.free(s.flow[i]);
         s.pyr[i] = nullptr;
         s.edge[i] = nullptr;
-        s.flow[i] = nullptr;
     }
-    scratch_free(ctx, &s.scr);
+    ctx->arena.free(s.flow);
+    s.flow = nullptr;
+    for (Scratch& sc : s.scr) scratch_free(ctx, &sc);
 }
 
 }  // namespace ebof
@@ -312,23 +351,29 @@ int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
         Lut lut;
         if ((rc = lut_for(ctx, p->alpha, p->surface, &lut))) return rc;
         const size_t N = (size_t)p->width * p->height;
+        const bool warm = (p->flags & EBOF_WARM_START) != 0;
         bool ok = true;
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < kPyrBufs; ++i) {
             s.pyr[i] = (float*)ctx->arena.alloc(s.g.pyr_floats * sizeof(float));
             s.edge[i] = (uint8_t*)ctx->arena.alloc(N);
-            s.flow[i] = (float*)ctx->arena.alloc(2 * N * sizeof(float));
-            ok = ok && s.pyr[i] && s.edge[i] && s.flow[i];
+            ok = ok && s.pyr[i] && s.edge[i];
         }
-        if (ok) ok = scratch_alloc(ctx, s.g, &s.scr, S->stream) == EBOF_OK;
+        if (warm) {
+            s.flow = (float*)ctx->arena.alloc(2 * N * sizeof(float));
+            ok = ok && s.flow;
+        }
+        for (Scratch& sc : s.scr)
+            if (ok) ok = scratch_alloc(ctx, s.g, &sc, nullptr) == EBOF_OK;
         if (!ok) {
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < kPyrBufs; ++i) {
                 ctx->arena.free(s.pyr[i]);
                 ctx->arena.free(s.edge[i]);
-                ctx->arena.free(s.flow[i]);
             }
-            scratch_free(ctx, &s.scr);
+            ctx->arena.free(s.flow);
+            for (Scratch& sc : s.scr) scratch_free(ctx, &sc);
             set_error("arena full: a %dx%d stream needs %zu bytes of resident state, %zu free", p->width, p->height,
-                      2 * (size_t)s.g.pyr_floats * 4 + 2 * N + 16 * N + (size_t)ebof_window_scratch_bytes(p),
+                      kPyrBufs * ((size_t)s.g.pyr_floats * 4 + N) + (warm ? 8 * N : 0) +
+                          2 * (size_t)ebof_window_scratch_bytes(p),
                       ctx->arena.bytes_free());
             return EBOF_E_NOMEM;
         }
@@ -482,7 +527,7 @@ int ebof_drain(ebof_ctx* ctx) {
     ServeState* S = ctx->serve;
     if (!S) return EBOF_OK;
     std::unique_lock<std::mutex> lk(S->mu);
-    S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty(); });
+    S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight.empty() && S->forming == 0; });
     return S->error;
 }
 

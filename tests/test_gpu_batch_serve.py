@@ -265,7 +265,8 @@ def _check_outs(streams, ref, outs, k, tag):
         assert torch.equal(o["flow"], r[3]), (tag, s, "flow")
 
 
-@pytest.mark.parametrize("rows, tile_w, lanes, grid", [(1, 256, 8, 256), (8, 128, 4, 0), (2, 64, 4, 4096)])
+@pytest.mark.parametrize("rows, tile_w, lanes, grid", [(1, 256, 8, 256), (8, 128, 4, 0), (2, 64, 4, 4096),
+                                                        (4, 16, 8, 0)])
 def test_batch_forced_launch_shapes_equal_alone(ctx, tmp_path, rows, tile_w, lanes, grid):
     """Every tile shape and block count the tuner can pick gives the stage
     calls' results: shapes forced through the tuning cache file."""
@@ -312,7 +313,7 @@ def test_autotune_cache_roundtrip(tmp_path):
             assert key == L.batch_layout_key(batch)
             v = [int(x) for x in vals.split()]
             assert len(v) == 2 + L.EBOF_TUNE_LEVELS + L.EBOF_TUNE_STAGES
-            assert v[0] in (1, 2, 4, 8) and v[1] in (64, 128, 256)
+            assert v[0] in (1, 2, 4, 8) and v[1] in (16, 64, 128, 256)
             assert all(x in (4, 8) for x in v[2:2 + L.EBOF_TUNE_LEVELS])
         finally:
             torch.cuda.synchronize()

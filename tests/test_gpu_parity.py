@@ -289,6 +289,9 @@ def test_flow_mask_vs_oracle(ctx):
     _say("flow masked")
     fm = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], mask=g0["_edge_dev"])
     m = r0["Edf"].astype(bool)
+    # pixels off the mask skip their sums: the same bits as masking the dense flow
+    fd = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
+    assert np.array_equal(fm, np.where(m[None], fd, 0.0))
     ref = OracleFlow(p, r0, r1, mask=True)
     assert np.all(fm[:, ~m] == 0.0)
     assert_flow_matches(fm, ref, "masked C1")
