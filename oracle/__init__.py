@@ -78,6 +78,9 @@ def _load():
     lib.oref_fwl.restype = f64
     lib.oref_window_end_area.argtypes = [i32, i32, P, P, i64, i64, i32, i32]
     lib.oref_window_end_area.restype = i64
+    lib.oref_var_refine.argtypes = [i32, i32, P, P, P, i32, i32, f64, f64, f64, f64]
+    lib.oref_dis_flow_refined.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P, P, P]
+    lib.oref_dis_flow_refined.restype = ctypes.c_int
     lib.oref_dis_flow.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P]
     lib.oref_dis_flow.restype = ctypes.c_int
     lib.oref_dis_flow_warm.argtypes = [i32, i32, i32, P, P, i32, i32, i32, f64, P, P, P]
@@ -253,12 +256,36 @@ def patch_count(W, H, ps=8, stride=4):
     return int(_load().oref_patch_count(W, H, ps, stride))
 
 
+class VarParams(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("inner", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("delta", ctypes.c_double), ("omega", ctypes.c_double)]
+
+
+# dense inverse search's usual refinement settings (5 fixed-point iterations
+# of 5 SOR sweeps, smoothness 20, gradient constancy 10, brightness 5, 1.6)
+VAR_DEFAULT = dict(outer=5, inner=5, alpha=20.0, gamma=10.0, delta=5.0, omega=1.6)
+
+
+def var_refine(I0, I1, U, outer=5, inner=5, alpha=20.0, gamma=10.0, delta=5.0, omega=1.6):
+    """Variational refinement of the dense flow U ([2,H,W], float64; a
+    refined copy is returned) between the level images I0 and I1."""
+    I0 = np.ascontiguousarray(I0, np.float32)
+    I1 = np.ascontiguousarray(I1, np.float32)
+    H, W = I0.shape
+    out = np.array(U, np.float64, copy=True, order="C")
+    assert out.shape == (2, H, W)
+    _load().oref_var_refine(W, H, _ptr(I0), _ptr(I1), _ptr(out), int(outer), int(inner), float(alpha),
+                            float(gamma), float(delta), float(omega))
+    return out
+
+
 def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=0.3,
-             want_patches=False, prev_flow=None):
+             want_patches=False, prev_flow=None, refine=None):
     """Dense inverse search flow from pyr0 (window k-1) to pyr1 (window k).
     Returns float64 [2,H,W] (u, v), and per-level patch flows if asked.
     prev_flow: None, or the previous pair's dense [2,H,W] flow, from which
-    the coarsest level starts (warm start)."""
+    the coarsest level starts (warm start).  refine: None, or a dict of
+    var_refine settings applied to every level's dense flow."""
     pyr0 = np.ascontiguousarray(pyr0, np.float32)
     pyr1 = np.ascontiguousarray(pyr1, np.float32)
     flow = np.empty((2, H, W), np.float64)
@@ -268,9 +295,13 @@ def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=0.3,
     if prev_flow is not None:
         warm = np.ascontiguousarray(prev_flow, np.float64)
         assert warm.shape == (2, H, W)
-    rc = _load().oref_dis_flow_warm(W, H, L, _ptr(pyr0), _ptr(pyr1), ps, stride,
-                                    iters, float(lam), _ptr(warm) if warm is not None else None,
-                                    _ptr(flow), _ptr(pu) if pu is not None else None)
+    vr = None
+    if refine is not None:
+        vr = VarParams(**{**VAR_DEFAULT, **refine})
+    rc = _load().oref_dis_flow_refined(W, H, L, _ptr(pyr0), _ptr(pyr1), ps, stride,
+                                       iters, float(lam), _ptr(warm) if warm is not None else None,
+                                       ctypes.byref(vr) if vr is not None else None,
+                                       _ptr(flow), _ptr(pu) if pu is not None else None)
     if rc != 0:
         raise ValueError("oref_dis_flow rejected its arguments")
     if want_patches:

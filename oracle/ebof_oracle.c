@@ -633,10 +633,179 @@ void oref_dis_level(int32_t W, int32_t H, const float *I0, const float *I1,
     free(T);
 }
 
-int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
-                       const float *pyr1, int32_t ps, int32_t stride,
-                       int32_t iters, double lambda, const double *prev_flow,
-                       double *flow, double *patch_uv)
+/* ------------------------------------------------------------------------ */
+/* Variational refinement of a dense flow (the third stage of dense inverse  */
+/* search): a few fixed-point iterations of the linearised robust energy     */
+/*   sum_x delta Psi(E_c) + gamma Psi(E_g) + alpha Psi(|grad(u)|^2 +          */
+/*         |grad(v)|^2),  Psi(s^2) = sqrt(s^2 + eps^2),                       */
+/* E_c the brightness-constancy and E_g the gradient-constancy residual of   */
+/* the flow increment, each solved by red-black block SOR.                   */
+/* ------------------------------------------------------------------------ */
+static double px_clamped(const double *f, int32_t W, int32_t H, int64_t x,
+                         int64_t y)
+{
+    if (x < 0)
+        x = 0;
+    if (x >= W)
+        x = W - 1;
+    if (y < 0)
+        y = 0;
+    if (y >= H)
+        y = H - 1;
+    return f[(size_t)y * W + x];
+}
+
+/* central differences along x and y, replicated border */
+static void grad(const double *f, int32_t W, int32_t H, double *fx, double *fy)
+{
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            size_t p = (size_t)y * W + x;
+            fx[p] = 0.5 * (px_clamped(f, W, H, x + 1, y) - px_clamped(f, W, H, x - 1, y));
+            fy[p] = 0.5 * (px_clamped(f, W, H, x, y + 1) - px_clamped(f, W, H, x, y - 1));
+        }
+}
+
+static double robust_weight(double s2)
+{
+    const double eps = 1e-3;
+    return 1.0 / sqrt(s2 + eps * eps);
+}
+
+void oref_var_refine(int32_t W, int32_t H, const float *I0f, const float *I1f,
+                     double *U, int32_t outer, int32_t inner, double alpha,
+                     double gamma, double delta, double omega)
+{
+    size_t N = (size_t)W * H;
+    /* images on the 8-bit scale the weights assume */
+    double *I0 = (double *)malloc(sizeof(double) * N);
+    double *I1w = (double *)malloc(sizeof(double) * N);
+    double *A = (double *)malloc(sizeof(double) * N);
+    double *d[14];
+    for (int i = 0; i < 14; i++)
+        d[i] = (double *)malloc(sizeof(double) * N);
+    double *gx0 = d[0], *gy0 = d[1], *gx1 = d[2], *gy1 = d[3];
+    double *Ix = d[4], *Iy = d[5], *Ixx = d[6], *Ixy = d[7], *Iyx = d[8], *Iyy = d[9];
+    double *du = d[10], *dv = d[11], *s = d[12], *tmp = d[13];
+    double *It = (double *)malloc(sizeof(double) * N);
+    double *Ixt = (double *)malloc(sizeof(double) * N);
+    double *Iyt = (double *)malloc(sizeof(double) * N);
+    double *a11 = (double *)malloc(sizeof(double) * N);
+    double *a12 = (double *)malloc(sizeof(double) * N);
+    double *a22 = (double *)malloc(sizeof(double) * N);
+    double *b1 = (double *)malloc(sizeof(double) * N);
+    double *b2 = (double *)malloc(sizeof(double) * N);
+    (void)tmp;
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            size_t p = (size_t)y * W + x;
+            I0[p] = 255.0 * (double)I0f[p];
+            I1w[p] = 255.0 * bilinear(I1f, W, H, x + U[p], y + U[N + p]);
+            A[p] = 0.5 * (I0[p] + I1w[p]);
+            It[p] = I1w[p] - I0[p];
+        }
+    /* first derivatives of both images and of their average, then the
+     * second derivatives of the average; the temporal change of the
+     * gradient is the warped image's gradient minus the reference's */
+    grad(I0, W, H, gx0, gy0);
+    grad(I1w, W, H, gx1, gy1);
+    grad(A, W, H, Ix, Iy);
+    grad(Ix, W, H, Ixx, Ixy);
+    grad(Iy, W, H, Iyx, Iyy);
+    for (size_t p = 0; p < N; p++) {
+        Ixt[p] = gx1[p] - gx0[p];
+        Iyt[p] = gy1[p] - gy0[p];
+        Ixy[p] = 0.5 * (Ixy[p] + Iyx[p]); /* the mixed derivative, symmetrised */
+        du[p] = 0.0;
+        dv[p] = 0.0;
+    }
+    for (int32_t o = 0; o < outer; o++) {
+        /* weights at the current increment (lagged) */
+        for (int32_t y = 0; y < H; y++)
+            for (int32_t x = 0; x < W; x++) {
+                size_t p = (size_t)y * W + x;
+                double c = It[p] + (Ix[p] * du[p] + Iy[p] * dv[p]);
+                double g1 = Ixt[p] + (Ixx[p] * du[p] + Ixy[p] * dv[p]);
+                double g2 = Iyt[p] + (Ixy[p] * du[p] + Iyy[p] * dv[p]);
+                double wc = delta * robust_weight(c * c);
+                double wg = gamma * robust_weight(g1 * g1 + g2 * g2);
+                a11[p] = wc * Ix[p] * Ix[p] + wg * (Ixx[p] * Ixx[p] + Ixy[p] * Ixy[p]);
+                a12[p] = wc * (Ix[p] * Iy[p]) + wg * (Ixx[p] * Ixy[p] + Ixy[p] * Iyy[p]);
+                a22[p] = wc * Iy[p] * Iy[p] + wg * (Ixy[p] * Ixy[p] + Iyy[p] * Iyy[p]);
+                b1[p] = wc * Ix[p] * It[p] + wg * (Ixx[p] * Ixt[p] + Ixy[p] * Iyt[p]);
+                b2[p] = wc * Iy[p] * It[p] + wg * (Ixy[p] * Ixt[p] + Iyy[p] * Iyt[p]);
+                /* smoothness weight of the total flow u + du, v + dv */
+                double ux = 0.5 * ((px_clamped(U, W, H, x + 1, y) + px_clamped(du, W, H, x + 1, y)) -
+                                   (px_clamped(U, W, H, x - 1, y) + px_clamped(du, W, H, x - 1, y)));
+                double uy = 0.5 * ((px_clamped(U, W, H, x, y + 1) + px_clamped(du, W, H, x, y + 1)) -
+                                   (px_clamped(U, W, H, x, y - 1) + px_clamped(du, W, H, x, y - 1)));
+                double vx = 0.5 * ((px_clamped(U + N, W, H, x + 1, y) + px_clamped(dv, W, H, x + 1, y)) -
+                                   (px_clamped(U + N, W, H, x - 1, y) + px_clamped(dv, W, H, x - 1, y)));
+                double vy = 0.5 * ((px_clamped(U + N, W, H, x, y + 1) + px_clamped(dv, W, H, x, y + 1)) -
+                                   (px_clamped(U + N, W, H, x, y - 1) + px_clamped(dv, W, H, x, y - 1)));
+                /* (summed so that swapping the axes, u and v, swaps nothing) */
+                s[p] = alpha * robust_weight((ux * ux + vy * vy) + (uy * uy + vx * vx));
+            }
+        /* red-black block SOR: pixels with x + y even, then odd; each solves
+         * its 2x2 system with the neighbours' current increments and relaxes
+         * towards the solution */
+        for (int32_t it = 0; it < inner; it++)
+            for (int32_t colour = 0; colour < 2; colour++)
+                for (int32_t y = 0; y < H; y++)
+                    for (int32_t x = 0; x < W; x++) {
+                        if (((x + y) & 1) != colour)
+                            continue;
+                        size_t p = (size_t)y * W + x;
+                        /* the four neighbours (absent ones weigh 0), added
+                         * as (left + right) + (up + down) */
+                        double w[4] = {0.0, 0.0, 0.0, 0.0}, tu[4] = {0.0, 0.0, 0.0, 0.0},
+                               tv[4] = {0.0, 0.0, 0.0, 0.0};
+                        const int32_t nx[4] = {x - 1, x + 1, x, x};
+                        const int32_t ny[4] = {y, y, y - 1, y + 1};
+                        for (int k = 0; k < 4; k++) {
+                            if (nx[k] < 0 || nx[k] >= W || ny[k] < 0 || ny[k] >= H)
+                                continue;
+                            size_t q = (size_t)ny[k] * W + nx[k];
+                            w[k] = 0.5 * (s[p] + s[q]);
+                            tu[k] = w[k] * ((U[q] - U[p]) + du[q]);
+                            tv[k] = w[k] * ((U[N + q] - U[N + p]) + dv[q]);
+                        }
+                        double sw = (w[0] + w[1]) + (w[2] + w[3]);
+                        double ru = (tu[0] + tu[1]) + (tu[2] + tu[3]);
+                        double rv = (tv[0] + tv[1]) + (tv[2] + tv[3]);
+                        double m11 = a11[p] + sw, m22 = a22[p] + sw, m12 = a12[p];
+                        double r1 = ru - b1[p], r2 = rv - b2[p];
+                        double det = m11 * m22 - m12 * m12;
+                        double su = (m22 * r1 - m12 * r2) / det;
+                        double sv = (m11 * r2 - m12 * r1) / det;
+                        du[p] = (1.0 - omega) * du[p] + omega * su;
+                        dv[p] = (1.0 - omega) * dv[p] + omega * sv;
+                    }
+    }
+    for (size_t p = 0; p < N; p++) {
+        U[p] += du[p];
+        U[N + p] += dv[p];
+    }
+    free(I0);
+    free(I1w);
+    free(A);
+    for (int i = 0; i < 14; i++)
+        free(d[i]);
+    free(It);
+    free(Ixt);
+    free(Iyt);
+    free(a11);
+    free(a12);
+    free(a22);
+    free(b1);
+    free(b2);
+}
+
+int oref_dis_flow_refined(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                          const float *pyr1, int32_t ps, int32_t stride,
+                          int32_t iters, double lambda,
+                          const double *prev_flow, const oref_var_params *vr,
+                          double *flow, double *patch_uv)
 {
     if (L < 1 || L > 16 || ps < 1 || stride < 1 || iters < 0)
         return -1;
@@ -675,6 +844,10 @@ int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
             memcpy(patch_uv + 2 * poff[l], pu, sizeof(double) * 2 * np);
         double *Ul = (double *)malloc(sizeof(double) * 2 * (size_t)Wl * Hl);
         oref_densify(Wl, Hl, pyr0 + loff[l], pyr1 + loff[l], ps, stride, pu, Ul);
+        if (vr)
+            oref_var_refine(Wl, Hl, pyr0 + loff[l], pyr1 + loff[l], Ul, vr->outer,
+                            vr->inner, vr->alpha, vr->gamma, vr->delta,
+                            vr->omega);
         free(Uc);
         Uc = Ul;
         free(u0);
@@ -683,6 +856,15 @@ int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
     memcpy(flow, Uc, sizeof(double) * 2 * (size_t)W * H);
     free(Uc);
     return 0;
+}
+
+int oref_dis_flow_warm(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                       const float *pyr1, int32_t ps, int32_t stride,
+                       int32_t iters, double lambda, const double *prev_flow,
+                       double *flow, double *patch_uv)
+{
+    return oref_dis_flow_refined(W, H, L, pyr0, pyr1, ps, stride, iters,
+                                 lambda, prev_flow, NULL, flow, patch_uv);
 }
 
 int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,

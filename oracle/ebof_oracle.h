@@ -152,6 +152,35 @@ void oref_dis_level(int32_t W, int32_t H, const float *I0, const float *I1,
 void oref_densify(int32_t W, int32_t H, const float *I0, const float *I1,
                   int32_t ps, int32_t stride, const double *pu, double *U);
 
+/* Variational refinement (the third stage of dense inverse search) of a
+ * dense flow U (2*W*H doubles, in/out) between I0 and I1 (W x H floats, the
+ * [0,1] surfaces taken on the 8-bit scale, x255): `outer` fixed-point
+ * iterations, each weighting the linearised brightness-constancy residual
+ * It + Ix du + Iy dv (weight delta), the gradient-constancy residuals
+ * Ixt + Ixx du + Ixy dv and Iyt + Ixy du + Iyy dv (weight gamma) and the
+ * smoothness of the refined flow (weight alpha) by the robust penalty's
+ * derivative 1 / sqrt(s^2 + 1e-6) at the current increment, then `inner`
+ * red-black block SOR sweeps (relaxation omega) on the 2x2 systems of the
+ * increment; finally U += (du, dv).  Derivatives: central differences with
+ * replicated border, Ix, Iy, Ixx, Iyy, Ixy (symmetrised) of the average of
+ * I0 and the warped I1(x + U) (bilinear, replicated border), It = I1w - I0,
+ * Ixt, Iyt = the warped image's gradient minus the reference's. */
+typedef struct {
+    int32_t outer, inner;
+    double alpha, gamma, delta, omega;
+} oref_var_params;
+void oref_var_refine(int32_t W, int32_t H, const float *I0, const float *I1,
+                     double *U, int32_t outer, int32_t inner, double alpha,
+                     double gamma, double delta, double omega);
+
+/* oref_dis_flow_warm with the refinement applied to each level's dense flow
+ * before it starts the next level (vr NULL: no refinement). */
+int oref_dis_flow_refined(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                          const float *pyr1, int32_t ps, int32_t stride,
+                          int32_t iters, double lambda,
+                          const double *prev_flow, const oref_var_params *vr,
+                          double *flow, double *patch_uv);
+
 /* Number of patches of one level: ceil((W-ps)/stride)+1 by the same in y. */
 int64_t oref_patch_count(int32_t W, int32_t H, int32_t ps, int32_t stride);
 
