@@ -68,6 +68,10 @@ extern "C" {
 #define EBOF_WARM_START 4u  /* served stream: the coarsest level starts from
                                 the stream's previous flow (kept resident),
                                 as ebof_flow_warm does, instead of from 0   */
+#define EBOF_VAR_REFINE 8u  /* stage calls (ebof_flow, ebof_flow_warm): each
+                                level's dense flow is refined variationally
+                                before the next level starts (the third stage
+                                of dense inverse search; see ebof_flow)      */
 
 typedef struct ebof_ctx ebof_ctx; /* opaque, library-owned */
 
@@ -85,7 +89,8 @@ typedef struct {
     int32_t stride;        /* patch grid stride, 1..8                        */
     int32_t iters;         /* inverse-search iterations per patch, 0..1024   */
     float lambda_reg;      /* Tikhonov term added to the patch Hessian, > 0  */
-    uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START */
+    uint32_t flags;        /* EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START
+                              | EBOF_VAR_REFINE */
     int32_t surface;       /* EBOF_SURFACE_*: the distance surface (Sec. IV-B) */
 } ebof_params;
 
@@ -223,7 +228,20 @@ int ebof_window_surface_range(ebof_ctx *ctx, const ebof_params *p,
  * from twice the coarser level's flow at the pixel nearest its centre, from 0
  * at the coarsest level.  flow_out: device 2*width*height floats.  mask: NULL,
  * or device width*height bytes (the edge image of window k-1); with
- * EBOF_MASK_FLOW set the flow is written as 0 where the mask is 0. */
+ * EBOF_MASK_FLOW set the flow is written as 0 where the mask is 0.
+ * With EBOF_VAR_REFINE, each level's dense flow (the densification at every
+ * pixel) is refined before the next level starts from it (at the pixel
+ * nearest a patch centre, doubled): 5 fixed-point iterations, each weighting
+ * the linearised brightness-constancy residual (weight 5), the
+ * gradient-constancy residuals (weight 10) and the refined flow's smoothness
+ * (weight 20) by the robust penalty's derivative 1 / sqrt(s^2 + 1e-6) at the
+ * current increment, then 5 red-black block SOR sweeps (relaxation 1.6) of
+ * the per-pixel 2x2 systems; images on the 8-bit scale (x255), derivatives
+ * by central differences with replicated border (Ix, Iy, Ixx, Ixy, Iyy of the
+ * average of the reference and the warped image, It and the gradient change
+ * between them), in double precision.  The context then also holds 18
+ * doubles per pixel of scratch and the dense flow of every level.  Stage calls only: batched and
+ * served windows with EBOF_VAR_REFINE are refused (EBOF_E_INVAL). */
 int ebof_flow(ebof_ctx *ctx, const ebof_params *p, const float *pyr_prev,
               const float *pyr_curr, const uint8_t *mask, float *flow_out,
               void *hip_stream);

@@ -27,6 +27,7 @@ EBOF_E_STATE = -6
 EBOF_MASK_FLOW = 1
 EBOF_CHAIN_ALWAYS = 2
 EBOF_WARM_START = 4
+EBOF_VAR_REFINE = 8
 EBOF_SURFACE_EXP, EBOF_SURFACE_LINEAR, EBOF_SURFACE_BOUNDED, EBOF_SURFACE_LOG = 0, 1, 2, 3
 EBOF_MAX_BATCH = 1024
 EBOF_TUNE_OFF = 0

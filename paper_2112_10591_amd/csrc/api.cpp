@@ -111,7 +111,7 @@ static int validate(const ebof_params* p) {
         set_error("surface %d is not one of EBOF_SURFACE_*", p->surface);
         return EBOF_E_INVAL;
     }
-    if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START)) {
+    if (p->flags & ~(EBOF_MASK_FLOW | EBOF_CHAIN_ALWAYS | EBOF_WARM_START | EBOF_VAR_REFINE)) {
         set_error("unknown flags 0x%x", p->flags);
         return EBOF_E_INVAL;
     }
@@ -213,6 +213,8 @@ int scratch_alloc(ebof_ctx* ctx, const Geom& g, Scratch* s, hipStream_t) {
 }
 
 void scratch_free(ebof_ctx* ctx, Scratch* s) {
+    ctx->arena.free(s->var);
+    ctx->arena.free(s->ud);
     ctx->arena.free(s->e_raw);
     ctx->arena.free(s->colmask);
     ctx->arena.free(s->g);
@@ -638,6 +640,10 @@ int run_batch_impl(ebof_ctx* ctx, BatchRunner& br, const ebof_window* w, const W
     for (int32_t i = 0; i < n; ++i) {
         int rc = validate(w[i].params);
         if (rc) return rc;
+        if (w[i].params->flags & EBOF_VAR_REFINE) {
+            set_error("window %d: the variational refinement runs in the stage calls only", i);
+            return EBOF_E_INVAL;
+        }
         const bool zero_out = extra && extra[i].zero_out;
         if (w[i].n < 0 || (w[i].n > 0 && (!w[i].x || !w[i].y || !w[i].t)) || !w[i].edge_out || !w[i].pyr_out ||
             ((w[i].pyr_prev || zero_out) && !w[i].flow_out)) {
@@ -1129,9 +1135,24 @@ int ebof_window_surface(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, 
 
 // The inverse search, level by level, and the densification of window
 // descriptor d (timed per kernel when ctx has timing on).
-static void flow_launches(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d, hipStream_t st) {
+static void flow_launches(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d, hipStream_t st,
+                          double* var = nullptr) {
     Tune tune = kStageTune;
     resolve_dis_lanes(tune, &d, 1);
+    if (var) {  // each level refined before the next starts from it
+        for (int l = p->levels - 1; l >= 0; --l) {
+            auto dis = [&] {
+                launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l,
+                                 tune.dis_lanes[l]);
+            };
+            if (ctx)
+                timed(ctx, EBOF_K_DIS_LEVEL, st, dis);
+            else
+                dis();
+            launch_var_level(d, l, var, st);
+        }
+        return;
+    }
     auto dis = [&] {
         for (int l = p->levels - 1; l >= 0; --l)
             launch_dis_level(one_launch(&d, stage_items(d, kStDis + l, true, false, tune), st), l, tune.dis_lanes[l]);
@@ -1186,11 +1207,27 @@ int ebof_flow_warm(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, c
     }
     hipStream_t st = (hipStream_t)hip_stream;
     const Geom g = make_geom(*p);
+    const bool refine = (p->flags & EBOF_VAR_REFINE) != 0;
+    const size_t N0 = (size_t)g.W * g.H;
     Scratch scr;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         Scratch* s = stage_scratch(ctx, g, st, &rc);
         if (!s) return rc;
+        if (refine && !s->var) {
+            const size_t bv = (size_t)kVarScratchPerPixel * N0 * sizeof(double);
+            const size_t bu = 2 * (size_t)g.pyr_floats * sizeof(float);
+            s->var = (double*)ctx->arena.alloc(bv);
+            s->ud = (float*)ctx->arena.alloc(bu);
+            if (!s->var || !s->ud) {
+                ctx->arena.free(s->var);
+                ctx->arena.free(s->ud);
+                s->var = nullptr;
+                s->ud = nullptr;
+                set_error("arena full: variational refinement needs %zu bytes", bv + bu);
+                return EBOF_E_NOMEM;
+            }
+        }
         scr = *s;
     }
     Lut lut{p->alpha, p->surface, 0, 1.0f, nullptr};
@@ -1202,7 +1239,8 @@ int ebof_flow_warm(ebof_ctx* ctx, const ebof_params* p, const float* pyr_prev, c
     d.flow = flow_out;
     d.flow_init = flow_init;
     d.flow_keep = flow_dense_out;
-    flow_launches(ctx, p, d, st);
+    if (refine) d.ud = scr.ud;
+    flow_launches(ctx, p, d, st, refine ? scr.var : nullptr);
     return launch_status(ctx);
 }
 
@@ -1215,6 +1253,10 @@ int ebof_flow_noalloc(const ebof_params* p, const float* pyr_prev, const float* 
         return EBOF_E_INVAL;
     }
     const Geom g = make_geom(*p);
+    if (p->flags & EBOF_VAR_REFINE) {
+        set_error("ebof_flow_noalloc: the variational refinement needs scratch (use ebof_flow)");
+        return EBOF_E_INVAL;
+    }
     if (g.patches > kNoAllocPatches) {
         set_error("ebof_flow_noalloc: %lld patches exceed the fixed scratch of %lld", (long long)g.patches,
                   (long long)kNoAllocPatches);

@@ -40,6 +40,8 @@ struct Scratch {
     uint64_t* colmask = nullptr;
     uint16_t* g = nullptr;
     float2* puv = nullptr;
+    double* var = nullptr;  // variational refinement: working planes (allocated on first use)
+    float* ud = nullptr;    // ... and every level's refined dense flow
     uint32_t stamp = 0;
     bool needs_zero = true;
     // next stamp; sets needs_zero when the counter wraps

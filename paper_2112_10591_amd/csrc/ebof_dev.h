@@ -82,6 +82,8 @@ struct WinDesc {
     const float* flow_init; // level-0 flow of the previous pair (2*W*H): the
                             // coarsest level's start, or null (start at 0)
     float* flow_keep;       // 2*W*H copy of the flow before masking, or null
+    float* ud;              // variational refinement: every level's refined dense flow
+                            // (level l's u and v planes at 2 * lv[l].off), or null
     unsigned long long* n_dropped;  // optional counter
     LevelGeom lv[kMaxLevels];
 };
@@ -173,6 +175,9 @@ void launch_edt_rows(const Launch& L, int rows_nr);
 void launch_pyr_chain(const Launch& L, int from);
 void launch_dis_level(const Launch& L, int level, int lanes);
 void launch_densify(const Launch& L, int tile_w);
+// variational refinement of level l (single window, after its inverse search)
+void launch_var_level(const WinDesc& d, int l, double* scratch, hipStream_t st);
+constexpr int kVarScratchPerPixel = 18;  // doubles per level-0 pixel
 
 // Device address, on the current HIP device, of the fixed patch-displacement
 // array of the allocation-free flow call (kNoAllocPatches float2); looked up

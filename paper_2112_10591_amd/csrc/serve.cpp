@@ -341,6 +341,10 @@ int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
     if (ctx->failed) return EBOF_E_DEVICE;
     int rc = validate_params(p);
     if (rc) return rc;
+    if (p->flags & EBOF_VAR_REFINE) {
+        set_error("ebof_stream_open: the variational refinement runs in the stage calls only");
+        return EBOF_E_INVAL;
+    }
     if ((rc = serve_init(ctx))) return rc;
     ServeState* S = ctx->serve;
     ServeStream s;

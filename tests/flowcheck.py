@@ -90,8 +90,11 @@ def ref_window(p, ev):
 
 
 def oracle_flow(p, r0, r1, prev_flow=None):
+    """The oracle's flow for parameters p (with the variational refinement
+    when p asks for it)."""
+    refine = {} if p.flags & 8 else None  # EBOF_VAR_REFINE: the library's settings are the oracle's defaults
     return oracle.dis_flow(r0["pyr"], r1["pyr"], p.width, p.height, p.levels, stride=p.stride, iters=p.iters,
-                           lam=float(np.float32(p.lambda_reg)), prev_flow=prev_flow)
+                           lam=float(np.float32(p.lambda_reg)), prev_flow=prev_flow, refine=refine)
 
 
 def masked(r0, flow):

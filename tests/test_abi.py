@@ -40,7 +40,7 @@ def test_params_default_follow_paper_settings():
     ("width", 7), ("width", 8193), ("height", 0), ("levels", 0), ("levels", 9), ("n_d", -1),
     ("n_f", 6), ("alpha", 0.0), ("alpha", float("nan")), ("alpha", 1000.0), ("patch", 16),
     ("stride", 0), ("stride", 9), ("iters", -1), ("iters", 2000), ("lambda_reg", 0.0),
-    ("dt_us", 0), ("flags", 8), ("struct_size", 12)])
+    ("dt_us", 0), ("flags", 16), ("struct_size", 12)])
 def test_validate_rejects(field, value):
     p = L.ebof_params_default(346, 260)
     setattr(p, field, value)

@@ -411,3 +411,45 @@ def test_flow_on_bounded_surface_vs_oracle(ctx):
     f = gpu_flow(ctx, p, gs[0]["_pyr_dev"], gs[1]["_pyr_dev"])
     d_sat = float(np.float32(p.alpha)) * np.log(255.0)
     assert_flow_matches(f, OracleFlow(p, rs[0], rs[1]), "C1 DS_LB", scale=d_sat)
+
+
+# --------------------------------------------------------------------------
+# variational refinement of every level (the third stage of dense inverse
+# search)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", ["c1", "c2", "odd"])
+def test_flow_variational_refinement_vs_oracle(ctx, cfg):
+    """EBOF_VAR_REFINE: every level's dense flow refined before the next
+    starts from it, against the oracle's refined flow; masked output equal to
+    the masked dense copy; the refinement changes the flow."""
+    if cfg == "odd":
+        W, H = 130, 66
+        p = L.ebof_params_default(W, H, levels=2, stride=3, n_d=0, n_f=5,
+                                  flags=L.EBOF_VAR_REFINE | L.EBOF_MASK_FLOW)
+        evs = [random_events(W, H, W * H // 6, 31), random_events(W, H, W * H // 6, 32)]
+    else:
+        s = synth.c1_stream(0) if cfg == "c1" else synth.c2_stream(0)
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_VAR_REFINE | L.EBOF_MASK_FLOW)
+        evs = [s.window(k) for k in (0, 1)]
+    W, H = p.width, p.height
+    (g0, r0), (g1, r1) = windows_gpu_and_oracle(ctx, p, evs)
+    _say(f"refined flow {cfg} ({W}x{H}, L{p.levels})")
+    f = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    dense = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    L.ebof_flow_warm(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], f, flow_dense_out=dense, mask=g0["_edge_dev"])
+    plain = L.ebof_params_default(W, H, levels=p.levels, stride=p.stride, n_d=p.n_d, n_f=p.n_f)
+    fp = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    L.ebof_flow(ctx, plain, g0["_pyr_dev"], g1["_pyr_dev"], fp)
+    torch.cuda.synchronize()
+    f, dense, fp = (a.cpu().numpy().reshape(2, H, W).astype(np.float64) for a in (f, dense, fp))
+    m = r0["Edf"].astype(bool)
+    assert np.array_equal(f, np.where(m[None], dense, 0.0))
+    assert_flow_matches(dense, OracleFlow(p, r0, r1), f"refined {cfg}")
+    assert np.abs(dense - fp).max() > 1e-3, "the refinement changed nothing"
+
+
+def test_variational_refinement_refused_outside_stage_calls(ctx):
+    p = L.ebof_params_default(346, 260, flags=L.EBOF_VAR_REFINE)
+    with pytest.raises(L.EbofError) as ei:
+        L.ebof_stream_open(ctx, p)
+    assert ei.value.code == L.EBOF_E_INVAL
