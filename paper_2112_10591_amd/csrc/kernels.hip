@@ -723,6 +723,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int kx_last = min(kx0 + kPatchesPerItem, pnx) - 1;
         const int ky = ky0 + prow, kx = kx0 + slot;
         const bool valid = kx < pnx && ky < pny;
+        // When only the masked flow is wanted, a level-0 item with no pixel
+        // on the mask is not needed: a pixel's flow reads only the patches
+        // that contain it, and the densification skips pixels off the mask.
+        if (level == 0 && (d->flags & EBOF_MASK_FLOW) && d->mask && !d->flow_keep && !d->ud) {
+            const int fx0 = min(kx0 * s, Wl - kPatch), fx1 = min(kx_last * s, Wl - kPatch) + kPatch;
+            const int fy0 = min(ky0 * s, Hl - kPatch), fy1 = min(ky_last * s, Hl - kPatch) + kPatch;
+            const int fw = fx1 - fx0, fn = fw * (fy1 - fy0);
+            int any = 0;
+            for (int i = threadIdx.x; i < fn; i += kBlock) {
+                const int r = i / fw;
+                any |= d->mask[(size_t)(fy0 + r) * Wl + fx0 + (i - r * fw)];
+            }
+            if (!__syncthreads_or(any)) continue;
+        }
         const int kxc = min(kx, kx_last), kyc = min(ky, ky_last);
         const int ox = min(kxc * s, Wl - kPatch), oy = min(kyc * s, Hl - kPatch);
         const int x = ox + cg * CPL;  // the lane's first column
