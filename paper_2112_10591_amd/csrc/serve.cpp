@@ -12,11 +12,14 @@
 // every batch: the preprocessing stages, then the flow stages) on that lane's
 // HIP stream.  Batches alternate between two lanes: a batch's preprocessing
 // runs while the previous batch's flow does, and its flow stages wait for the
-// previous batch to complete (a stream's window k+1 reads window k's pyramid
-// and follows its flow).  Three pyramid buffers per stream keep the windows
-// being written and read apart: window k+1's preprocessing writes the buffer
-// that neither window k's flow nor its own reads.  A completion thread waits
-// for each batch (they complete in order) and timestamps its windows.
+// previous batch's preprocessing (a stream's window k+1 reads window k's
+// pyramid), or for all of it when a window starts from its stream's previous
+// flow; a lane's own batches are ordered by its stream, so that covers every
+// earlier batch.  Three pyramid buffers per stream keep the windows being
+// written and read apart: window k+1's preprocessing writes the buffer that
+// neither window k's flow nor its own reads; consecutive windows use the
+// stream's two scratches in turn.  A completion thread waits for the batches
+// in the order they were issued and timestamps their windows.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -78,6 +81,8 @@ struct TicketInfo {
 
 struct Batch {
     hipEvent_t done = nullptr;
+    hipEvent_t pre_done = nullptr;  // its preprocessing (pyramids) complete
+    bool warm = false;              // a window starts from its stream's previous flow
     std::vector<uint64_t> tickets;
     std::vector<int32_t> status;
     std::vector<int32_t> sids;
@@ -108,6 +113,7 @@ struct ServeState {
     BatchRunner runner[kLanes];
     int next_lane = 0;
     hipEvent_t last_done = nullptr;  // completion of the newest batch issued
+    hipEvent_t last_pre = nullptr;   // ... and of its preprocessing
     int forming = 0;                 // batches taken from the queue, not yet in flight
     int32_t error = EBOF_OK;
 };
@@ -170,6 +176,7 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             // densification overwrites it: one buffer serves both)
             w.flow_dense_out = (warm && s.has_prev) ? s.flow : nullptr;
             w.flow_init = (warm && s.has_prev && s.has_flow) ? s.flow : nullptr;
+            b.warm = b.warm || w.flow_init != nullptr;
             ext[i].mask_out = q.mask_out;
             ext[i].zero_out = !s.has_prev;
             scr[i] = &s.scr[s.scr_next];
@@ -190,9 +197,14 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
         const int li = S->next_lane;
         S->next_lane = (li + 1) % kLanes;
         hipStream_t st = S->lane[li];
-        const hipEvent_t prev = S->last_done;
+        // The flow stages read the pyramids the previous batch wrote, and a
+        // warm start reads the flows it wrote: they wait for its
+        // preprocessing, or for all of it (the other lane's work).
+        const hipEvent_t prev = b.warm ? S->last_done : S->last_pre;
         b.done = get_event(S);
+        b.pre_done = get_event(S);
         S->last_done = b.done;
+        S->last_pre = b.pre_done;
         ++S->forming;
         lk.unlock();
         // the batch's event copies were queued in order on the copy stream:
@@ -200,10 +212,12 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
         int rc = EBOF_OK;
         if (!b.copy_events.empty())
             rc = check_hip(ctx, hipStreamWaitEvent(st, b.copy_events.back(), 0), "hipStreamWaitEvent");
-        // the flow stages after the previous batch (issued on the other
-        // lane), unless it has completed already
+        // between this batch's preprocessing and its flow stages: mark the
+        // preprocessing done, then wait for the previous batch's part this
+        // flow reads (unless that has completed already)
         const std::function<int(hipStream_t)> after_prev = [&](hipStream_t s_) {
-            if (!prev || hipEventQuery(prev) == hipSuccess) return (int)EBOF_OK;
+            int r = b.pre_done ? check_hip(ctx, hipEventRecord(b.pre_done, s_), "hipEventRecord") : EBOF_OK;
+            if (r || !prev || hipEventQuery(prev) == hipSuccess) return r;
             return check_hip(ctx, hipStreamWaitEvent(s_, prev, 0), "hipStreamWaitEvent");
         };
         if (rc == EBOF_OK) {
@@ -213,7 +227,7 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
         }
         if (rc == EBOF_OK && b.done) rc = check_hip(ctx, hipEventRecord(b.done, st), "hipEventRecord");
         lk.lock();
-        if (rc != EBOF_OK || !b.done) {
+        if (rc != EBOF_OK || !b.done || !b.pre_done) {
             if (rc == EBOF_OK) rc = EBOF_E_DEVICE;
             for (auto& st_ : b.status) st_ = rc;
             S->error = rc;
@@ -252,6 +266,7 @@ static void reaper_loop(ServeState* S) {
         for (size_t off : b.dev_offs) S->dev_ring_alloc.release(off);
         for (hipEvent_t e : b.copy_events) S->event_pool.push_back(e);
         if (b.done) S->event_pool.push_back(b.done);
+        if (b.pre_done) S->event_pool.push_back(b.pre_done);
         if (failed) S->error = EBOF_E_DEVICE;
         S->cv_work.notify_all();
         S->cv_done.notify_all();
