@@ -1,25 +1,25 @@
 // serve.cpp -- serving runtime.
 //
 // A served stream keeps its recent windows' pyramids and edge images
-// resident in the arena (three of each, in turn), two preprocessing scratches
-// (in turn) and, with EBOF_WARM_START, its previous flow before masking;
-// opening a stream is admitted only while the arena can hold that state.
-// Submitted windows are queued; their host events are copied into a pinned
-// ring and sent asynchronously (copy stream) into a device ring in the arena.
-// A batch-former thread takes whatever is queued (at most one window per
-// stream per batch, in submission order) as soon as a compute lane is free,
-// and runs it as one launch per stage (two captured graphs, replayed for
-// every batch: the preprocessing stages, then the flow stages) on that lane's
-// HIP stream.  Batches alternate between two lanes: a batch's preprocessing
-// runs while the previous batch's flow does, and its flow stages wait for the
-// previous batch's preprocessing (a stream's window k+1 reads window k's
-// pyramid), or for all of it when a window starts from its stream's previous
-// flow; a lane's own batches are ordered by its stream, so that covers every
-// earlier batch.  Three pyramid buffers per stream keep the windows being
-// written and read apart: window k+1's preprocessing writes the buffer that
-// neither window k's flow nor its own reads; consecutive windows use the
-// stream's two scratches in turn.  A completion thread waits for the batches
-// in the order they were issued and timestamps their windows.
+// resident in the arena (one more than the compute lanes, in turn), one
+// scratch per lane (in turn) and, with EBOF_WARM_START, its previous flow
+// before masking; opening a stream is admitted only while the arena can hold
+// that state.  Submitted windows are queued; their host events are copied
+// into a pinned ring and sent asynchronously (copy stream) into a device ring
+// in the arena.  A batch-former thread takes whatever is queued (at most one
+// window per stream per batch, in submission order) as soon as a compute
+// lane is free, and runs it as one launch per stage (two captured graphs,
+// replayed for every batch: the preprocessing stages, then the flow stages)
+// on that lane's HIP stream.  Batches go to the lanes in turn and overlap:
+// a batch's flow stages wait only for the newest batch of every other lane
+// to finish its preprocessing (a stream's window k+1 reads window k's
+// pyramid), or to finish entirely when a window starts from its stream's
+// previous flow; a lane's own batches are ordered by its stream, so that
+// covers every earlier batch.  Up to one window per lane of a stream is in
+// flight at once, so lanes + 1 pyramid buffers keep what a window's
+// preprocessing writes apart from what earlier windows' flows read.  A
+// completion thread waits for the batches in the order they were issued and
+// timestamps their windows.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -34,9 +34,12 @@ static int64_t now_ns() {
         .count();
 }
 
-constexpr int kLanes = 2;             // compute streams; batches alternate between them
+constexpr int kLanes = 3;             // compute streams; batches go to them in turn
 constexpr int kMaxInflight = kLanes;  // batches on the GPU at once
-constexpr int kPyrBufs = 3;           // resident pyramids and edge images per stream
+// Batches of different lanes overlap (up to kLanes in flight), so a stream's
+// window k+j (j < kLanes) may be preprocessed while window k's flow runs:
+// kLanes + 1 resident pyramids and edge images, kLanes scratches.
+constexpr int kPyrBufs = kLanes + 1;
 constexpr int kServeMaxBatch = 256;   // windows per batch
 constexpr size_t kPinnedRing = size_t(128) << 20;
 constexpr size_t kDevRingMax = size_t(1) << 30;
@@ -46,7 +49,7 @@ static size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 struct ServeStream {
     ebof_params p;
     Geom g;
-    Scratch scr[2];  // preprocessing scratch of consecutive windows, in turn
+    Scratch scr[kLanes];  // scratch of consecutive windows, in turn
     int scr_next = 0;
     float* pyr[kPyrBufs] = {};
     uint8_t* edge[kPyrBufs] = {};
@@ -112,8 +115,8 @@ struct ServeState {
     hipStream_t lane[kLanes] = {};
     BatchRunner runner[kLanes];
     int next_lane = 0;
-    hipEvent_t last_done = nullptr;  // completion of the newest batch issued
-    hipEvent_t last_pre = nullptr;   // ... and of its preprocessing
+    hipEvent_t lane_done[kLanes] = {};  // completion of each lane's newest batch
+    hipEvent_t lane_pre[kLanes] = {};   // ... and of its preprocessing
     int forming = 0;                 // batches taken from the queue, not yet in flight
     int32_t error = EBOF_OK;
 };
@@ -180,7 +183,7 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
             ext[i].mask_out = q.mask_out;
             ext[i].zero_out = !s.has_prev;
             scr[i] = &s.scr[s.scr_next];
-            s.scr_next ^= 1;
+            s.scr_next = (s.scr_next + 1) % kLanes;
             b.tickets.push_back(q.ticket);
             b.status.push_back(s.has_prev ? EBOF_OK : EBOF_NO_FLOW);
             b.sids.push_back(q.sid);
@@ -197,14 +200,18 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
         const int li = S->next_lane;
         S->next_lane = (li + 1) % kLanes;
         hipStream_t st = S->lane[li];
-        // The flow stages read the pyramids the previous batch wrote, and a
-        // warm start reads the flows it wrote: they wait for its
-        // preprocessing, or for all of it (the other lane's work).
-        const hipEvent_t prev = b.warm ? S->last_done : S->last_pre;
+        // The flow stages read pyramids that earlier batches wrote, and a
+        // warm start the flows they wrote: they wait for the newest batch of
+        // every other lane, its preprocessing or all of it (a lane's older
+        // batches precede it on its stream).
+        std::vector<hipEvent_t> prev;
+        for (int x = 0; x < kLanes; ++x)
+            if (x != li && (b.warm ? S->lane_done[x] : S->lane_pre[x]))
+                prev.push_back(b.warm ? S->lane_done[x] : S->lane_pre[x]);
         b.done = get_event(S);
         b.pre_done = get_event(S);
-        S->last_done = b.done;
-        S->last_pre = b.pre_done;
+        S->lane_done[li] = b.done;
+        S->lane_pre[li] = b.pre_done;
         ++S->forming;
         lk.unlock();
         // the batch's event copies were queued in order on the copy stream:
@@ -217,8 +224,10 @@ static void former_loop(ebof_ctx* ctx, ServeState* S) {
         // flow reads (unless that has completed already)
         const std::function<int(hipStream_t)> after_prev = [&](hipStream_t s_) {
             int r = b.pre_done ? check_hip(ctx, hipEventRecord(b.pre_done, s_), "hipEventRecord") : EBOF_OK;
-            if (r || !prev || hipEventQuery(prev) == hipSuccess) return r;
-            return check_hip(ctx, hipStreamWaitEvent(s_, prev, 0), "hipStreamWaitEvent");
+            for (hipEvent_t e : prev)
+                if (!r && hipEventQuery(e) != hipSuccess)
+                    r = check_hip(ctx, hipStreamWaitEvent(s_, e, 0), "hipStreamWaitEvent");
+            return r;
         };
         if (rc == EBOF_OK) {
             std::lock_guard<std::mutex> g(ctx->mu);
@@ -265,6 +274,12 @@ static void reaper_loop(ServeState* S) {
         }
         for (size_t off : b.dev_offs) S->dev_ring_alloc.release(off);
         for (hipEvent_t e : b.copy_events) S->event_pool.push_back(e);
+        // (a completed batch needs no more waiting on: its events go back to
+        // the pool, and the lanes forget them)
+        for (int x = 0; x < kLanes; ++x) {
+            if (S->lane_done[x] == b.done) S->lane_done[x] = nullptr;
+            if (S->lane_pre[x] == b.pre_done) S->lane_pre[x] = nullptr;
+        }
         if (b.done) S->event_pool.push_back(b.done);
         if (b.pre_done) S->event_pool.push_back(b.pre_done);
         if (failed) S->error = EBOF_E_DEVICE;
@@ -392,7 +407,7 @@ int ebof_stream_open(ebof_ctx* ctx, const ebof_params* p, int32_t* stream_id) {
             for (Scratch& sc : s.scr) scratch_free(ctx, &sc);
             set_error("arena full: a %dx%d stream needs %zu bytes of resident state, %zu free", p->width, p->height,
                       kPyrBufs * ((size_t)s.g.pyr_floats * 4 + N) + (warm ? 8 * N : 0) +
-                          2 * (size_t)ebof_window_scratch_bytes(p),
+                          kLanes * (size_t)ebof_window_scratch_bytes(p),
                       ctx->arena.bytes_free());
             return EBOF_E_NOMEM;
         }
