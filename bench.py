@@ -209,8 +209,8 @@ def summarize_traffic(fetch_dir, write_dir):
         b = (f_ * ff + w_ * wf) * 1024
         rec["kernels"][k] = {"dispatches": len(fa[k]), "fetch_kib_per_launch": f_, "write_kib_per_launch": w_,
                              "hbm_bytes_per_launch": b}
-        md.append(f"| `{k}` | {len(fa[k])} | {f_:.1f} | {w_:.1f} | {f_ * ff / 1024:.2f} | {w_ * wf / 1024:.2f} | "
-                  f"{b / 1e6:.2f} |")
+        md.append(f"| `{k}` | {len(fa[k])} | {f_:.1f} | {w_:.1f} | {f_ * ff * 1024 / 1e6:.2f} | "
+                  f"{w_ * wf * 1024 / 1e6:.2f} | {b / 1e6:.2f} |")
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
     with open(os.path.join(ROOT, "profiles", "hbm_traffic_1280x720_plain.md"), "w") as f:
