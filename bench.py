@@ -332,14 +332,17 @@ def pipelined_driver(lib, h, sptrs, NB, slot0, preprocess, flow_of):
     """The pipelined plain form: window k binned and turned into its pyramid,
     then the flow k-1 -> k, all on stream k mod NS (NS = len(sptrs)), the
     flow once window k-1's pyramid (another stream's work) is ready; buffers
-    in a ring of NB (window k reuses the buffers of window k-NB once the
+    in a ring of NB > NS (window k reuses the buffers of window k-NB once the
     flows that read them are done).  The streams are ordered by the
     context's stream counters (ebof_stream_signal / ebof_stream_wait), one
     per stream from slot0 on: window k's preprocessing stores 2k+1 into its
-    stream's counter, its flow 2k+2.  Returns run(k_lo, k_hi), which issues
-    windows k_lo .. k_hi-1; work issued before k_lo must be complete."""
+    stream's counter.  That store also tells that flow k-NS, earlier on the
+    same stream, is done, so flows store nothing.  Returns run(k_lo, k_hi),
+    which issues windows k_lo .. k_hi-1; work issued before k_lo must be
+    complete."""
     import ctypes
     NS = len(sptrs)
+    assert NB > NS, "the ring must outlast a round of the streams"
 
     def check(rc):
         if rc:
@@ -349,29 +352,29 @@ def pipelined_driver(lib, h, sptrs, NB, slot0, preprocess, flow_of):
     val = ctypes.c_uint32()
 
     def flow_done(j):  # the host knows flow j has completed
-        f = j % NS
-        if seen[f] < 2 * j + 2:
+        f, need = j % NS, 2 * (j + NS) + 1  # window j+NS's preprocessing, after flow j on its stream
+        if seen[f] < need:
             check(lib.ebof_signal_read(h, slot0 + f, ctypes.byref(val)))
             seen[f] = val.value
-        return seen[f] >= 2 * j + 2
+        return seen[f] >= need
 
     def run(k_lo, k_hi):
         for i in range(NS):
             seen[i] = 0
         for k in range(k_lo, k_hi):
             i = k % NS
-            for j in (k - NB, k - NB + 1):  # the flows that last read buffer k % NB
-                if j >= max(1, k_lo) and not flow_done(j):
-                    check(lib.ebof_stream_wait(h, slot0 + j % NS, 2 * j + 2, sptrs[i]))
+            # the flows that last read buffer k % NB; one on this stream is
+            # ordered before window k already, and window j+NS < k has been
+            # issued for the others
+            for j in (k - NB, k - NB + 1):
+                if j >= max(1, k_lo) and j % NS != i and not flow_done(j):
+                    check(lib.ebof_stream_wait(h, slot0 + j % NS, 2 * (j + NS) + 1, sptrs[i]))
             preprocess(k, i)
+            check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 1, sptrs[i]))
             if k > 0:
-                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 1, sptrs[i]))
                 if k - 1 >= k_lo:  # window k-1's pyramid, from another stream
                     check(lib.ebof_stream_wait(h, slot0 + (k - 1) % NS, 2 * k - 1, sptrs[i]))
                 flow_of(k, i)
-                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 2, sptrs[i]))
-            else:
-                check(lib.ebof_stream_signal(h, slot0 + i, 2 * k + 1, sptrs[i]))
 
     return run
 
