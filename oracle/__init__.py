@@ -91,6 +91,10 @@ def _load():
     lib.oref_densify.argtypes = [i32, i32, P, P, i32, i32, P, P]
     lib.oref_patch_count.argtypes = [i32, i32, i32, i32]
     lib.oref_patch_count.restype = i64
+    lib.oref_ff_transport.argtypes = [i32, i32, P, P]
+    lib.oref_ff_smooth.argtypes = [i32, i32, i32, P]
+    lib.oref_flow_filter.argtypes = [i32, i32, i32, P, P, i32, P, P, P, P]
+    lib.oref_flow_filter.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -307,6 +311,61 @@ def dis_flow(pyr0, pyr1, W, H, L, ps=8, stride=4, iters=16, lam=0.3,
     if want_patches:
         return flow, pu
     return flow
+
+
+# Update-prediction filter (Sec. III-D's flow block, Sec. IV-A's layer
+# parameters): the reading is spelled out in ebof_oracle.h.
+def ff_transport(U):
+    """The previous flow U ([2,H,W]) carried along itself over one window:
+    P(x) = U(x - U(x)), bilinear with replicated border."""
+    U = np.ascontiguousarray(U, np.float64)
+    _, H, W = U.shape
+    P = np.empty_like(U)
+    _load().oref_ff_transport(W, H, _ptr(U), _ptr(P))
+    return P
+
+
+def ff_smooth(F, iters):
+    """`iters` Jacobi iterations of the five-point mean (replicated border)
+    on both planes of F ([2,H,W]); a smoothed copy is returned."""
+    out = np.array(F, np.float64, copy=True, order="C")
+    _, H, W = out.shape
+    _load().oref_ff_smooth(W, H, int(iters), _ptr(out))
+    return out
+
+
+def filter_state_size(W, H, layers):
+    """Doubles (and floats on the GPU) of a filter state of `layers` layers."""
+    return sum(2 * w * h for w, h in level_sizes(W, H, layers))
+
+
+def flow_filter(pyr0, pyr1, W, H, L, gamma, smooth, state=None):
+    """One step of the update-prediction filter from pyr0 (window k-1) to
+    pyr1 (window k), both L-level pyramids.  gamma / smooth: per layer, layer
+    0 the finest; their length is the number of layers.  state: the previous
+    step's flat state (None: zero).  Returns (flow [2,H,W] float64, state)."""
+    pyr0 = np.ascontiguousarray(pyr0, np.float32)
+    pyr1 = np.ascontiguousarray(pyr1, np.float32)
+    F = len(gamma)
+    assert len(smooth) == F
+    n = filter_state_size(W, H, F)
+    st = np.zeros(n, np.float64) if state is None else np.array(state, np.float64, copy=True, order="C")
+    assert st.shape == (n,)
+    g = np.ascontiguousarray(gamma, np.float64)
+    sm = np.ascontiguousarray(smooth, np.int32)
+    flow = np.empty((2, H, W), np.float64)
+    rc = _load().oref_flow_filter(W, H, L, _ptr(pyr0), _ptr(pyr1), F, _ptr(g), _ptr(sm), _ptr(st), _ptr(flow))
+    if rc != 0:
+        raise ValueError("oref_flow_filter rejected its arguments")
+    return flow, st
+
+
+def filter_layer(state, W, H, l):
+    """Layer l ([2,H_l,W_l]) of a flat filter state."""
+    sizes = level_sizes(W, H, l + 1)
+    off = sum(2 * w * h for w, h in sizes[:l])
+    w, h = sizes[l]
+    return np.asarray(state)[off:off + 2 * w * h].reshape(2, h, w)
 
 
 def _patch_grid(W, H, ps, stride):

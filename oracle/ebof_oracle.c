@@ -875,3 +875,132 @@ int oref_dis_flow(int32_t W, int32_t H, int32_t L, const float *pyr0,
     return oref_dis_flow_warm(W, H, L, pyr0, pyr1, ps, stride, iters, lambda,
                               NULL, flow, patch_uv);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Section III-D names the paper's flow block: an update-prediction filter  */
+/* that predicts the flow by image warping, carries it from one window to   */
+/* the next (its memory effect) and stacks the loops over pyramid layers,   */
+/* each layer with a regularisation weight and smoothing iterations          */
+/* (Sec. IV-A).  The reading below is spelled out in the header.            */
+/* ------------------------------------------------------------------------ */
+/* bilinear interpolation of a double field, replicated border */
+static double bilinear_d(const double *f, int32_t W, int32_t H, double sx,
+                         double sy)
+{
+    double fx = floor(sx), fy = floor(sy);
+    double ax = sx - fx, ay = sy - fy;
+    if (fx < -2.0)
+        fx = -2.0;
+    if (fx > W + 2.0)
+        fx = W + 2.0;
+    if (fy < -2.0)
+        fy = -2.0;
+    if (fy > H + 2.0)
+        fy = H + 2.0;
+    int64_t x0 = (int64_t)fx, y0 = (int64_t)fy;
+    double f00 = px_clamped(f, W, H, x0, y0);
+    double f10 = px_clamped(f, W, H, x0 + 1, y0);
+    double f01 = px_clamped(f, W, H, x0, y0 + 1);
+    double f11 = px_clamped(f, W, H, x0 + 1, y0 + 1);
+    return (1.0 - ay) * ((1.0 - ax) * f00 + ax * f10) +
+           ay * ((1.0 - ax) * f01 + ax * f11);
+}
+
+void oref_ff_transport(int32_t W, int32_t H, const double *U, double *P)
+{
+    size_t N = (size_t)W * H;
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            size_t q = (size_t)y * W + x;
+            double sx = x - U[q], sy = y - U[N + q];
+            P[q] = bilinear_d(U, W, H, sx, sy);
+            P[N + q] = bilinear_d(U + N, W, H, sx, sy);
+        }
+}
+
+void oref_ff_smooth(int32_t W, int32_t H, int32_t iters, double *F)
+{
+    size_t N = (size_t)W * H;
+    double *T = malloc(2 * N * sizeof(double));
+    for (int32_t it = 0; it < iters; it++) {
+        for (int c = 0; c < 2; c++) {
+            const double *f = F + c * N;
+            for (int32_t y = 0; y < H; y++)
+                for (int32_t x = 0; x < W; x++)
+                    T[c * N + (size_t)y * W + x] =
+                        (px_clamped(f, W, H, x, y) + px_clamped(f, W, H, x - 1, y) +
+                         px_clamped(f, W, H, x + 1, y) + px_clamped(f, W, H, x, y - 1) +
+                         px_clamped(f, W, H, x, y + 1)) / 5.0;
+        }
+        memcpy(F, T, 2 * N * sizeof(double));
+    }
+    free(T);
+}
+
+int oref_flow_filter(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                     const float *pyr1, int32_t layers, const double *gamma,
+                     const int32_t *smooth, double *state, double *flow)
+{
+    if (W < 1 || H < 1 || L < 1 || L > 64 || layers < 1 || layers > L)
+        return -1;
+    int32_t w[64], h[64];
+    size_t off[64], soff[64];
+    w[0] = W;
+    h[0] = H;
+    off[0] = soff[0] = 0;
+    for (int32_t l = 1; l < L; l++) {
+        w[l] = (w[l - 1] + 1) / 2;
+        h[l] = (h[l - 1] + 1) / 2;
+        off[l] = off[l - 1] + (size_t)w[l - 1] * h[l - 1];
+        soff[l] = soff[l - 1] + 2 * (size_t)w[l - 1] * h[l - 1];
+    }
+    for (int32_t l = 0; l < layers; l++)
+        if (gamma[l] <= 0.0 || smooth[l] < 0)
+            return -1;
+    double *Dc = NULL; /* the coarser layer's innovation */
+    for (int32_t l = layers - 1; l >= 0; l--) {
+        const int32_t Wl = w[l], Hl = h[l];
+        const size_t N = (size_t)Wl * Hl;
+        const float *I0 = pyr0 + off[l], *I1 = pyr1 + off[l];
+        double *U = state + soff[l];
+        double *Psi = malloc(2 * N * sizeof(double));
+        double *Phi = malloc(2 * N * sizeof(double));
+        oref_ff_transport(Wl, Hl, U, Psi);
+        if (Dc) {
+            const int32_t Wc = w[l + 1], Hc = h[l + 1];
+            const size_t Nc = (size_t)Wc * Hc;
+            for (int32_t y = 0; y < Hl; y++)
+                for (int32_t x = 0; x < Wl; x++) {
+                    int32_t X = x / 2, Y = y / 2;
+                    if (X > Wc - 1)
+                        X = Wc - 1;
+                    if (Y > Hc - 1)
+                        Y = Hc - 1;
+                    size_t q = (size_t)y * Wl + x, qc = (size_t)Y * Wc + X;
+                    Psi[q] += 2.0 * Dc[qc];
+                    Psi[N + q] += 2.0 * Dc[Nc + qc];
+                }
+        }
+        for (int32_t y = 0; y < Hl; y++)
+            for (int32_t x = 0; x < Wl; x++) {
+                size_t q = (size_t)y * Wl + x;
+                double gx = 255.0 * 0.5 * (at_clamped(I0, Wl, Hl, x + 1, y) - at_clamped(I0, Wl, Hl, x - 1, y));
+                double gy = 255.0 * 0.5 * (at_clamped(I0, Wl, Hl, x, y + 1) - at_clamped(I0, Wl, Hl, x, y - 1));
+                double r = 255.0 * (bilinear(I1, Wl, Hl, x + Psi[q], y + Psi[N + q]) - (double)I0[q]);
+                double k = r / (gx * gx + gy * gy + gamma[l]);
+                Phi[q] = Psi[q] - gx * k;
+                Phi[N + q] = Psi[N + q] - gy * k;
+            }
+        oref_ff_smooth(Wl, Hl, smooth[l], Phi);
+        for (size_t q = 0; q < 2 * N; q++) {
+            U[q] = Phi[q];
+            Phi[q] -= Psi[q]; /* the innovation, for the finer layer */
+        }
+        free(Psi);
+        free(Dc);
+        Dc = Phi;
+    }
+    free(Dc);
+    memcpy(flow, state, 2 * (size_t)W * H * sizeof(double));
+    return 0;
+}

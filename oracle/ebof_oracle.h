@@ -181,6 +181,41 @@ int oref_dis_flow_refined(int32_t W, int32_t H, int32_t L, const float *pyr0,
                           const double *prev_flow, const oref_var_params *vr,
                           double *flow, double *patch_uv);
 
+/* Update-prediction flow filter: the kind of frame-based flow block the
+ * paper's Sec. III-D selects (a predictive filter: the flow is predicted by
+ * warping and propagated in time, with update-prediction loops stacked over
+ * pyramid layers, each with its own regularisation weight and number of
+ * smoothing iterations, the Sec. IV-A parameters).  The paper gives no
+ * equations; this reading is the one the GPU library implements:
+ *   state: per layer l < layers (pyramid level l, W_l x H_l), the flow U_l of
+ *     the previous window pair (pixels of that level per window), two planes;
+ *     zero before the first pair.
+ *   for l = layers-1 down to 0:
+ *     prediction  P_l(x) = U_l(x - U_l(x)): the previous flow carried along
+ *                 itself over one window (bilinear, replicated border);
+ *                 Psi_l = P_l, plus, below the top layer, twice the coarser
+ *                 layer's innovation D_{l+1} at the parent pixel
+ *                 (floor(x/2), floor(y/2));
+ *     update      with g = 255 grad I0(x) (central differences, replicated
+ *                 border) and r = 255 (I1(x + Psi_l(x)) - I0(x)) (bilinear,
+ *                 replicated border): Phi = Psi_l - g r / (|g|^2 + gamma_l),
+ *                 the minimiser of (g.(Phi - Psi_l) + r)^2 +
+ *                 gamma_l |Phi - Psi_l|^2;
+ *     smoothing   smooth_l Jacobi iterations Phi <- mean of Phi at x and its
+ *                 four neighbours (replicated border), both planes;
+ *     U_l <- Phi, D_l = Phi - Psi_l.
+ *   The output flow is U_0.
+ * oref_ff_transport: P from U (one W x H layer, two planes each).
+ * oref_ff_smooth: `iters` iterations on F (two planes, in place).
+ * oref_flow_filter: pyr0 / pyr1 of L >= layers levels in the packed layout;
+ *   state: 2 * sum_{l<layers} W_l H_l doubles, layer 0 first (in/out);
+ *   flow: 2*W*H doubles (U_0).  Returns 0, or -1 on bad arguments. */
+void oref_ff_transport(int32_t W, int32_t H, const double *U, double *P);
+void oref_ff_smooth(int32_t W, int32_t H, int32_t iters, double *F);
+int oref_flow_filter(int32_t W, int32_t H, int32_t L, const float *pyr0,
+                     const float *pyr1, int32_t layers, const double *gamma,
+                     const int32_t *smooth, double *state, double *flow);
+
 /* Number of patches of one level: ceil((W-ps)/stride)+1 by the same in y. */
 int64_t oref_patch_count(int32_t W, int32_t H, int32_t ps, int32_t stride);
 
