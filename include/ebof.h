@@ -448,6 +448,60 @@ int ebof_fwl(ebof_ctx *ctx, const ebof_params *p, const uint16_t *x,
              int64_t t0_us, const float *flow, double *out_dev,
              void *hip_stream);
 
+/* ---- update-prediction flow filter --------------------------------------------
+ * The kind of flow block Sec. III-D selects: a predictive filter whose state
+ * is the flow itself, carried from one window to the next (its memory effect)
+ * and refined by an update per pyramid layer, each layer with its own
+ * regularisation weight and number of smoothing iterations (the parameters of
+ * Sec. IV-A).  The paper gives no equations; per window pair, for every layer
+ * l from the coarsest (layers-1) to the finest (0), on pyramid level l
+ * (W_l x H_l) of both windows' pyramids (I0: window k-1, I1: window k):
+ *   prediction  Psi = U_l(x - U_l(x)): the layer's previous flow carried along
+ *               itself (bilinear, replicated border); below the top layer
+ *               plus twice the coarser layer's innovation at the parent pixel
+ *               (x/2, y/2);
+ *   update      Phi = Psi - g r / (|g|^2 + gamma_l) with g = 255 grad I0
+ *               (central differences, replicated border) and
+ *               r = 255 (I1(x + Psi) - I0(x)) (bilinear): the minimiser of
+ *               (g.(Phi - Psi) + r)^2 + gamma_l |Phi - Psi|^2;
+ *   smoothing   smooth_l Jacobi iterations of the five-point mean of both
+ *               planes (replicated border);
+ *   U_l <- Phi; the innovation Phi - Psi goes to the next finer layer.
+ * The output flow is U_0 (pixels per window), zero off the edge pixels of
+ * mask when p->flags has EBOF_MASK_FLOW and mask is not NULL.  Single
+ * precision. */
+typedef struct {
+    int32_t layers;                  /* filter layers, 1 .. p->levels                */
+    float gamma[EBOF_MAX_LEVELS];    /* layer l's regularisation weight (l = 0 the
+                                        finest), finite and > 0                     */
+    int32_t smooth[EBOF_MAX_LEVELS]; /* layer l's smoothing iterations, 0 .. 1000    */
+} ebof_filter_params;
+
+/* Sec. IV-A's settings: 3 layers; for sensors up to 346x260 weights 500, 250
+ * and 50 with 5, 25 and 50 smoothing iterations (finest layer first: the
+ * paper lists the layers from the coarsest), for larger ones 500 and 20 at
+ * every layer.  EBOF_E_INVAL when out is NULL. */
+int ebof_filter_params_default(int32_t width, int32_t height, ebof_filter_params *out);
+
+/* Floats of a filter state: 2 * sum over the layers of W_l * H_l; -1 (with the
+ * error set) when p or fp is invalid. */
+int64_t ebof_filter_state_floats(const ebof_params *p, const ebof_filter_params *fp);
+
+/* One filter step from pyramid pyr_prev (window k-1) to pyr_curr (window k),
+ * both of p->levels levels (device, ebof_pyramid_floats floats each).
+ * state: device, ebof_filter_state_floats floats, layer 0 first, each layer
+ * its u plane then its v plane (row-major W_l x H_l); on entry the previous
+ * step's flows (zeros before the first step), on return this step's.
+ * flow_out: device 2*W*H floats (u plane, v plane).  mask: NULL or device
+ * W*H bytes (E_df of window k-1).  Work memory comes from the context's
+ * arena, per sensor size, layer count and stream; calls on one stream are
+ * ordered, calls on different streams use different work memory.  Returns
+ * EBOF_E_INVAL on bad arguments, EBOF_E_NOMEM when the arena cannot hold the
+ * work memory (about 8.7 W*H floats for 3 layers). */
+int ebof_flow_filter(ebof_ctx *ctx, const ebof_params *p, const ebof_filter_params *fp,
+                     const float *pyr_prev, const float *pyr_curr, const uint8_t *mask,
+                     float *state, float *flow_out, void *hip_stream);
+
 /* ---- measurement -------------------------------------------------------------
  * Kernel timing: when enabled, every launch of a selected kernel is
  * bracketed by a pair of HIP events recorded on its stream right before and

@@ -30,6 +30,7 @@ EBOF_WARM_START = 4
 EBOF_VAR_REFINE = 8
 EBOF_SURFACE_EXP, EBOF_SURFACE_LINEAR, EBOF_SURFACE_BOUNDED, EBOF_SURFACE_LOG = 0, 1, 2, 3
 EBOF_MAX_BATCH = 1024
+EBOF_MAX_LEVELS = 8
 EBOF_TUNE_OFF = 0
 EBOF_TUNE_AUTO = 1
 EBOF_TUNE_LEVELS = 8   # lanes-per-patch values per cache line (one per level)
@@ -92,6 +93,11 @@ class ebof_window(ctypes.Structure):
 _lib = None
 
 
+class ebof_filter_params(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int32), ("gamma", ctypes.c_float * EBOF_MAX_LEVELS),
+                ("smooth", ctypes.c_int32 * EBOF_MAX_LEVELS)]
+
+
 def load():
     """Load libebof.so; raises when it has not been built."""
     global _lib
@@ -136,6 +142,9 @@ def load():
         "ebof_timing_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
                              ctypes.c_int),
         "ebof_version": ([], ctypes.c_char_p),
+        "ebof_filter_params_default": ([i32, i32, ctypes.POINTER(ebof_filter_params)], ctypes.c_int),
+        "ebof_filter_state_floats": ([pp, ctypes.POINTER(ebof_filter_params)], i64),
+        "ebof_flow_filter": ([P, pp, ctypes.POINTER(ebof_filter_params), P, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -151,7 +160,8 @@ def exported_symbols():
             "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_flow_errors", "ebof_fwl", "ebof_window_end", "ebof_window_surface_range", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
             "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
-            "ebof_timing_enable", "ebof_timing_read", "ebof_version"]
+            "ebof_timing_enable", "ebof_timing_read", "ebof_version", "ebof_filter_params_default",
+            "ebof_filter_state_floats", "ebof_flow_filter"]
 
 
 # --------------------------------------------------------------------------
@@ -322,6 +332,43 @@ def ebof_flow_warm(ctx, p, pyr_prev, pyr_curr, flow_out, flow_init=None, flow_de
     fd = _dev(flow_dense_out, torch.float32, 2 * N, "flow_dense_out", optional=True)
     return _check(ctx.handle, ctx.lib.ebof_flow_warm(ctx.handle, ctypes.byref(p), a, b, m, fi, f, fd,
                                                      _stream(stream)))
+
+
+def ebof_filter_params_default(width, height, **overrides):
+    """Sec. IV-A's filter settings for a width x height sensor; overrides:
+    layers=, gamma=[...], smooth=[...] (finest layer first)."""
+    fp = ebof_filter_params()
+    rc = load().ebof_filter_params_default(int(width), int(height), ctypes.byref(fp))
+    if rc != EBOF_OK:
+        raise EbofError(rc, load().ebof_last_error(None).decode())
+    if "layers" in overrides:
+        fp.layers = int(overrides["layers"])
+    for name in ("gamma", "smooth"):
+        if name in overrides:
+            arr = getattr(fp, name)
+            for l, v in enumerate(overrides[name]):
+                arr[l] = v
+    return fp
+
+
+def ebof_filter_state_floats(p, fp):
+    n = load().ebof_filter_state_floats(ctypes.byref(p), ctypes.byref(fp))
+    if n < 0:
+        raise EbofError(EBOF_E_INVAL, load().ebof_last_error(None).decode())
+    return int(n)
+
+
+def ebof_flow_filter(ctx, p, fp, pyr_prev, pyr_curr, state, flow_out, mask=None, stream=None):
+    """One step of the update-prediction flow filter (state in/out)."""
+    P = ebof_pyramid_floats(p)
+    N = p.width * p.height
+    a = _dev(pyr_prev, torch.float32, P, "pyr_prev")
+    b = _dev(pyr_curr, torch.float32, P, "pyr_curr")
+    m = _dev(mask, torch.uint8, N, "mask", optional=True)
+    s = _dev(state, torch.float32, ebof_filter_state_floats(p, fp), "state")
+    f = _dev(flow_out, torch.float32, 2 * N, "flow_out")
+    return _check(ctx.handle, ctx.lib.ebof_flow_filter(ctx.handle, ctypes.byref(p), ctypes.byref(fp), a, b, m, s,
+                                                       f, _stream(stream)))
 
 
 def ebof_flow_noalloc(p, pyr_prev, pyr_curr, flow_out, mask=None, stream=None):

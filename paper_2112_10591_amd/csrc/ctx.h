@@ -117,6 +117,8 @@ struct ebof_ctx {
     std::map<std::tuple<int, int, int, int, uintptr_t>, ebof::Scratch> stage_scratch;
     // evaluation-call scratch per (pixels, HIP stream)
     std::map<std::pair<int64_t, uintptr_t>, ebof::EvalScratch> eval_scratch;
+    // update-prediction filter work memory per (width, height, layers, stream)
+    std::map<std::tuple<int32_t, int32_t, int32_t, uintptr_t>, float*> filter_scratch;
     // adaptive-window scratch per HIP stream
     std::map<uintptr_t, void*> window_scratch;
 

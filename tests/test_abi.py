@@ -100,3 +100,29 @@ def test_flow_noalloc_host_checks():
     big = L.ebof_params_default(8192, 8192, stride=1, levels=1)
     assert lib.ebof_flow_noalloc(ctypes.byref(big), dummy, dummy, None, dummy, None) == L.EBOF_E_NOMEM
     assert "fixed scratch" in lib.ebof_last_error(None).decode()
+
+
+def test_filter_params_and_state_size():
+    """The flow filter's defaults follow Sec. IV-A (three layers; at 346x260
+    weights 500 / 250 / 50 and 5 / 25 / 50 smoothing iterations from the
+    finest layer, 500 and 20 at every layer for HD), its state holds two
+    planes per layer, and bad settings are refused on the host."""
+    lo = L.ebof_filter_params_default(346, 260)
+    hi = L.ebof_filter_params_default(1280, 720)
+    assert lo.layers == 3 and list(lo.gamma)[:3] == [500.0, 250.0, 50.0] and list(lo.smooth)[:3] == [5, 25, 50]
+    assert hi.layers == 3 and list(hi.gamma)[:3] == [500.0] * 3 and list(hi.smooth)[:3] == [20] * 3
+    p = L.ebof_params_default(346, 260)
+    assert L.ebof_filter_state_floats(p, lo) == 2 * (346 * 260 + 173 * 130 + 87 * 65)
+    lib = L.load()
+    for field, value in [("layers", 0), ("layers", 4), ("gamma", 0.0), ("gamma", float("nan")),
+                         ("gamma", float("inf")), ("smooth", -1), ("smooth", 1001)]:
+        fp = L.ebof_filter_params_default(346, 260)
+        if field == "layers":
+            fp.layers = value
+        else:
+            getattr(fp, field)[1] = value
+        assert lib.ebof_filter_state_floats(ctypes.byref(p), ctypes.byref(fp)) == -1, (field, value)
+    assert lib.ebof_filter_params_default(346, 260, None) == L.EBOF_E_INVAL
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    assert lib.ebof_flow_filter(None, ctypes.byref(p), ctypes.byref(lo), dummy, dummy, None, dummy, dummy,
+                                None) == L.EBOF_E_INVAL
