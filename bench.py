@@ -652,6 +652,45 @@ def main():
                          "an i9-9880H + Quadro RTX 5000 (different flow method and hardware)",
     }
 
+    # ---------------- the update-prediction filter in place of DIS ----------
+    # (the flow block Sec. III-D describes; Sec. IV-A's HD settings): the
+    # sequential plain form with ebof_flow_filter as the flow stage, and the
+    # filter step alone, timed by events on the stream
+    fp = L.ebof_filter_params_default(W, H)
+    f_state = torch.zeros(L.ebof_filter_state_floats(p, fp), dtype=torch.float32, device=dev)
+    f_flow = torch.empty(2 * N, dtype=torch.float32, device=dev)
+    fpp, fsp, ffp = ctypes.byref(fp), vp(f_state.data_ptr()), vp(f_flow.data_ptr())
+
+    def filter_of(k):
+        b, bp = k % NB, (k - 1) % NB
+        check(lib.ebof_flow_filter(h, pp, fpp, pyr_p[bp], pyr_p[b], edge_p[bp], fsp, ffp, sptrs[0]))
+
+    with torch.cuda.stream(streams[0]):
+        for k in range(Wm):
+            preprocess(k, 0)
+            if k > 0:
+                filter_of(k)
+        sync_all()
+        t0 = time.perf_counter()
+        for k in range(Wm, Wm + K):
+            preprocess(k, 0)
+            filter_of(k)
+        sync_all()
+        f_fps = K / (time.perf_counter() - t0)
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(streams[0])
+        for _ in range(K):
+            filter_of(Wm + K - 1)
+        eb.record(streams[0])
+        eb.synchronize()
+        f_ms = ea.elapsed_time(eb) / K
+    out["flow_filter"] = {
+        "settings": {"layers": fp.layers, "gamma": list(fp.gamma)[:fp.layers], "smooth": list(fp.smooth)[:fp.layers]},
+        "plain_sequential_frames_per_s": f_fps, "ms_per_step": f_ms,
+        "note": "ebof_flow_filter in place of ebof_flow on the 1280x720 sequence, one stream; ms_per_step: the "
+                "filter step alone (HIP events around K steps)"}
+    log(f"flow filter: {f_fps:.0f} frames/s sequential with the filter as the flow stage; step {f_ms:.4f} ms")
+
     # ---------------- the low-resolution plain config ------------------------
     c1 = [] if args.no_c1 else synth.generate("c1", 0, range(64), workers=args.workers)
     c1_pair = None

@@ -6,8 +6,9 @@ and outlier rate against the generator's motion field and by the flow warp
 loss.  The paper's datasets are not available: the generator's streams stand
 in for them (346x260 translating segments, 1280x720 affine scenes).
 
-Every computation runs in the library (stage calls, ebof_flow_errors,
-ebof_fwl); this module only chooses parameters and averages the results.
+Every computation runs in the library (stage calls, ebof_flow_filter,
+ebof_flow_errors, ebof_fwl); this module only chooses parameters and
+averages the results.
 
     python -m paper_2112_10591_amd.evalkit [--pairs N] [--hd] [--sweep]
 """
@@ -36,12 +37,14 @@ def _window(ctx, p, ev):
     return e, pr, dv
 
 
-def score(ctx, stream, p, pairs, warm=False):
+def score(ctx, stream, p, pairs, warm=False, filt=None):
     """Mean AEE, outlier fraction (reference edge pixels away from the
     border) and FWL (the reference window's events, each voting 1: the
     generator draws polarities at random, so signed votes would cancel
     rather than sharpen) over `pairs` consecutive window pairs; warm: each
-    flow starts from the previous pair's."""
+    flow starts from the previous pair's; filt: an ebof_filter_params, the
+    flow then comes from the update-prediction filter (its state carried
+    from pair to pair, from zero)."""
     W, H = p.width, p.height
     inner = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
     inner[BORDER:H - BORDER, BORDER:W - BORDER] = 1
@@ -49,11 +52,17 @@ def score(ctx, stream, p, pairs, warm=False):
     dense = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
     before = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
     aee, out, fwl = [], [], []
+    state = None
+    if filt is not None:
+        state = torch.zeros(L.ebof_filter_state_floats(p, filt), dtype=torch.float32, device="cuda")
     prev = _window(ctx, p, stream.window(0))
     for k in range(1, pairs + 1):
         cur = _window(ctx, p, stream.window(k))
-        init = before if (warm and k > 1) else None
-        L.ebof_flow_warm(ctx, p, prev[1], cur[1], flow, flow_init=init, flow_dense_out=dense, mask=prev[0])
+        if filt is not None:
+            L.ebof_flow_filter(ctx, p, filt, prev[1], cur[1], state, dense)
+        else:
+            init = before if (warm and k > 1) else None
+            L.ebof_flow_warm(ctx, p, prev[1], cur[1], flow, flow_init=init, flow_dense_out=dense, mask=prev[0])
         gt = torch.from_numpy(stream.gt_flow(k).astype(np.float32).reshape(-1)).cuda()
         m = (prev[0].view(H, W) * inner).contiguous()
         a, o, n = L.ebof_flow_errors(ctx, W, H, dense, gt, m)
@@ -77,6 +86,10 @@ def ablations(ctx, stream, pairs):
     rows.append(("proposed + warm start from the previous pair", score(ctx, stream, p, pairs, warm=True)))
     p = L.ebof_params_default(stream.W, stream.H, flags=L.EBOF_MASK_FLOW | L.EBOF_VAR_REFINE)
     rows.append(("proposed + variational refinement", score(ctx, stream, p, pairs)))
+    p = L.ebof_params_default(stream.W, stream.H, flags=L.EBOF_MASK_FLOW)
+    fp = L.ebof_filter_params_default(stream.W, stream.H)
+    rows.append(("update-prediction filter in place of DIS (Sec. IV-A settings)",
+                 score(ctx, stream, p, pairs, filt=fp)))
     for name, over in [("proposed (eq. 1)", {}), ("NDF: no denoising/filling", dict(n_d=0, n_f=5)),
                        ("DS_L: linear distance", dict(surface=L.EBOF_SURFACE_LINEAR)),
                        ("DS_LB: distance bounded at d_sat", dict(surface=L.EBOF_SURFACE_BOUNDED)),
