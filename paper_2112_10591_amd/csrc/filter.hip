@@ -25,6 +25,7 @@ constexpr int kFfBlock = 256;
 constexpr int kFfTile = 32;                      // smoothing: output tile edge
 constexpr int kFfSteps = 8;                      // smoothing: iterations per launch (= halo)
 constexpr int kFfEdge = kFfTile + 2 * kFfSteps;  // smoothing: tile edge with its halo
+constexpr int kFfCells = kFfEdge * kFfEdge / kFfBlock;  // smoothing: cells per thread
 constexpr int kFfMaxSmooth = 1000;
 
 __device__ __forceinline__ int ff_clamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -100,25 +101,35 @@ __global__ __launch_bounds__(kFfBlock) void k_ff_smooth(const float* __restrict_
         buf[0][1][idx] = in ? src[N + g] : 0.0f;
     }
     __syncthreads();
-    // a cell's neighbour: the pixel's own index clamped into the image (the
-    // replicated border), then into the tile (cells that reach past the tile
-    // are in the halo and their values are not used at the end)
-    auto loc = [&](int gx, int gy) -> int {
-        const int lx = ff_clamp(ff_clamp(gx, 0, w - 1) - X0, 0, kFfEdge - 1);
-        const int ly = ff_clamp(ff_clamp(gy, 0, h - 1) - Y0, 0, kFfEdge - 1);
-        return ly * kFfEdge + lx;
-    };
+    // Each thread owns kFfCells cells of the tile.  A cell's neighbour is the
+    // pixel's own index clamped into the image (the replicated border), then
+    // into the tile (cells that reach past the tile are in the halo and
+    // their values are not used at the end): one bit per side says whether
+    // the neighbour is a different cell, one whether the cell is on the image.
+    static_assert(kFfEdge * kFfEdge == kFfCells * kFfBlock, "the tile's cells are spread evenly");
+    int side[kFfCells];
+#pragma unroll
+    for (int k = 0; k < kFfCells; ++k) {
+        const int idx = threadIdx.x + k * kFfBlock;
+        const int lx = idx % kFfEdge, ly = idx / kFfEdge;
+        const int gx = X0 + lx, gy = Y0 + ly;
+        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        side[k] = (in ? 16 : 0) | (gx > 0 && lx > 0 ? 1 : 0) | (gx < w - 1 && lx < kFfEdge - 1 ? 2 : 0) |
+                  (gy > 0 && ly > 0 ? 4 : 0) | (gy < h - 1 && ly < kFfEdge - 1 ? 8 : 0);
+    }
     for (int it = 0; it < iters; ++it) {
         const int cur = it & 1;
-        for (int idx = threadIdx.x; idx < kFfEdge * kFfEdge; idx += kFfBlock) {
-            const int gx = X0 + idx % kFfEdge, gy = Y0 + idx / kFfEdge;
-            if (gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
-            const int c = loc(gx, gy), l = loc(gx - 1, gy), r = loc(gx + 1, gy), u = loc(gx, gy - 1),
-                      d = loc(gx, gy + 1);
+#pragma unroll
+        for (int k = 0; k < kFfCells; ++k) {
+            const int m = side[k];
+            if (!(m & 16)) continue;
+            const int idx = threadIdx.x + k * kFfBlock;
+            const int l = (m & 1) ? idx - 1 : idx, r = (m & 2) ? idx + 1 : idx;
+            const int u = (m & 4) ? idx - kFfEdge : idx, d = (m & 8) ? idx + kFfEdge : idx;
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 const float* b = buf[cur][p];
-                buf[cur ^ 1][p][idx] = ((((b[c] + b[l]) + b[r]) + b[u]) + b[d]) / 5.0f;
+                buf[cur ^ 1][p][idx] = ((((b[idx] + b[l]) + b[r]) + b[u]) + b[d]) * 0.2f;
             }
         }
         __syncthreads();
