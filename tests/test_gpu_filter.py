@@ -143,3 +143,31 @@ def test_filter_argument_checks(ctx):
     fp.layers = 4
     assert lib.ebof_flow_filter(h, ctypes.byref(p), ctypes.byref(fp), b, b, None, b, b, None) == L.EBOF_E_INVAL
     assert "layers" in lib.ebof_last_error(h).decode()
+
+
+@pytest.mark.parametrize("W,H,levels,layers,smooth", [(8, 8, 1, 1, [3]), (16, 17, 2, 2, [0, 17]),
+                                                       (67, 45, 3, 3, [8, 1, 16])])
+def test_filter_random_state_and_images(ctx, W, H, levels, layers, smooth):
+    """Random pyramids (not surfaces) and a random previous state of up to
+    3 px, at the smallest sizes and smoothing counts of 0, 1, 8, 16 and 17
+    (one partial launch, exactly one or two full ones, and two plus one)."""
+    rng = np.random.default_rng(W * 100 + H)
+    p = L.ebof_params_default(W, H, levels=levels)
+    fp = L.ebof_filter_params_default(W, H, layers=layers, gamma=[40.0, 90.0, 300.0][:layers], smooth=smooth)
+    P = L.ebof_pyramid_floats(p)
+    pyr0 = rng.random(P).astype(np.float32)
+    pyr1 = rng.random(P).astype(np.float32)
+    st0 = rng.uniform(-3.0, 3.0, L.ebof_filter_state_floats(p, fp)).astype(np.float32)
+    state = dev(st0)
+    flow = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    L.ebof_flow_filter(ctx, p, fp, dev(pyr0), dev(pyr1), state, flow)
+    of, ost = oracle.flow_filter(pyr0, pyr1, W, H, levels, [float(fp.gamma[l]) for l in range(layers)], smooth,
+                                 st0.astype(np.float64))
+    torch.cuda.synchronize()
+    gs = state.cpu().numpy().astype(np.float64)
+    for l in range(layers):
+        e = epe(layer_view(gs, W, H, l), layer_view(ost, W, H, l))
+        say(f"  {W}x{H} layer {l}: EPE vs oracle mean {e.mean():.2e} max {e.max():.2e}")
+        assert e.mean() <= FLOW_MEAN and np.percentile(e, 99.9) <= FLOW_P999, (W, H, l)
+    e = epe(flow.cpu().numpy().reshape(2, H, W).astype(np.float64), of)
+    assert e.mean() <= FLOW_MEAN and np.percentile(e, 99.9) <= FLOW_P999
