@@ -602,7 +602,9 @@ def main():
                 "traffic": measured_traffic("k_dis_level"), **timing,
                 "work_per_window": dis_flops_window(L, p)}
     else:
-        bytes_per_window = {"edt_rows": 2 * N + 4 * N, "densify": 4 * N + 4 * N + N + 8 * N,
+        # edt_rows without squared distances exported: column masks in,
+        # surface out (the column distances are formed in the kernel)
+        bytes_per_window = {"edt_rows": N // 8 + 4 * N, "densify": 4 * N + 4 * N + N + 8 * N,
                             "scatter": 12 * 300_000, "denoise_fill": 2 * N,
                             "edt_cols": N // 8 + 2 * N, "pack_cols": N + N // 8,
                             "pyr_down": pyr_bytes(L, p)}.get(dominant, 0)
@@ -909,7 +911,7 @@ def bench_batched(L, ctx, c3, steps, dev, stream):
         if cnt:
             kern[name] = max(ms - cnt * pair_ms, 0.0) / nb_t
     lib.ebof_timing_enable(h, 0)
-    rows_bytes = sum(6 * q.width * q.height for q in params)
+    rows_bytes = sum(q.width * q.height // 8 + 4 * q.width * q.height for q in params)  # masks in, surface out
     pyr_b = sum(pyr_bytes(L, q) for q in params)
     hbm = {}
     for name, nbytes in (("edt_rows", rows_bytes), ("pyr_down", pyr_b)):

@@ -1063,11 +1063,13 @@ static int bin_impl(ebof_ctx* ctx, const ebof_params* p, const uint16_t* x, cons
 
 // The distance transform, surface and pyramid (Sec. III-C) of the edge image
 // d.e_df into d.d2 / d.pyr; the column masks are packed first unless the
-// fill already wrote them.
+// fill already wrote them.  A saturating surface with no squared distance
+// exported skips the column pass (edt_local).
 static void surface_impl(ebof_ctx* ctx, const ebof_params* p, const WinDesc& d, hipStream_t st, bool packed) {
     if (!packed)
         timed(ctx, EBOF_K_PACK_COLS, st, [&] { launch_pack_cols(one_launch(&d, stage_items(d, kStPack, false, false, kStageTune), st)); });
-    timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
+    if (!edt_local(d))
+        timed(ctx, EBOF_K_EDT_COLS, st, [&] { launch_edt_cols(one_launch(&d, stage_items(d, kStCols, false, false, kStageTune), st)); });
     timed(ctx, EBOF_K_EDT_ROWS, st, [&] { launch_edt_rows(one_launch(&d, stage_items(d, kStRows, false, false, kStageTune), st), kStageTune.rows_nr); });
     if (p->levels > 1)
         timed(

@@ -88,6 +88,15 @@ struct WinDesc {
     LevelGeom lv[kMaxLevels];
 };
 
+// A window whose squared distance is not exported and whose surface is
+// looked up (it saturates from lut_n on) needs column distances only up to
+// lut_r: the row pass then forms them itself from the column bit masks,
+// capped at lut_r, and the column pass has no work (k_edt_rows).
+__host__ __device__ inline bool edt_local(const WinDesc& d) {
+    return d.d2 == nullptr && d.surf_kind != EBOF_SURFACE_LINEAR && d.surf_kind != EBOF_SURFACE_LOG &&
+           d.lut_n > 0 && d.lut_r <= kRowReach;
+}
+
 // Stages of the batched pipeline; each has a prefix sum of work items.
 enum Stage : int32_t {
     kStZero = 0,

@@ -364,7 +364,14 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
 // the squared distance: lut[D2] below lut_n, exactly 1.0f from there on.  When
 // D2 is not exported the search also stops at r^2 >= lut_n: a minimum of
 // lut_n or more gives 1.0f whatever it is, and a smaller one is always found
-// before that radius.
+// before that radius.  Such a window (edt_local) needs g only up to lut_r:
+// the item forms its rows' column distances from the column masks (the
+// chunk's word and its two neighbours, which reach 64 rows each way), capped
+// at lut_r, over a band of lut_r rounded up to kRowUnroll columns each side,
+// and there is no column pass.  Capping changes no candidate below lut_n: a
+// squared distance under lut_n <= lut_r^2 comes from a column less than
+// lut_r away whose g is less than lut_r, and every candidate that involves a
+// capped g is at least lut_r^2.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t g_sq(uint32_t g) { return g == kGInf ? 0x7fffffffu : g * g; }
 
@@ -390,13 +397,43 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         const float sat = d->lut_sat;
         // (a surface that never saturates needs the exact distance everywhere)
         const uint32_t cap = (exp_d2 || computed) ? 0xffffffffu : (uint32_t)lut_n;
-        const int lo = max(0, x0 - R), hi = min(W, x0 + kRowSeg + R);
+        const bool loc = edt_local(*d);
+        const int band = loc ? (d->lut_r + kRowUnroll - 1) / kRowUnroll * kRowUnroll : R;
+        const int lo = max(0, x0 - band), hi = min(W, x0 + kRowSeg + band);
         const int ww = hi - lo;
         const uint16_t* __restrict__ g = d->g + (size_t)y0 * W;
         const float* __restrict__ lut = d->lut;
-        stage_window<8>(sG, ww, NR, [&](int r, int c) -> uint32_t {
-            return r < nrows ? g_sq(g[(size_t)r * W + lo + c]) : 0x7fffffffu;
-        });
+        if (loc) {
+            // the item's rows lie in one 64-row chunk (NR divides kChunk)
+            const int ck = y0 / kChunk, nch = (H + kChunk - 1) / kChunk;
+            const int rr0 = y0 - ck * kChunk, lr = d->lut_r;
+            const uint64_t* __restrict__ cm = d->colmask + lo;
+            for (int c = threadIdx.x; c < ww; c += kBlock) {
+                const uint64_t m = cm[(size_t)ck * W + c];
+                const uint64_t mp = ck > 0 ? cm[(size_t)(ck - 1) * W + c] : 0ull;
+                const uint64_t mn = ck + 1 < nch ? cm[(size_t)(ck + 1) * W + c] : 0ull;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const int rr = rr0 + k;  // row within the chunk
+                    int gv = lr;
+                    const uint64_t dn = m >> rr;                                     // bits >= rr
+                    const uint64_t up = rr == 63 ? m : (m & ((2ull << rr) - 1));     // bits <= rr
+                    if (dn)
+                        gv = min(gv, __ffsll((unsigned long long)dn) - 1);
+                    else if (mn)
+                        gv = min(gv, kChunk - rr + __ffsll((unsigned long long)mn) - 1);
+                    if (up)
+                        gv = min(gv, rr - (63 - __clzll(up)));
+                    else if (mp)
+                        gv = min(gv, rr + 1 + __clzll(mp));
+                    sG[k * ww + c] = k < nrows ? (uint32_t)(gv * gv) : 0x7fffffffu;
+                }
+            }
+        } else {
+            stage_window<8>(sG, ww, NR, [&](int r, int c) -> uint32_t {
+                return r < nrows ? g_sq(g[(size_t)r * W + lo + c]) : 0x7fffffffu;
+            });
+        }
         if (lut_lds) {
             float lv[kLutLds / kBlock];
 #pragma unroll
@@ -444,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
                     for (int k = 0; k < NR; ++k) best[k] = min(best[k], rr2 + min(cl[u][k], cr[u][k]));
                 }
             }
-            if (r > R) {  // beyond the staged columns
+            if (!loc && r > R) {  // beyond the staged columns (a capped search never gets here)
                 for (;; ++r) {
                     const uint32_t r2 = (uint32_t)r * (uint32_t)r;
                     const bool lft = x - r >= 0, rgt = x + r < W;
@@ -1156,7 +1193,8 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const
     if (stage == kStZero) return zero ? (int32_t)((N + kZeroBytesPerItem - 1) / kZeroBytesPerItem) : 0;
     if (stage == kStScatter) return (int32_t)((d.n_ev + kEventsPerItem - 1) / kEventsPerItem);
     if (stage == kStDenoise) return ((d.W + kTile - 1) / kTile) * ((d.H + kTileH - 1) / kTileH);
-    if (stage == kStPack || stage == kStCols) return bands * nch;
+    if (stage == kStPack) return bands * nch;
+    if (stage == kStCols) return edt_local(d) ? 0 : bands * nch;
     if (stage == kStRows) return ((d.H + t.rows_nr - 1) / t.rows_nr) * ((d.W + kRowSeg - 1) / kRowSeg);
     if (stage >= kStPyr && stage < kStPyr + kMaxLevels - 1) {
         const int from = (stage - kStPyr) * kPyrChain;

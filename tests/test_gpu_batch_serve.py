@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2112_10591_amd import synth
 from flowcheck import OracleFlow, assert_flow_matches, ref_window
 
@@ -104,6 +105,85 @@ def test_window_surface_equals_two_stage_calls(ctx):
                 assert torch.equal(e, e0) and torch.equal(pr, pr0), (W, "no events")
                 assert int((d2 != 2**31 - 1).sum()) == 0
         _say(f"window_surface {W}x{H}: {len(evs) + 1} windows")
+
+
+def _crop(w, W, H):
+    keep = (w["x"] < W) & (w["y"] < H)
+    return dict(x=dev(w["x"][keep]), y=dev(w["y"][keep]), t=dev(w["t"][keep]), t0=w["t0"])
+
+
+def test_capped_row_pass_equals_column_pass(ctx):
+    """A window whose squared distances are not exported and whose surface
+    saturates within 64 px takes the row pass that forms capped column
+    distances from the column masks itself (no column pass); with squared
+    distances exported, the column pass and the exact row pass run.  Edge
+    image and pyramid are bit-identical between the two and the pyramid
+    equals the oracle's: 346x260 and 1280x720 streams, alpha 3.5 (the
+    surface saturates 61 px out: the widest band) and 4.5 (beyond 64 px: the
+    column pass again), the bounded surface DS_LB, N_d / N_f at their
+    extremes, sensors of 61x23 (one chunk), 70x300 (narrower than a row
+    segment, five chunks) and 600x130, and a window with no events."""
+    cases = list(mixed_streams(n_low=2, n_hd=1, windows=2))
+    s = synth.c1_stream(3)
+    c1 = [s.window(k) for k in range(2)]
+    for over in (dict(alpha=3.5), dict(alpha=4.5), dict(surface=L.EBOF_SURFACE_BOUNDED), dict(n_d=0, n_f=5),
+                 dict(n_d=4, n_f=1)):
+        cases.append((L.ebof_params_default(s.W, s.H, **over), [_crop(w, s.W, s.H) for w in c1]))
+    cases.append((L.ebof_params_default(61, 23, levels=1), [_crop(c1[1], 61, 23), _crop(c1[1], 0, 0)]))
+    cases.append((L.ebof_params_default(70, 300, levels=2), [_crop(c1[0], 70, 300)]))
+    hd = synth.c3_streams()[10].window(0)
+    cases.append((L.ebof_params_default(600, 130, levels=2), [_crop(hd, 600, 130)]))
+    for p, evs in cases:
+        W, H = p.width, p.height
+        P = L.ebof_pyramid_floats(p)
+        for k, ev in enumerate(evs):
+            outs = []
+            for with_d2 in (True, False):
+                e = torch.empty(W * H, dtype=torch.uint8, device="cuda")
+                pr = torch.full((P,), float("nan"), dtype=torch.float32, device="cuda")
+                d2 = torch.empty(W * H, dtype=torch.int32, device="cuda") if with_d2 else None
+                L.ebof_window_surface(ctx, p, ev["x"], ev["y"], ev["t"], ev["t0"], e, pr, d2_out=d2)
+                outs.append((e, pr))
+            torch.cuda.synchronize()
+            assert torch.equal(outs[0][0], outs[1][0]), (W, H, k, "edge")
+            assert torch.equal(outs[0][1].view(torch.int32), outs[1][1].view(torch.int32)), (W, H, k, "pyramid")
+            if p.surface == L.EBOF_SURFACE_BOUNDED:
+                continue  # (the oracle's window takes eq. 1; the bounded surface is pinned in test_gpu_parity)
+            r = oracle.window(W, H, ev["x"].cpu().numpy(), ev["y"].cpu().numpy(), ev["t"].cpu().numpy(), ev["t0"],
+                              p.dt_us, p.n_d, p.n_f, float(np.float32(p.alpha)), p.levels)
+            assert np.array_equal(outs[1][0].cpu().numpy().reshape(H, W), r["Edf"]), (W, H, k)
+            np.testing.assert_allclose(outs[1][1].cpu().numpy(), r["pyr"], rtol=1e-6, atol=1e-7)
+        _say(f"capped row pass {W}x{H} (alpha {p.alpha:.2f}, surface kind {p.surface}, N_d {p.n_d}, "
+             f"N_f {p.n_f}): bit-identical")
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4, 8])
+def test_batch_capped_row_pass_equals_alone(ctx, tmp_path, rows):
+    """The batched form without squared distances (capped row pass, no
+    column pass) at every row count the tuner can pick: pyramids and flows
+    equal the stage calls' with squared distances exported."""
+    streams = mixed_streams(n_low=2, n_hd=1, windows=2)
+    ref = [alone(ctx, p, evs) for p, evs in streams]
+    outs = _outs_for(streams, ref, 1)
+    batch = _batch_of(streams, outs, 1)
+    for w in batch:
+        w["d2_out"] = None
+    path = tmp_path / "tune.txt"
+    vals = [rows, 64] + [4] * L.EBOF_TUNE_LEVELS + [0] * L.EBOF_TUNE_STAGES
+    path.write_text(L.batch_layout_key(batch) + "\t" + " ".join(map(str, vals)) + "\n")
+    L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, str(path))
+    try:
+        stream = torch.cuda.Stream()
+        _say(f"batch, capped row pass, rows={rows}")
+        L.ebof_run_batch(ctx, batch, stream=stream)
+        torch.cuda.synchronize()
+        for s_ in range(len(streams)):
+            r, o = ref[s_][1], outs[s_]
+            assert torch.equal(o["edge"], r[0]), (rows, s_, "edge")
+            assert torch.equal(o["pyr"], r[1]), (rows, s_, "pyramid")
+            assert torch.equal(o["flow"], r[3]), (rows, s_, "flow")
+    finally:
+        L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, None)
 
 
 def test_pipelined_driver_equals_sequential():
