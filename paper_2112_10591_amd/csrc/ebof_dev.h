@@ -18,7 +18,11 @@ constexpr int kMaxLevels = EBOF_MAX_LEVELS;
 constexpr int kPatch = EBOF_PATCH;
 constexpr uint16_t kGInf = 0xFFFF;  // "no edge pixel in this column"
 constexpr int kBlock = 256;         // threads per block of every kernel but the pyramid's
-constexpr int kPyrBlock = 512;      // threads per block of the pyramid chain
+#ifndef EBOF_PYR_TILE
+#define EBOF_PYR_TILE 8
+#endif
+constexpr int kPyrTile = EBOF_PYR_TILE;               // pyramid: deepest level's tile edge per block
+constexpr int kPyrBlock = kPyrTile >= 8 ? 512 : 256;  // threads per block of the pyramid chain
 
 // work-item granularity of each stage
 constexpr int kEventsPerItem = 512;   // scatter: events per block

@@ -533,12 +533,12 @@ __device__ __forceinline__ int reflect101(int i, int n) {
     return clampi(i, 0, n - 1);  // only reached for samples no output uses
 }
 
-// One launch builds up to three levels below level `from`.  A block owns an
-// 8x8 tile of the deepest level it builds; it stages the region of level
-// `from` that the tile depends on (85x85 for three levels) and computes each
-// intermediate level over the region the next one needs, writing only its own
-// part of every level.  Regions: R(deepest) = 8, R(k-1) = 2 R(k) + 3, origin
-// o(k-1) = 2 o(k) - 2.
+// One launch builds up to three levels below level `from`.  A block owns a
+// kPyrTile x kPyrTile tile (8x8) of the deepest level it builds; it stages the
+// region of level `from` that the tile depends on (85x85 for three levels)
+// and computes each intermediate level over the region the next one needs,
+// writing only its own part of every level.  Regions: R(deepest) = kPyrTile,
+// R(k-1) = 2 R(k) + 3, origin o(k-1) = 2 o(k) - 2.
 //
 // Borders: a level's outputs read its source only within two pixels of the
 // source image (positions -2 .. w+1), and reflect-101 maps those positions
@@ -579,29 +579,31 @@ __device__ __forceinline__ float binom25(const float* q) {
 template <bool B>
 __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                          int from) {
-    // one array, three regions (85x85 | 41x41 | 19x19); offsets rather than
-    // pointers keep every access in the LDS address space
-    __shared__ float sP[85 * 85 + 41 * 41 + 19 * 19];
+    // one array, three regions (R0 x R0 | R1 x R1 | R2 x R2: 85 | 41 | 19 for
+    // 8x8 tiles); offsets rather than pointers keep every access in the LDS
+    // address space
+    constexpr int T = kPyrTile, R2c = 2 * T + 3, R1c = 2 * R2c + 3, R0c = 2 * R1c + 3;
+    __shared__ float sP[R0c * R0c + R1c * R1c + R2c * R2c];
     const int32_t total = item_total<B>(ba, total_arg);
     for (int32_t item = xcd_item(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         int32_t local;
         const WinDesc* d = locate<B>(one, ba, item, local);
         const int nlev = min(kPyrChain, d->L - 1 - from);
         const LevelGeom gd = d->lv[from + nlev];
-        const int tiles_x = (gd.w + 7) / 8;
+        const int tiles_x = (gd.w + T - 1) / T;
         const int tx = local % tiles_x, ty = local / tiles_x;
         int R[kPyrChain + 1], ox[kPyrChain + 1], oy[kPyrChain + 1];
         int buf[kPyrChain + 1];
-        R[nlev] = 8;
-        ox[nlev] = 8 * tx;
-        oy[nlev] = 8 * ty;
+        R[nlev] = T;
+        ox[nlev] = T * tx;
+        oy[nlev] = T * ty;
         for (int k = nlev - 1; k >= 0; --k) {
             R[k] = 2 * R[k + 1] + 3;
             ox[k] = 2 * ox[k + 1] - 2;
             oy[k] = 2 * oy[k + 1] - 2;
         }
         for (int k = 0; k <= nlev; ++k)
-            buf[k] = (nlev - k == 1) ? 85 * 85 + 41 * 41 : (nlev - k == 2) ? 85 * 85 : 0;
+            buf[k] = (nlev - k == 1) ? R0c * R0c + R1c * R1c : (nlev - k == 2) ? R0c * R0c : 0;
         {
             // every position takes the value of its reflected position
             // (clamped as well: positions beyond the band are never read)
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
             const int in = buf[k - 1], outb = buf[k];
             const int Rin = R[k - 1], oxi = ox[k - 1], oyi = oy[k - 1];
             const int n = R[k];
-            const int span = 8 << (nlev - k);
+            const int span = T << (nlev - k);
             const int cx0 = span * tx, cy0 = span * ty;
             float* dst = d->pyr + gt.off;
             int r, cc, dr, dc;
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
                 if (X < -band || X >= gt.w + band || Y < -band || Y >= gt.h + band) continue;
                 const int Xr = reflect101(X, gt.w), Yr = reflect101(Y, gt.h);
                 const float* q = sP + in + (2 * Yr - 2 - oyi) * Rin + (2 * Xr - 2 - oxi);
-                const float v = Rin == 85 ? binom25<85>(q) : Rin == 41 ? binom25<41>(q) : binom25<19>(q);
+                const float v = Rin == R0c ? binom25<R0c>(q) : Rin == R1c ? binom25<R1c>(q) : binom25<R2c>(q);
                 if (k < nlev) sP[outb + r * n + cc] = v;
                 if (X == Xr && Y == Yr && X >= cx0 && X < cx0 + span && Y >= cy0 && Y < cy0 + span)
                     dst[(size_t)Y * gt.w + X] = v;
@@ -1200,7 +1202,7 @@ int32_t stage_items(const WinDesc& d, int stage, bool has_flow, bool zero, const
         const int from = (stage - kStPyr) * kPyrChain;
         if (from >= d.L - 1) return 0;
         const LevelGeom& g = d.lv[from + std::min(kPyrChain, d.L - 1 - from)];
-        return ((g.w + 7) / 8) * ((g.h + 7) / 8);
+        return ((g.w + kPyrTile - 1) / kPyrTile) * ((g.h + kPyrTile - 1) / kPyrTile);
     }
     if (stage >= kStDis && stage < kStDis + kMaxLevels) {
         const int l = stage - kStDis;
