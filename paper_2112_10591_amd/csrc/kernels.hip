@@ -426,7 +426,17 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
                         gv = min(gv, rr - (63 - __clzll(up)));
                     else if (mp)
                         gv = min(gv, rr + 1 + __clzll(mp));
-                    sG[k * ww + c] = k < nrows ? (uint32_t)(gv * gv) : 0x7fffffffu;
+                    if constexpr (NR % 2 == 0) {
+                        // rows 2j and 2j+1 as the halves of word j (row
+                        // beyond the image: 0, so never searched)
+                        const uint32_t v = k < nrows ? (uint32_t)(gv * gv) : 0u;
+                        if (k & 1)
+                            sG[(k >> 1) * ww + c] |= v << 16;
+                        else
+                            sG[(k >> 1) * ww + c] = v;
+                    } else {
+                        sG[k * ww + c] = k < nrows ? (uint32_t)(gv * gv) : 0x7fffffffu;
+                    }
                 }
             }
         } else {
@@ -446,6 +456,59 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         }
         __syncthreads();
         const int x = x0 + threadIdx.x;
+        if constexpr (NR % 2 == 0) {
+            if (loc) {
+                // Capped search on 16-bit pairs: every value stays below
+                // 2^15 (g^2 and r^2 at most 64^2 here; a column outside the
+                // image reads kFar), so two rows take one packed add and one
+                // packed min per candidate column.
+                typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+                constexpr int NP = NR / 2;
+                constexpr uint32_t kFar = 0x3FFF3FFFu;
+                if (x < W) {
+                    const uint32_t* row = sG - lo;  // rows 2j, 2j+1 at row + j * ww
+                    u16x2 best[NP];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) best[j] = __builtin_bit_cast(u16x2, row[j * ww + x]);
+                    constexpr int U = kRowUnroll;
+                    for (int r = 1; r <= R; r += U) {
+                        const uint32_t r2 = (uint32_t)(r * r);
+                        bool live = false;
+#pragma unroll
+                        for (int j = 0; j < NP; ++j) live |= r2 < best[j].x || r2 < best[j].y;
+                        if (!live || r2 >= (uint32_t)lut_n || (x - r < 0 && x + r >= W)) break;
+                        u16x2 cl[U][NP], cr[U][NP];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int rr = r + u;
+                            const bool lft = x - rr >= 0, rgt = x + rr < W;
+#pragma unroll
+                            for (int j = 0; j < NP; ++j) {
+                                cl[u][j] = __builtin_bit_cast(u16x2, lft ? row[j * ww + x - rr] : kFar);
+                                cr[u][j] = __builtin_bit_cast(u16x2, rgt ? row[j * ww + x + rr] : kFar);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const u16x2 rr2 = (u16x2)(unsigned short)((r + u) * (r + u));
+#pragma unroll
+                            for (int j = 0; j < NP; ++j)
+                                best[j] = __builtin_elementwise_min(best[j],
+                                                                    __builtin_elementwise_min(cl[u][j], cr[u][j]) + rr2);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        if (k < nrows) {
+                            const uint32_t b = (k & 1) ? best[k >> 1].y : best[k >> 1].x;
+                            d->pyr[(size_t)(y0 + k) * W + x] = b < (uint32_t)lut_n ? (lut_lds ? sLut[b] : lut[b]) : sat;
+                        }
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
+        }
         if (x < W) {
             const uint32_t* row = sG - lo;  // row k at row + k * ww, columns lo .. hi-1
             uint32_t best[NR];
@@ -519,6 +582,35 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         __syncthreads();
     }
 }
+
+// Copies the h x w window of img at (x0, y0) into LDS row-major with pitch
+// p: element (r, c) at dst[r * p + c] takes img(map(y0 + r, H), map(x0 + c,
+// W)), map placing positions outside the image (clamping for a replicated
+// border, reflect-101 for the pyramid).  The block's NT / 64 waves take rows
+// in turn and move each row in 64-column pieces straight from global memory
+// into LDS (lane i of a piece lands at word i), so no registers hold the data
+// and every load of the window is in flight at once.  The caller waits for
+// the loads (lds_load_wait) and synchronises the block before reading.
+template <int NT, class Map>
+__device__ __forceinline__ void stage_rows_lds_map(float* __restrict__ dst, const float* __restrict__ img, int W,
+                                                   int H, int x0, int y0, int w, int h, int p, Map map) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < w; c0 += 64) {
+        const int gx = map(x0 + c0 + lane, W);
+        if (c0 + lane < w) {
+            for (int r = wave; r < h; r += NT / 64)
+                __builtin_amdgcn_global_load_lds(img + (size_t)map(y0 + r, H) * W + gx,
+                                                 (__attribute__((address_space(3))) void*)(dst + r * p + c0), 4, 0, 0);
+        }
+    }
+}
+// ... with indices clamped into the image (replicated border)
+__device__ __forceinline__ void stage_rows_lds(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
+                                               int x0, int y0, int w, int h, int p) {
+    stage_rows_lds_map<kBlock>(dst, img, W, H, x0, y0, w, h, p, [](int i, int n) { return clampi(i, 0, n - 1); });
+}
+// waits for this wave's loads into LDS (and everything else outstanding)
+__device__ __forceinline__ void lds_load_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // --------------------------------------------------------------------------
 // Pyramid: level l+1 = 5x5 binomial (separable [1 4 6 4 1]) of level l,
@@ -608,14 +700,9 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
             // every position takes the value of its reflected position
             // (clamped as well: positions beyond the band are never read)
             const LevelGeom g0 = d->lv[from];
-            const float* __restrict__ src = d->pyr + g0.off;
-            const int oxs = ox[0], oys = oy[0];
-            auto at = [&](int r, int cc) {
-                const int X = clampi(reflect101(oxs + cc, g0.w), 0, g0.w - 1);
-                const int Y = clampi(reflect101(oys + r, g0.h), 0, g0.h - 1);
-                return src[(size_t)Y * g0.w + X];
-            };
-            stage_window<8, float, decltype(at), kPyrBlock>(sP + buf[0], R[0], R[0], at);
+            stage_rows_lds_map<kPyrBlock>(sP + buf[0], d->pyr + g0.off, g0.w, g0.h, ox[0], oy[0], R[0], R[0], R[0],
+                                          [](int i, int n) { return clampi(reflect101(i, n), 0, n - 1); });
+            lds_load_wait();
         }
         __syncthreads();
         for (int k = 1; k <= nlev; ++k) {
@@ -676,27 +763,6 @@ constexpr int kDisMargin = kPatch + 6;   // around the initial windows: covers a
 constexpr int kDisMargin0 = kPatch + 2;  // ... at level 0, where the initial displacement
                                          // (from a level of twice the resolution) drifts less
 
-// Copies the h x w window of img at (x0, y0), indices clamped into the image
-// (replicated border), into LDS row-major with pitch p: element (r, c) at
-// dst[r * p + c].  The block's waves take rows in turn and move each row in
-// 64-column pieces straight from global memory into LDS (lane i of a piece
-// lands at word i), so no registers hold the data and every load of the
-// window is in flight at once.  The caller waits for the loads
-// (lds_load_wait) and synchronises the block before reading.
-__device__ __forceinline__ void stage_rows_lds(float* __restrict__ dst, const float* __restrict__ img, int W, int H,
-                                               int x0, int y0, int w, int h, int p) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < w; c0 += 64) {
-        const int gx = clampi(x0 + c0 + lane, 0, W - 1);
-        if (c0 + lane < w) {
-            for (int r = wave; r < h; r += kBlock / 64)
-                __builtin_amdgcn_global_load_lds(img + (size_t)clampi(y0 + r, 0, H - 1) * W + gx,
-                                                 (__attribute__((address_space(3))) void*)(dst + r * p + c0), 4, 0, 0);
-        }
-    }
-}
-// waits for this wave's loads into LDS (and everything else outstanding)
-__device__ __forceinline__ void lds_load_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // sums over the LP lanes of a patch (LP = 8: quad swaps then the half-row
 // mirror; LP = 4: the two quad swaps), result in every lane
