@@ -562,9 +562,29 @@ def main():
         issue_ms = (time.perf_counter() - t0) * 1e3 / K  # host time to issue a window
         sync_all()
         torch.cuda.synchronize()
+        fps_py = K / (time.perf_counter() - t0)
+        issue_py = issue_ms
+        log(f"plain (pipelined, {NS} streams, issued from Python): {fps_py:.1f} frames/s "
+            f"({1e3 / fps_py:.4f} ms/window, host issue {issue_ms:.4f} ms/window)")
+        # (3) the same pipelined form issued natively (ebof_run_sequence: the
+        # same stage calls and counters, no Python between the calls), which
+        # gives the headline rate; it continues the sequence in the same ring
+        # on counter slots of its own
+        k1, k2 = k0 + K, k0 + K + 4 * NS
+        ring = [dict(edge=edge[b], pyr=pyr[b], flow=flows[b]) for b in range(NB)]
+        L.Sequence(ctx, p, [evs[k % len(evs)] for k in range(k1, k2)], ring, streams, slot0=32).run(k1, k2)  # untimed
+        sync_all()
+        nat = L.Sequence(ctx, p, [evs[k % len(evs)] for k in range(k2, k2 + K)], ring, streams, slot0=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nat.run(k2, k2 + K)
+        issue_ms = (time.perf_counter() - t0) * 1e3 / K
+        sync_all()
+        torch.cuda.synchronize()
         fps = K / (time.perf_counter() - t0)
-        log(f"plain (pipelined, {NS} streams): {fps:.1f} frames/s "
+        log(f"plain (pipelined, {NS} streams, ebof_run_sequence): {fps:.1f} frames/s "
             f"({1e3 / fps:.4f} ms/window, host issue {issue_ms:.4f} ms/window)")
+        k0 = k2
     elapsed = K / fps
 
     # ---------------- unloaded per-window latency (plain) -------------------
@@ -643,6 +663,9 @@ def main():
         "plain_form": "sequential" if args.sequential_only else "pipelined",
         "plain_streams": NS,
         "plain_host_issue_ms_per_window": issue_ms,
+        "plain_driver": None if args.sequential_only else "ebof_run_sequence (native)",
+        "plain_pipelined_python_frames_per_s": None if args.sequential_only else fps_py,
+        "plain_pipelined_python_host_issue_ms_per_window": None if args.sequential_only else issue_py,
         "plain_sequential_frames_per_s": fps_seq,
         "epe_vs_oracle_px": epe,
         "kernels_ms_per_window": {k: v["ms_per_window"] for k, v in breakdown.items()},
@@ -749,11 +772,11 @@ def path_roofline(bytes_per_window, fps, copy_gbs):
 
 
 def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair, copy_gbs):
-    """The 346x260 plain path, sequential and pipelined, on the 1280x720
-    section's streams."""
-    """346x260 plain path (the low-resolution config): sequential and
-    pipelined rates over the C1 stream's windows, and the EPE against the
-    oracle on its first pair (oracle_pair: (flow, mask) or None)."""
+    """346x260 plain path (the low-resolution config) on the 1280x720
+    section's streams: sequential and pipelined rates over the C1 stream's
+    windows (pipelined issued natively, and from Python for comparison),
+    and the EPE against the oracle on its first pair (oracle_pair: (flow,
+    mask) or None)."""
     import ctypes
     import torch
     p = L.ebof_params_default(346, 260, flags=L.EBOF_MASK_FLOW)
@@ -816,13 +839,28 @@ def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair, copy_gbs):
     t0 = time.perf_counter()
     pipelined(k0, k0 + steps)
     torch.cuda.synchronize()
+    fps_py = steps / (time.perf_counter() - t0)
+    # natively issued (ebof_run_sequence), continuing in the same ring on
+    # counter slots 48..
+    k0 += steps
+    ring = [dict(edge=edge[b], pyr=pyr[b], flow=flows[b]) for b in range(NB)]
+    L.Sequence(ctx, p, [evs[k % len(evs)] for k in range(k0, k0 + 4 * NS)], ring, streams, slot0=48).run(
+        k0, k0 + 4 * NS)
+    torch.cuda.synchronize()
+    k0 += 4 * NS
+    nat = L.Sequence(ctx, p, [evs[k % len(evs)] for k in range(k0, k0 + steps)], ring, streams, slot0=48)
+    t0 = time.perf_counter()
+    nat.run(k0, k0 + steps)
+    torch.cuda.synchronize()
     fps = steps / (time.perf_counter() - t0)
     ev_mean = float(np.mean([e["n"] for e in evs]))
     res = {"workload": f"346x260 plain single camera stream, {len(c1)} windows of 20k events, 40 segments "
                        "translating (+2.5, -1.5) px per window, 5% noise, L=3",
-           "frames_per_s": fps, "sequential_frames_per_s": fps_seq, "streams": NS, "timed_windows": steps,
+           "frames_per_s": fps, "driver": "ebof_run_sequence (native)", "python_driver_frames_per_s": fps_py,
+           "sequential_frames_per_s": fps_seq, "streams": NS, "timed_windows": steps,
            "epe_vs_oracle_px": epe, "path_roofline": path_roofline(path_bytes(ev_mean, P, N), fps, copy_gbs)}
-    log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined; EPE vs oracle {epe}")
+    log(f"C1 346x260 plain: {fps_seq:.0f} frames/s sequential, {fps:.0f} pipelined "
+        f"({fps_py:.0f} issued from Python); EPE vs oracle {epe}")
     return res
 
 

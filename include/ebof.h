@@ -416,6 +416,56 @@ int ebof_signal_read(ebof_ctx *ctx, int32_t slot, uint32_t *value);
 #define EBOF_MAX_OWNED_STREAMS 16
 int ebof_stream_create(ebof_ctx *ctx, void **hip_stream);
 
+/* ---- pipelined plain driver ------------------------------------------------------
+ * One camera stream's consecutive windows through the per-window path
+ * (Sec. III, Fig. 1: binning, denoising and filling, distance surface and
+ * pyramid of window k, then the flow from window k-1 to window k), issued
+ * natively and pipelined over n_streams HIP streams with the counters above,
+ * so that consecutive windows' blocks run concurrently.  Window k's
+ * ebof_window_surface runs on streams[k mod n_streams], then counter
+ * slot0 + (k mod n_streams) is set to 2k + 1; its ebof_flow (the previous
+ * window's pyramid as reference, masked to the previous window's E_df when
+ * p asks for it) follows on the same stream once counter
+ * slot0 + ((k-1) mod n_streams) reaches 2k - 1.
+ *
+ * win[i]: the events of window k_lo + i (device arrays, as for
+ * ebof_window_surface), for k_lo <= k < k_hi.  ring: n_ring > n_streams slots
+ * of caller-owned device buffers; window k writes its edge image (E_df) and
+ * pyramid into ring[k mod n_ring] and its flow into ring[k mod n_ring].flow
+ * (2 * width * height floats).  A slot is reused by window k + n_ring only
+ * after the flows that read it (k + 1's) and the one that writes its flow
+ * (k's) have completed: the host reads the counters and otherwise makes the
+ * stream wait, so the call never blocks on the device.  Asynchronous: it
+ * returns once everything is issued; the caller synchronises the streams
+ * before reading the outputs.
+ *
+ * Calls may continue a sequence: with k_lo > 0, ring[(k_lo - 1) mod n_ring]
+ * must hold window k_lo - 1's edge image and pyramid and all work of the
+ * earlier calls must have completed.  The counters only grow: window indices
+ * must increase across calls that share slots (a new sequence from k = 0
+ * takes other slots or another context), and 2 k_hi + 1 must fit in 32 bits.
+ * Window 0 gets no flow (its ring slot's flow is not written).
+ * Errors: EBOF_E_INVAL for NULL arrays, n_streams < 1, n_ring <= n_streams,
+ * k_hi < k_lo, k_lo < 0 or slots out of range; the first error of a stage
+ * call is returned as is (work issued before it stays issued). */
+typedef struct {
+    const uint16_t *x;
+    const uint16_t *y;
+    const int64_t *t;
+    int64_t n;
+    int64_t t0_us;
+} ebof_window_events;
+
+typedef struct {
+    uint8_t *edge;
+    float *pyr;
+    float *flow;
+} ebof_ring_slot;
+
+int ebof_run_sequence(ebof_ctx *ctx, const ebof_params *p, const ebof_window_events *win, int64_t k_lo,
+                      int64_t k_hi, const ebof_ring_slot *ring, int32_t n_ring, void *const *streams,
+                      int32_t n_streams, int32_t slot0);
+
 /* ---- evaluation (Sec. IV, evaluation metrics) -----------------------------------
  * Asynchronous on hip_stream; results land in device memory (out_dev) when
  * the stream reaches them.  Scratch comes from the context's arena, one per

@@ -90,6 +90,15 @@ class ebof_window(ctypes.Structure):
     ]
 
 
+class ebof_window_events(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("t0_us", ctypes.c_int64)]
+
+
+class ebof_ring_slot(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_void_p), ("pyr", ctypes.c_void_p), ("flow", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -138,6 +147,8 @@ def load():
         "ebof_stream_wait": ([P, i32, u32, P], ctypes.c_int),
         "ebof_signal_read": ([P, i32, ctypes.POINTER(u32)], ctypes.c_int),
         "ebof_stream_create": ([P, ctypes.POINTER(P)], ctypes.c_int),
+        "ebof_run_sequence": ([P, pp, ctypes.POINTER(ebof_window_events), i64, i64, ctypes.POINTER(ebof_ring_slot),
+                               i32, ctypes.POINTER(P), i32, i32], ctypes.c_int),
         "ebof_timing_enable": ([P, u32], ctypes.c_int),
         "ebof_timing_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
                              ctypes.c_int),
@@ -159,7 +170,7 @@ def exported_symbols():
             "ebof_window_scratch_bytes", "ebof_create", "ebof_destroy", "ebof_last_error",
             "ebof_bin_events", "ebof_edt_surface", "ebof_window_surface", "ebof_flow", "ebof_flow_warm", "ebof_flow_noalloc", "ebof_flow_errors", "ebof_fwl", "ebof_window_end", "ebof_window_surface_range", "ebof_run_batch", "ebof_set_tuning",
             "ebof_stream_open", "ebof_stream_close", "ebof_submit", "ebof_poll", "ebof_drain",
-            "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create",
+            "ebof_stream_signal", "ebof_stream_wait", "ebof_signal_read", "ebof_stream_create", "ebof_run_sequence",
             "ebof_timing_enable", "ebof_timing_read", "ebof_version", "ebof_filter_params_default",
             "ebof_filter_state_floats", "ebof_flow_filter"]
 
@@ -527,6 +538,42 @@ def ebof_stream_create(ctx):
     s = ctypes.c_void_p()
     _check(ctx.handle, ctx.lib.ebof_stream_create(ctx.handle, ctypes.byref(s)))
     return torch.cuda.ExternalStream(s.value)
+
+
+class Sequence:
+    """Arguments of ebof_run_sequence built once (device pointers of every
+    window's events, the ring slots, the streams), so that a call issues a
+    whole run of windows with one crossing into the library.
+    windows: dicts with x, y, t (device tensors) and t0 (window i of the
+    list is window k_lo + i of a run); ring: dicts with edge (uint8, W*H),
+    pyr (float32, pyramid floats) and flow (float32, 2*W*H); streams: torch
+    streams (e.g. from ebof_stream_create)."""
+
+    def __init__(self, ctx, p, windows, ring, streams, slot0=0):
+        self.ctx, self.p, self.slot0 = ctx, p, int(slot0)
+        N = p.width * p.height
+        P = ebof_pyramid_floats(p)
+        self.win = (ebof_window_events * max(1, len(windows)))()
+        for i, w in enumerate(windows):
+            n = int(w["x"].numel())
+            self.win[i] = ebof_window_events(_dev(w["x"], torch.uint16, n, "x"), _dev(w["y"], torch.uint16, n, "y"),
+                                             _dev(w["t"], torch.int64, n, "t"), n, int(w["t0"]))
+        self.ring = (ebof_ring_slot * len(ring))()
+        for i, r in enumerate(ring):
+            self.ring[i] = ebof_ring_slot(_dev(r["edge"], torch.uint8, N, "edge"), _dev(r["pyr"], torch.float32, P, "pyr"),
+                                          _dev(r["flow"], torch.float32, 2 * N, "flow"))
+        self.streams = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
+        self.n_win, self.n_ring, self.n_streams = len(windows), len(ring), len(streams)
+
+    def run(self, k_lo, k_hi):
+        """Issues windows k_lo .. k_hi-1 (the events of window k_lo + i are
+        windows[i])."""
+        if k_hi - k_lo > self.n_win:
+            raise ValueError("more windows than the sequence holds")
+        lib = self.ctx.lib
+        _check(self.ctx.handle, lib.ebof_run_sequence(self.ctx.handle, ctypes.byref(self.p), self.win, int(k_lo),
+                                                      int(k_hi), self.ring, self.n_ring, self.streams, self.n_streams,
+                                                      self.slot0))
 
 
 def ebof_timing_enable(ctx, kernels):

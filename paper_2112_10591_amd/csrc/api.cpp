@@ -958,6 +958,55 @@ int ebof_signal_read(ebof_ctx* ctx, int32_t slot, uint32_t* value) {
     return EBOF_OK;
 }
 
+// The pipelined plain driver: the per-window stage calls of one camera
+// stream, window k on stream k mod n_streams, ordered by the counters.  A
+// flow j is known complete once window j + n_streams (issued after it on
+// the same stream) has stored its counter value.
+int ebof_run_sequence(ebof_ctx* ctx, const ebof_params* p, const ebof_window_events* win, int64_t k_lo, int64_t k_hi,
+                      const ebof_ring_slot* ring, int32_t n_ring, void* const* streams, int32_t n_streams,
+                      int32_t slot0) {
+    int rc = ctx_ok(ctx);
+    if (rc) return rc;
+    if (!p || !win || !ring || !streams || n_streams < 1 || n_ring <= n_streams || k_lo < 0 || k_hi < k_lo ||
+        slot0 < 0 || slot0 > EBOF_SIGNAL_SLOTS - n_streams || 2 * k_hi + 1 > (int64_t)UINT32_MAX) {
+        set_error("ebof_run_sequence: NULL array, n_ring <= n_streams, bad window range or slots out of range");
+        return EBOF_E_INVAL;
+    }
+    std::vector<uint32_t> seen((size_t)n_streams, 0u);
+    auto flow_done = [&](int64_t j) {
+        const int f = (int)(j % n_streams);
+        const uint32_t need = (uint32_t)(2 * (j + n_streams) + 1);
+        if (seen[f] < need) {
+            uint32_t v = 0;
+            if (ebof_signal_read(ctx, slot0 + f, &v) == EBOF_OK) seen[f] = v;
+        }
+        return seen[f] >= need;
+    };
+    for (int64_t k = k_lo; k < k_hi; ++k) {
+        const int i = (int)(k % n_streams);
+        void* st = streams[i];
+        // the flows that last read ring slot k mod n_ring (one on this stream
+        // is ordered before window k already)
+        for (int64_t j = k - n_ring; j <= k - n_ring + 1; ++j) {
+            if (j < std::max<int64_t>(1, k_lo) || j % n_streams == i || flow_done(j)) continue;
+            if ((rc = ebof_stream_wait(ctx, slot0 + (int)(j % n_streams), (uint32_t)(2 * (j + n_streams) + 1), st)))
+                return rc;
+        }
+        const ebof_window_events& e = win[k - k_lo];
+        const ebof_ring_slot& b = ring[k % n_ring];
+        if ((rc = ebof_window_surface(ctx, p, e.x, e.y, e.t, e.n, e.t0_us, b.edge, nullptr, nullptr, b.pyr, st)))
+            return rc;
+        if ((rc = ebof_stream_signal(ctx, slot0 + i, (uint32_t)(2 * k + 1), st))) return rc;
+        if (k > 0) {
+            if (k - 1 >= k_lo && (rc = ebof_stream_wait(ctx, slot0 + (int)((k - 1) % n_streams), (uint32_t)(2 * k - 1), st)))
+                return rc;
+            const ebof_ring_slot& bp = ring[(k - 1) % n_ring];
+            if ((rc = ebof_flow(ctx, p, bp.pyr, b.pyr, bp.edge, b.flow, st))) return rc;
+        }
+    }
+    return EBOF_OK;
+}
+
 int ebof_stream_create(ebof_ctx* ctx, void** hip_stream) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;

@@ -234,6 +234,46 @@ def test_pipelined_driver_equals_sequential():
         c.close()
 
 
+def test_native_sequence_equals_sequential():
+    """ebof_run_sequence (the pipelined plain driver issued natively: window k
+    on stream k mod 4, a ring of 5 buffer slots) gives every window the flow
+    of the sequential stage calls, also when a second call continues the
+    sequence; and it rejects a ring no longer than the stream count and a
+    reversed window range."""
+    import ctypes
+    c = L.ebof_create(arena_bytes=1 << 30)
+    try:
+        s = synth.c1_stream(0)
+        nwin, NB = 20, 5
+        wins = [s.window(k) for k in range(nwin)]
+        p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+        N, P = s.W * s.H, L.ebof_pyramid_floats(p)
+        evs = [dict(x=dev(w["x"]), y=dev(w["y"]), t=dev(w["t"]), t0=w["t0"]) for w in wins]
+        ref = alone(c, p, evs)
+        streams = [L.ebof_stream_create(c) for _ in range(4)]
+        ring = [dict(edge=torch.empty(N, dtype=torch.uint8, device="cuda"),
+                     pyr=torch.empty(P, dtype=torch.float32, device="cuda"),
+                     flow=torch.full((2 * N,), float("nan"), dtype=torch.float32, device="cuda")) for _ in range(NB)]
+        torch.cuda.synchronize()
+        for lo, hi in ((0, 12), (12, nwin)):
+            L.Sequence(c, p, evs[lo:hi], ring, streams, slot0=8).run(lo, hi)
+            torch.cuda.synchronize()
+            for k in range(max(1, hi - NB), hi):
+                assert torch.equal(ring[k % NB]["flow"], ref[k][3]), (lo, hi, k)
+                assert torch.equal(ring[k % NB]["pyr"], ref[k][1]) and torch.equal(ring[k % NB]["edge"], ref[k][0])
+        seq = L.Sequence(c, p, evs[:4], ring[:4], streams, slot0=8)
+        assert c.lib.ebof_run_sequence(c.handle, ctypes.byref(p), seq.win, 20, 24, seq.ring, 4, seq.streams, 4,
+                                       8) == L.EBOF_E_INVAL
+        assert c.lib.ebof_run_sequence(c.handle, ctypes.byref(p), seq.win, 24, 20, seq.ring, 4, seq.streams, 3,
+                                       8) == L.EBOF_E_INVAL
+        assert c.lib.ebof_run_sequence(c.handle, ctypes.byref(p), seq.win, 20, 24, seq.ring, 4, seq.streams, 3,
+                                       L.EBOF_SIGNAL_SLOTS - 2) == L.EBOF_E_INVAL
+        _say(f"native sequence: {nwin} windows in two calls, ring {NB}, 4 streams")
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 def test_stage_calls_across_stamp_wrap():
     """A stage scratch marks a window's pixels with a stamp 1..255 and clears
     its staging image when the stamp wraps: 262 windows on one stream
