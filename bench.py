@@ -301,29 +301,43 @@ def cpu_oracle_baseline(p, c2, n_single, n_threads):
 
     ns = max(1, n_single)
     t0 = time.time()
+    tw = time.time()
     rs = [win(0)]
+    t_win, t_flow = time.time() - tw, 0.0
     flows = {}
     for k in range(1, ns + 1):
+        tw = time.time()
         rs.append(win(k))
+        tf = time.time()
         flows[k] = (flow(rs[k - 1], rs[k]), rs[k - 1]["Edf"].astype(bool))
+        t_win += tf - tw
+        t_flow += time.time() - tf
         rs[k - 1] = None
     dt1 = time.time() - t0
-    log(f"cpu oracle, 1 thread: {ns / dt1:.3f} frames/s over {dt1:.1f}s")
+    log(f"cpu oracle, 1 thread: {ns / dt1:.3f} frames/s over {dt1:.1f}s "
+        f"(window stage {1e3 * t_win / (ns + 1):.0f} ms, flow {1e3 * t_flow / ns:.0f} ms)")
     nt = max(1, n_threads)
     nm = 2 * nt  # flows in the threaded sample: two per thread
     base = ns + 1
     t0 = time.time()
     with cf.ThreadPoolExecutor(nt) as ex:
         ws = list(ex.map(win, [(base + k) % len(c2) for k in range(nm + 1)]))
+        tf = time.time()
         list(ex.map(lambda k: flow(ws[k], ws[k + 1]), range(nm)))
     dtn = time.time() - t0
+    dtw, dtf = tf - t0, time.time() - tf
     log(f"cpu oracle, {nt} threads: {nm / dtn:.3f} frames/s over {dtn:.1f}s")
     cpu = {"value": nm / dtn, "unit": "frames/s", "cores": nt, "kind": "oracle",
            "sample": f"{nm + 1} consecutive 1280x720 windows of 300k events (the first primes), full path per "
                      f"window incl. flow, plain C oracle on {nt} threads (windows, then flows, in parallel), "
                      f"{dtn:.1f}s",
+           "per_stage_windows_per_s": {"window (edge image through pyramid, Sec. III-A to III-C)": (nm + 1) / dtw,
+                                       "flow (Sec. III-D)": nm / dtf},
            "single_thread": {"value": ns / dt1, "cores": 1,
-                             "sample": f"{ns + 1} consecutive windows, one thread, {dt1:.1f}s"},
+                             "sample": f"{ns + 1} consecutive windows, one thread, {dt1:.1f}s",
+                             "per_stage_windows_per_s": {
+                                 "window (edge image through pyramid, Sec. III-A to III-C)": (ns + 1) / t_win,
+                                 "flow (Sec. III-D)": ns / t_flow}},
            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count()}
     return cpu, flows
 
