@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json and profiles/hbm_traffic_1280x720_plain.md from the "
                          "FETCH_SIZE and WRITE_SIZE passes over PROFILE_CMD --copy-calib 256, then exit")
+    ap.add_argument("--summarize-batch-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="write profiles/kernels_batch16_mixed.md from a rocprofv3 kernel trace of "
+                         "BATCH_PROFILE_CMD and that run's bench.py line, then exit (no GPU needed)")
     ap.add_argument("--sequential-only", action="store_true",
                     help="time only the sequential plain form (value = its rate); for counter runs, "
                          "whose per-dispatch serialisation does not mix with cross-stream waits")
@@ -147,6 +150,64 @@ def summarize_trace(trace_dir, bench_json):
             "by each launch's own dispatch latency inside its bracket (which a trace does not count) and by the "
             "run-to-run spread of the subtracted pair; the roofline uses the live figure."]
     path = os.path.join(ROOT, "profiles", "kernels_1280x720_plain.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(f"wrote {path}")
+
+
+# The command the batched-form profile is taken over (the 16-window batch of
+# 10 x 346x260 + 6 x 1280x720; the plain section kept short).
+BATCH_PROFILE_CMD = ("python3 bench.py --steps 20 --warmup 4 --no-cpu-baseline --no-serving --no-c1 "
+                     "--sequential-only")
+
+
+def summarize_batch_trace(trace_dir, bench_json):
+    """profiles/kernels_batch16_mixed.md: per-kernel dispatch times of the
+    batched form (the `<true, ...>` kernels) from a `rocprofv3 --kernel-trace`
+    run of BATCH_PROFILE_CMD, medians over the dispatches (the tuner's first
+    launches of other shapes included), and the EDT row pass's and the
+    pyramid's algorithmic bytes per batch over those medians."""
+    import collections
+    durs = collections.OrderedDict()
+    for r in _csv_rows(trace_dir, "run_kernel_trace.csv"):
+        name = r["Kernel_Name"]
+        if "ebof::" not in name or "<true" not in name:
+            continue
+        short = name.replace("void ebof::", "").split("(")[0]
+        durs.setdefault(short, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    with open(bench_json) as f:
+        line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
+    bat = json.loads(line)["batched"]
+    out = ["# Kernel time, batched form: 16 windows (10 x 346x260 L3 + 6 x 1280x720 L4) per launch", "",
+           "Command (from the repository root, `TMPDIR=/tmp`):", "", "```",
+           f"rocprofv3 --kernel-trace --stats --output-format csv -d {trace_dir} -o run -- {BATCH_PROFILE_CMD} "
+           f"> {bench_json}", f"python3 bench.py --summarize-batch-trace {trace_dir} {bench_json}",
+           "```", "",
+           "Every stage is one launch over all 16 windows (one captured graph per batch). Medians over the "
+           "run's dispatches; the tuner's first launches of other shapes are among them.", "",
+           "| kernel | dispatches | median µs | p10 µs | p90 µs |", "|---|---:|---:|---:|---:|"]
+    med = {}
+    for k, v in sorted(durs.items(), key=lambda kv: -float(np.median(kv[1]))):
+        a = np.array(v)
+        med[k] = float(np.median(a))
+        out.append(f"| `{k}` | {len(a)} | {med[k]:.2f} | {np.percentile(a, 10):.2f} | {np.percentile(a, 90):.2f} |")
+    out += ["", "Against the HBM peak (8 TB/s), algorithmic bytes per batch over the median launch of the shape "
+            "the tuner chose (the most dispatched one):", "",
+            "| kernel | algorithmic MB per batch | median µs | TB/s | fraction of peak |", "|---|---:|---:|---:|---:|"]
+    for key, prefix in (("edt_rows", "k_edt_rows"), ("pyr_down", "k_pyr_chain")):
+        hb = bat.get("hbm", {}).get(key)
+        ks = [k for k in med if k.startswith(prefix)]
+        if not hb or not ks:
+            continue
+        k = max(ks, key=lambda n: len(durs[n]))  # the tuned shape: the one the timed batches run
+        m = med[k]
+        tbs = hb["bytes_per_batch"] / (m * 1e-6) / 1e12
+        out.append(f"| `{k}` | {hb['bytes_per_batch'] / 1e6:.1f} | {m:.2f} | {tbs:.2f} | "
+                   f"{tbs * 1e12 / (HBM_PEAK_GBS * 1e9):.3f} |")
+    out += ["", "EDT row pass: column masks in (1/8 B per pixel) and surface out (4 B); pyramid: 4 B read per "
+            "pixel of each source level and 4 B written per pixel of each level built. Both are bound by the "
+            "latency of their per-item chains, not by bandwidth."]
+    path = os.path.join(ROOT, "profiles", "kernels_batch16_mixed.md")
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print(f"wrote {path}")
@@ -397,6 +458,9 @@ def main():
     args = parse()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_batch_trace:
+        summarize_batch_trace(*args.summarize_batch_trace)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
