@@ -122,7 +122,8 @@ def test_capped_row_pass_equals_column_pass(ctx):
     surface saturates 61 px out: the widest band) and 4.5 (beyond 64 px: the
     column pass again), the bounded surface DS_LB, N_d / N_f at their
     extremes, sensors of 61x23 (one chunk), 70x300 (narrower than a row
-    segment, five chunks) and 600x130, and a window with no events."""
+    segment, five chunks), 600x130 and the smallest ones (8x8, 9x130,
+    300x9: the band wider than the image), and a window with no events."""
     cases = list(mixed_streams(n_low=2, n_hd=1, windows=2))
     s = synth.c1_stream(3)
     c1 = [s.window(k) for k in range(2)]
@@ -131,6 +132,8 @@ def test_capped_row_pass_equals_column_pass(ctx):
         cases.append((L.ebof_params_default(s.W, s.H, **over), [_crop(w, s.W, s.H) for w in c1]))
     cases.append((L.ebof_params_default(61, 23, levels=1), [_crop(c1[1], 61, 23), _crop(c1[1], 0, 0)]))
     cases.append((L.ebof_params_default(70, 300, levels=2), [_crop(c1[0], 70, 300)]))
+    for (w_, h_) in ((8, 8), (9, 130), (300, 9)):
+        cases.append((L.ebof_params_default(w_, h_, levels=1, n_d=0), [_crop(c1[0], w_, h_), _crop(c1[1], w_, h_)]))
     hd = synth.c3_streams()[10].window(0)
     cases.append((L.ebof_params_default(600, 130, levels=2), [_crop(hd, 600, 130)]))
     for p, evs in cases:
