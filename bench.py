@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--summarize-batch-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="write profiles/kernels_batch16_mixed.md from a rocprofv3 kernel trace of "
                          "BATCH_PROFILE_CMD and that run's bench.py line, then exit (no GPU needed)")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="PMC_DIR",
+                    help="write profiles/sq_counters_1280x720_plain.md from rocprofv3 --pmc passes of SQ_ "
+                         "counters over PROFILE_CMD, then exit (no GPU needed)")
     ap.add_argument("--sequential-only", action="store_true",
                     help="time only the sequential plain form (value = its rate); for counter runs, "
                          "whose per-dispatch serialisation does not mix with cross-stream waits")
@@ -208,6 +211,50 @@ def summarize_batch_trace(trace_dir, bench_json):
             "pixel of each source level and 4 B written per pixel of each level built. Both are bound by the "
             "latency of their per-item chains, not by bandwidth."]
     path = os.path.join(ROOT, "profiles", "kernels_batch16_mixed.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(f"wrote {path}")
+
+
+SQ_PASSES = ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS "
+             "SQ_WAIT_INST_ANY SQ_WAIT_ANY",
+             "SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_INSTS_VMEM_RD SQ_ACTIVE_INST_ANY SQ_BUSY_CU_CYCLES "
+             "SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_SALU")
+
+
+def summarize_sq(pmc_dirs):
+    """profiles/sq_counters_1280x720_plain.md: SQ counters per dispatch
+    (means over the run's dispatches of each kernel) from --pmc passes over
+    PROFILE_CMD, as rocprofv3 reports them, with per-wave instruction counts."""
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in pmc_dirs:
+        for r in _csv_rows(d, "run_counter_collection.csv"):
+            if "ebof::" not in r["Kernel_Name"]:
+                continue
+            short = r["Kernel_Name"].replace("void ebof::", "").replace("ebof::", "").split("(")[0]
+            vals[short][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    mean = {k: {c: float(np.mean(v)) for c, v in cs.items()} for k, cs in vals.items()}
+    cmds = [f"timeout -s KILL 180 rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- {PROFILE_CMD}"
+            for c, d in zip(SQ_PASSES, pmc_dirs)]
+    out = ["# SQ counters per dispatch, 1280x720 plain path (C2 windows)", "",
+           "Commands (from the repository root, `TMPDIR=/tmp`), one pass each:", "", "```", *cmds,
+           f"python3 bench.py --summarize-sq {' '.join(pmc_dirs)}", "```", "",
+           "Means over each kernel's dispatches of the values rocprofv3 reports (instruction counts are per "
+           "wave instruction, summed over the dispatch's waves; cycle counters in the counters' own units).", "",
+           "| kernel | waves | VALU instr / wave | LDS instr / wave | SALU instr / wave | VMEM reads / wave | "
+           "LDS bank-conflict cycles | LDS active cycles | wait-any / busy-CU cycles |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    order = sorted(mean, key=lambda k: -mean[k].get("SQ_BUSY_CU_CYCLES", 0))
+    for k in order:
+        m = mean[k]
+        w = max(1.0, m.get("SQ_WAVES", 1.0))
+        busy = m.get("SQ_BUSY_CU_CYCLES", 0.0)
+        out.append(f"| `{k}` | {w:.0f} | {m.get('SQ_INSTS_VALU', 0) / w:.0f} | {m.get('SQ_INSTS_LDS', 0) / w:.0f} | "
+                   f"{m.get('SQ_INSTS_SALU', 0) / w:.0f} | {m.get('SQ_INSTS_VMEM_RD', 0) / w:.1f} | "
+                   f"{m.get('SQ_LDS_BANK_CONFLICT', 0):.3g} | {m.get('SQ_ACTIVE_INST_LDS', 0):.3g} | "
+                   f"{(m.get('SQ_WAIT_ANY', 0) / busy) if busy else 0:.2f} |")
+    path = os.path.join(ROOT, "profiles", "sq_counters_1280x720_plain.md")
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print(f"wrote {path}")
@@ -458,6 +505,9 @@ def main():
     args = parse()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq)
         return
     if args.summarize_batch_trace:
         summarize_batch_trace(*args.summarize_batch_trace)
