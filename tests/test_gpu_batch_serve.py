@@ -264,6 +264,13 @@ def test_native_sequence_equals_sequential():
             for k in range(max(1, hi - NB), hi):
                 assert torch.equal(ring[k % NB]["flow"], ref[k][3]), (lo, hi, k)
                 assert torch.equal(ring[k % NB]["pyr"], ref[k][1]) and torch.equal(ring[k % NB]["edge"], ref[k][0])
+        # an empty range issues nothing; a run of window 0 alone writes no flow
+        L.Sequence(c, p, evs[:1], ring, streams, slot0=20).run(0, 0)
+        ring[0]["flow"].fill_(float("nan"))
+        L.Sequence(c, p, evs[:1], ring, streams, slot0=20).run(0, 1)
+        torch.cuda.synchronize()
+        assert torch.isnan(ring[0]["flow"]).all()
+        assert torch.equal(ring[0]["pyr"], ref[0][1]) and torch.equal(ring[0]["edge"], ref[0][0])
         seq = L.Sequence(c, p, evs[:4], ring[:4], streams, slot0=8)
         assert c.lib.ebof_run_sequence(c.handle, ctypes.byref(p), seq.win, 20, 24, seq.ring, 4, seq.streams, 4,
                                        8) == L.EBOF_E_INVAL
