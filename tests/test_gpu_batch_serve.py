@@ -189,6 +189,38 @@ def test_batch_capped_row_pass_equals_alone(ctx, tmp_path, rows):
         L.ebof_set_tuning(ctx, L.EBOF_TUNE_AUTO, None)
 
 
+def test_batch_of_consecutive_windows_of_one_camera(ctx):
+    """Consecutive windows of one camera in one batch (the batched form
+    along time): window k's reference pyramid and mask are window k-1's,
+    produced by the same batch's preprocessing stages, which all run before
+    its flow stages.  Edge images, pyramids and flows equal the stage
+    calls', in two consecutive batches (graph recorded, then replayed)."""
+    s = synth.c1_stream(4)
+    p = L.ebof_params_default(s.W, s.H, flags=L.EBOF_MASK_FLOW)
+    evs = []
+    for k in range(17):
+        w = s.window(k)
+        evs.append(dict(x=dev(w["x"]), y=dev(w["y"]), t=dev(w["t"]), t0=w["t0"]))
+    ref = alone(ctx, p, evs)
+    N, P = s.W * s.H, L.ebof_pyramid_floats(p)
+    edge = [torch.empty(N, dtype=torch.uint8, device="cuda") for _ in range(17)]
+    pyr = [torch.empty(P, dtype=torch.float32, device="cuda") for _ in range(17)]
+    flow = [torch.full((2 * N,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(17)]
+    L.ebof_window_surface(ctx, p, evs[0]["x"], evs[0]["y"], evs[0]["t"], evs[0]["t0"], edge[0], pyr[0])
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for k0 in (1, 9):
+        batch = [dict(params=p, x=evs[k]["x"], y=evs[k]["y"], t=evs[k]["t"], t0_us=evs[k]["t0"], edge_out=edge[k],
+                      pyr_out=pyr[k], pyr_prev=pyr[k - 1], mask=edge[k - 1], flow_out=flow[k])
+                 for k in range(k0, k0 + 8)]
+        L.ebof_run_batch(ctx, batch, stream=stream)
+    torch.cuda.synchronize()
+    for k in range(1, 17):
+        assert torch.equal(edge[k], ref[k][0]) and torch.equal(pyr[k], ref[k][1]), k
+        assert torch.equal(flow[k], ref[k][3]), k
+    _say("consecutive windows of one camera: two batches of 8, bit-identical to the stage calls")
+
+
 def test_pipelined_driver_equals_sequential():
     """The benchmark's pipelined plain driver (each window's surface call and
     flow on stream k mod 4, ordered by the context counters, a buffer ring of
