@@ -983,8 +983,10 @@ def bench_c1(L, ctx, c1, steps, dev, streams, oracle_pair, copy_gbs):
     fps = steps / (time.perf_counter() - t0)
     # the batched form along time: G consecutive windows of the camera per
     # ebof_run_batch call on one stream (window k's reference pyramid comes
-    # from the same batch's preprocessing), a ring of G + 2 buffer slots
-    G = 16
+    # from the same batch's preprocessing), a ring of G + 2 buffer slots;
+    # a group forms only from windows already queued (a recording, or a
+    # camera the consumer has fallen behind), so it trades latency for rate
+    G = 32
     NBg = G + 2
     k0 += steps
     torch.cuda.synchronize()
