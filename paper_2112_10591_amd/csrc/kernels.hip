@@ -734,22 +734,17 @@ __global__ __launch_bounds__(kPyrBlock) void k_pyr_chain(const WinDesc one, cons
 }
 
 // --------------------------------------------------------------------------
-// Dense inverse search.  The template gradients and the regularised Hessian
-// and its inverse are formed in double (once per patch); the initial
-// displacement from the coarser level is densified as at level 0 (single
-// precision, exact sample split); the iterations run in single precision.
+// Dense inverse search.  The template gradients and the Hessian's sums are
+// formed in single precision, the regularised Hessian's inverse in double
+// (once per patch); the initial displacement from the coarser level is
+// densified as at level 0 (single precision, exact sample split); the
+// iterations run in single precision.
 // With the Hessian regularised by lambda*I the step is bounded by
 // |b| / lambda, so single-precision rounding of the residual sums (relative
 // 2^-24 of sums of order one) moves a patch by far less than the endpoint
 // tolerance of the flow.
 // --------------------------------------------------------------------------
 // (every lane is a valid source for these patterns: no old value needed)
-template <int CTRL>
-__device__ __forceinline__ double dppd(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
 template <int CTRL>
 __device__ __forceinline__ float dppf(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -771,13 +766,6 @@ __device__ __forceinline__ float redf(float v) {
     v += dppf<0xB1>(v);
     v += dppf<0x4E>(v);
     if constexpr (LP == 8) v += dppf<0x141>(v);
-    return v;
-}
-template <int LP>
-__device__ __forceinline__ double redd(double v) {
-    v += dppd<0xB1>(v);
-    v += dppd<0x4E>(v);
-    if constexpr (LP == 8) v += dppd<0x141>(v);
     return v;
 }
 
@@ -907,32 +895,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // lane counts give the same bits and the launch shape never changes
         // a result.
         float fgx[CPL][kPatch], fgy[CPL][kPatch], tf[CPL][kPatch];
-        double hxx = 0.0, hxy = 0.0, hyy = 0.0;
+        double hxx, hxy, hyy;
         {
+            // gradients in single precision (the difference of two floats
+            // rounded once: the value a double difference rounded to float
+            // would give), the Hessian's sums too (relative error ~1e-6 of
+            // sums of order one; the inverse below is formed in double)
+            float fxx = 0.f, fxy = 0.f, fyy = 0.f;
             const float* base = sR + (oy - oyA + 1) * sw + (x - sx0);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                double sxx = 0.0, sxy = 0.0, syy = 0.0;
+                float sxx = 0.f, sxy = 0.f, syy = 0.f;
 #pragma unroll
                 for (int j = 0; j < kPatch; ++j) {
                     const float* q = base + j * sw + c;
                     tf[c][j] = q[0];
-                    const double gx = 0.5 * ((double)q[1] - (double)q[-1]);
-                    const double gy = 0.5 * ((double)q[sw] - (double)q[-sw]);
+                    const float gx = 0.5f * (q[1] - q[-1]);
+                    const float gy = 0.5f * (q[sw] - q[-sw]);
                     sxx += gx * gx;
                     sxy += gx * gy;
                     syy += gy * gy;
-                    fgx[c][j] = (float)gx;
-                    fgy[c][j] = (float)gy;
+                    fgx[c][j] = gx;
+                    fgy[c][j] = gy;
                 }
-                hxx = c ? hxx + sxx : sxx;
-                hxy = c ? hxy + sxy : sxy;
-                hyy = c ? hyy + syy : syy;
+                fxx = c ? fxx + sxx : sxx;
+                fxy = c ? fxy + sxy : sxy;
+                fyy = c ? fyy + syy : syy;
             }
+            hxx = (double)redf<LP>(fxx);
+            hxy = (double)redf<LP>(fxy);
+            hyy = (double)redf<LP>(fyy);
         }
-        hxx = redd<LP>(hxx);
-        hxy = redd<LP>(hxy);
-        hyy = redd<LP>(hyy);
         const double ha = hxx + lam, hc = hyy + lam;
         const double det = ha * hc - hxy * hxy;
         const double idet = 1.0 / det;
