@@ -1001,9 +1001,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         float ux = (float)u0x, uy = (float)u0y;
         const int iters = d->iters;
         float S[8] = {};  // SA, SB, SC, SD for the x gradient, then for the y gradient
+        float D[4] = {};  // SB - SA, SD - SC (x), then (y): formed with the sums
         int cix = INT32_MIN, ciy = INT32_MIN;
         for (int it = 0; it < iters; ++it) {
-            const float sxu = fminf(fmaxf(ux, -flim), flim), syu = fminf(fmaxf(uy, -flim), flim);
+            // (med3 clamps in one instruction, the same value as min(max()))
+            const float sxu = __builtin_amdgcn_fmed3f(ux, -flim, flim), syu = __builtin_amdgcn_fmed3f(uy, -flim, flim);
             const float fx = floorf(sxu), fy = floorf(syu);
             const float ax = sxu - fx, ay = syu - fy;
             const int ix = (int)fx, iy = (int)fy;
@@ -1055,9 +1057,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) S[k] = redf<LP>(S[k]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) D[k] = S[2 * k + 1] - S[2 * k];
             }
-            const float px_ = S[0] + ax * (S[1] - S[0]), qx_ = S[2] + ax * (S[3] - S[2]);
-            const float py_ = S[4] + ax * (S[5] - S[4]), qy_ = S[6] + ax * (S[7] - S[6]);
+            const float px_ = S[0] + ax * D[0], qx_ = S[2] + ax * D[1];
+            const float py_ = S[4] + ax * D[2], qy_ = S[6] + ax * D[3];
             const float bx = (px_ + ay * (qx_ - px_)) - fcx;
             const float by = (py_ + ay * (qy_ - py_)) - fcy;
             ux -= fia * bx + fib * by;
