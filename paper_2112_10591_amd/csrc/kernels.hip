@@ -994,9 +994,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // integer cell n = floor(u): with the cell's corner sums
         // SA = sum_j g_j I1(x_j + n), SB at n + (1, 0), SC at n + (0, 1),
         // SD at n + (1, 1), it is (SA + ax (SB - SA)) + ay ((SC + ax (SD -
-        // SC)) - (SA + ax (SB - SA))) - c.  The corner sums depend on the
-        // cell only, so a patch forms them when u enters a cell and reuses
-        // them while u stays there (the usual case once it converges).
+        // SC)) - (SA + ax (SB - SA))) - c, formed as P + ay (Q - P) with
+        // P = (SA - c) + ax (SB - SA) and Q = (SC - c) + ax (SD - SC).  The
+        // corner sums and their differences depend on the cell only, so a
+        // patch forms them when u enters a cell and reuses them while u
+        // stays there (the usual case once it converges).
         const float flim = (float)lim;
         float ux = (float)u0x, uy = (float)u0y;
         const int iters = d->iters;
@@ -1059,13 +1061,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 for (int k = 0; k < 8; ++k) S[k] = redf<LP>(S[k]);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) D[k] = S[2 * k + 1] - S[2 * k];
+                // c taken off the sums at the cell's corners y = 0 and 1 (b
+                // is still exactly 0 where I1 equals the template at an
+                // integer u)
+                S[0] -= fcx;
+                S[2] -= fcx;
+                S[4] -= fcy;
+                S[6] -= fcy;
             }
             const float px_ = S[0] + ax * D[0], qx_ = S[2] + ax * D[1];
             const float py_ = S[4] + ax * D[2], qy_ = S[6] + ax * D[3];
-            const float bx = (px_ + ay * (qx_ - px_)) - fcx;
-            const float by = (py_ + ay * (qy_ - py_)) - fcy;
-            ux -= fia * bx + fib * by;
-            uy -= fib * bx + fic * by;
+            const float bx = px_ + ay * (qx_ - px_);
+            const float by = py_ + ay * (qy_ - py_);
+            ux = fmaf(-fib, by, fmaf(-fia, bx, ux));
+            uy = fmaf(-fic, by, fmaf(-fib, bx, uy));
         }
         // outlier reset: back to the initial displacement when the patch
         // moved more than its size
