@@ -374,6 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_edt_cols(const WinDesc one, const Ba
 // capped g is at least lut_r^2.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t g_sq(uint32_t g) { return g == kGInf ? 0x7fffffffu : g * g; }
+// the capped search's 16-bit pair for a column outside the image: above any
+// candidate (g^2 and r^2 are at most 64^2 there), and with r^2 still below 2^15
+constexpr uint32_t kFarPair = 0x3FFF3FFFu;
 
 template <bool B, int NR>
 __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const BatchArgs ba,
@@ -399,7 +402,10 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
         const uint32_t cap = (exp_d2 || computed) ? 0xffffffffu : (uint32_t)lut_n;
         const bool loc = edt_local(*d);
         const int band = loc ? (d->lut_r + kRowUnroll - 1) / kRowUnroll * kRowUnroll : R;
-        const int lo = max(0, x0 - band), hi = min(W, x0 + kRowSeg + band);
+        // (the capped form stages its whole band, columns outside the image
+        // included, so that its search reads without bounds checks)
+        const int lo = loc ? x0 - band : max(0, x0 - band);
+        const int hi = loc ? x0 + kRowSeg + band : min(W, x0 + kRowSeg + band);
         const int ww = hi - lo;
         const uint16_t* __restrict__ g = d->g + (size_t)y0 * W;
         const float* __restrict__ lut = d->lut;
@@ -409,6 +415,17 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
             const int rr0 = y0 - ck * kChunk, lr = d->lut_r;
             const uint64_t* __restrict__ cm = d->colmask + lo;
             for (int c = threadIdx.x; c < ww; c += kBlock) {
+                if (lo + c < 0 || lo + c >= W) {  // outside the image: never the nearest
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        if constexpr (NR % 2 == 0) {
+                            if (!(k & 1)) sG[(k >> 1) * ww + c] = kFarPair;
+                        } else {
+                            sG[k * ww + c] = 0x7fffffffu;
+                        }
+                    }
+                    continue;
+                }
                 const uint64_t m = cm[(size_t)ck * W + c];
                 const uint64_t mp = ck > 0 ? cm[(size_t)(ck - 1) * W + c] : 0ull;
                 const uint64_t mn = ck + 1 < nch ? cm[(size_t)(ck + 1) * W + c] : 0ull;
@@ -460,11 +477,10 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
             if (loc) {
                 // Capped search on 16-bit pairs: every value stays below
                 // 2^15 (g^2 and r^2 at most 64^2 here; a column outside the
-                // image reads kFar), so two rows take one packed add and one
+                // image holds kFarPair), so two rows take one packed add and one
                 // packed min per candidate column.
                 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
                 constexpr int NP = NR / 2;
-                constexpr uint32_t kFar = 0x3FFF3FFFu;
                 if (x < W) {
                     const uint32_t* row = sG - lo;  // rows 2j, 2j+1 at row + j * ww
                     u16x2 best[NP];
@@ -476,16 +492,17 @@ __global__ __launch_bounds__(kBlock) void k_edt_rows(const WinDesc one, const Ba
                         bool live = false;
 #pragma unroll
                         for (int j = 0; j < NP; ++j) live |= r2 < best[j].x || r2 < best[j].y;
-                        if (!live || r2 >= (uint32_t)lut_n || (x - r < 0 && x + r >= W)) break;
+                        if (!live || r2 >= (uint32_t)lut_n) break;
+                        // (every radius read here lies in the staged band:
+                        // r + 3 <= band whenever r * r < lut_n <= lut_r^2)
                         u16x2 cl[U][NP], cr[U][NP];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const int rr = r + u;
-                            const bool lft = x - rr >= 0, rgt = x + rr < W;
 #pragma unroll
                             for (int j = 0; j < NP; ++j) {
-                                cl[u][j] = __builtin_bit_cast(u16x2, lft ? row[j * ww + x - rr] : kFar);
-                                cr[u][j] = __builtin_bit_cast(u16x2, rgt ? row[j * ww + x + rr] : kFar);
+                                cl[u][j] = __builtin_bit_cast(u16x2, row[j * ww + x - rr]);
+                                cr[u][j] = __builtin_bit_cast(u16x2, row[j * ww + x + rr]);
                             }
                         }
 #pragma unroll
