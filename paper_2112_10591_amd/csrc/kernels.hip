@@ -894,8 +894,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const float inv_s = 1.0f / (float)s;
             const Cover cx = cover_of(px, gc.w, gc.pnx, s, inv_s), cy = cover_of(py, gc.h, gc.pny, s, inv_s);
             float sw_, su, sv;
-            dens_sums(C1, gc.w, gc.h, px, py, C0[(size_t)py * gc.w + px], d->puv + gc.poff, gc.pnx, cx, cy, sw_, su,
-                      sv);
+            // (the densification's weighted mean at the patch centre:) the
+            // covering patches shared out over four lane slots (slot q % 4,
+            // in order), the slots' sums added as one tree (lanes ^ 1, then
+            // ^ 2 within a quad); with 8 lanes per patch lanes 4..7 repeat
+            // 0..3, so both lane counts form the same bits
+            {
+                const float c0v = C0[(size_t)py * gc.w + px];
+                const float2* __restrict__ pu = d->puv + gc.poff;
+                const int n = cx.n * cy.n;
+                sw_ = su = sv = 0.f;
+                for (int q = cg & 3; q < n; q += 4) {
+                    const int qy = q / cx.n, qx = q - qy * cx.n;
+                    const float2 uq = pu[(size_t)cover_index(cy, qy) * gc.pnx + cover_index(cx, qx)];
+                    const float w = dens_weight_f(dens_blend(dens_fetch(C1, gc.w, gc.h, px, py, uq.x, uq.y)) - c0v);
+                    sw_ += w;
+                    su += w * uq.x;
+                    sv += w * uq.y;
+                }
+                sw_ += dppf<0xB1>(sw_);
+                su += dppf<0xB1>(su);
+                sv += dppf<0xB1>(sv);
+                sw_ += dppf<0x4E>(sw_);
+                su += dppf<0x4E>(su);
+                sv += dppf<0x4E>(sv);
+            }
             u0x = 2.0 * (double)(su / sw_);
             u0y = 2.0 * (double)(sv / sw_);
         }
