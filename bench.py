@@ -146,12 +146,14 @@ def summarize_trace(trace_dir, bench_json):
     out += ["", "`k_dis_level` runs one launch per pyramid level (`<false, 8>`: 8 lanes per patch, levels "
             "3, 2, 1; `<false, 4>`: 4 lanes, level 0).",
             f"Over all of its dispatches the average is {dt / dn:.2f} µs per launch ({dt:.1f} µs / {dn} launches).",
-            "", "The same run's `bench.py` line measures it live in the sequential form, each launch bracketed by "
-            f"a pair of HIP events on its stream: {1e3 * roof['ms_per_launch_raw']:.2f} µs per launch raw, minus "
-            f"the cost of an empty pair on that stream ({1e3 * roof['event_pair_ms']:.2f} µs), "
+            "", "The same run's `bench.py` line measures it live in the sequential form, each window's launches "
+            "(its levels, back to back on one stream) bracketed by one pair of HIP events: "
+            f"{1e3 * roof['ms_per_launch_raw']:.2f} µs per launch raw, minus the cost of an empty pair on that "
+            f"stream ({1e3 * roof['event_pair_ms']:.2f} µs) once per window, "
             f"{1e3 * roof['ms_per_launch']:.2f} µs per launch over {roof['launches']} launches. The two differ "
-            "by each launch's own dispatch latency inside its bracket (which a trace does not count) and by the "
-            "run-to-run spread of the subtracted pair; the roofline uses the live figure."]
+            "by the dispatch gaps between the levels and the first level's dispatch latency (inside the bracket, "
+            "not counted by a trace) and by the run-to-run spread of the subtracted pair; the roofline uses the "
+            "live figure."]
     path = os.path.join(ROOT, "profiles", "kernels_1280x720_plain.md")
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
@@ -649,7 +651,7 @@ def main():
         log(f"EPE vs oracle on {len(errs)} pairs (reference edge pixels): {epe:.3e} px")
 
     # ---------------- per-kernel breakdown (warm-up, all kernels timed) ----
-    lib.ebof_timing_enable(h, (1 << len(L.KERNELS)) - 1)
+    L.ebof_timing_enable(ctx, L.KERNELS, span=True)
     for k in range(Wm):  # the sequential form: kernel times do not overlap
         step(k)
     sync_all()
@@ -664,9 +666,11 @@ def main():
     # ---------------- timed regions: plain path ----------------------------
     # (1) the strictly sequential form, one stream, with the dominant kernel
     # timed by HIP events around its launches (kernel times do not overlap
-    # here, so they are the kernel's own); (2) the pipelined form, untimed per
-    # kernel, which gives the headline rate.
-    lib.ebof_timing_enable(h, 1 << L.KERNELS.index(dominant))
+    # here, so they are the kernel's own; one pair per window brackets the
+    # kernel's launches of that window, e.g. the inverse search's levels, which
+    # run back to back); (2) the pipelined form, untimed per kernel, which
+    # gives the headline rate.
+    L.ebof_timing_enable(ctx, [dominant], span=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(Wm, Wm + K):
@@ -725,9 +729,9 @@ def main():
     lat = np.array(lat)
 
     # ---------------- roofline of the dominant kernel -----------------------
-    # The library brackets every launch of the kernel with a pair of HIP
-    # events; an empty pair on the same stream measures what the pair itself
-    # adds, subtracted once per launch.
+    # The library brackets the kernel's launches of each window with a pair of
+    # HIP events; an empty pair on the same stream measures what the pair
+    # itself adds, subtracted once per window.
     e0s = []
     for _ in range(64):
         ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -737,7 +741,7 @@ def main():
     streams[0].synchronize()
     pair_ms = float(np.median([a.elapsed_time(b) for a, b in e0s]))
     dom_ms_raw = dom_ms
-    dom_ms = max(dom_ms_raw - dom_cnt * pair_ms, 1e-9)
+    dom_ms = max(dom_ms_raw - K * pair_ms, 1e-9)
     per_launch_ms = dom_ms / max(1, dom_cnt)
     timing = {"ms_per_launch": per_launch_ms, "launches": dom_cnt,
               "ms_per_launch_raw": dom_ms_raw / max(1, dom_cnt), "event_pair_ms": pair_ms}

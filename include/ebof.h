@@ -558,7 +558,15 @@ int ebof_flow_filter(ebof_ctx *ctx, const ebof_params *p, const ebof_filter_para
  * right after it (the pair itself adds a fixed cost, which a caller can
  * measure with an empty pair); ebof_timing_read waits for them and returns
  * the total milliseconds and the launch count accumulated since the last
- * read (then resets).  Timing disables graph capture of the batched form. */
+ * read (then resets).  Timing disables graph capture of the batched form.
+ * With EBOF_TIMING_SPAN or-ed into the mask, the launches of a selected
+ * kernel that one call makes back to back on one stream (the inverse
+ * search's levels of ebof_flow) share one pair, recorded before the first
+ * and after the last, so that the kernels' own dispatch gaps, not a pair's
+ * wait for each launch, separate them; the launch count still counts each
+ * launch.  A pair's events come from a pool the context owns (created on
+ * demand, destroyed with it); if an event cannot be created, the launches
+ * run untimed. */
 #define EBOF_K_SCATTER 0
 #define EBOF_K_DENOISE_FILL 1
 #define EBOF_K_PACK_COLS 2
@@ -568,6 +576,7 @@ int ebof_flow_filter(ebof_ctx *ctx, const ebof_params *p, const ebof_filter_para
 #define EBOF_K_DIS_LEVEL 6
 #define EBOF_K_DENSIFY 7
 #define EBOF_K_COUNT 8
+#define EBOF_TIMING_SPAN 0x80000000u
 int ebof_timing_enable(ebof_ctx *ctx, uint32_t kernel_mask);
 int ebof_timing_read(ebof_ctx *ctx, int32_t kernel_id, double *total_ms,
                      int64_t *launches);

@@ -576,8 +576,13 @@ class Sequence:
                                                       self.slot0))
 
 
-def ebof_timing_enable(ctx, kernels):
-    mask = 0
+EBOF_TIMING_SPAN = 0x80000000
+
+
+def ebof_timing_enable(ctx, kernels, span=False):
+    """Time every launch of the named kernels (span: one event pair around
+    the launches of one kernel that a call makes back to back)."""
+    mask = EBOF_TIMING_SPAN if span else 0
     for k in kernels:
         mask |= 1 << KERNELS.index(k)
     return _check(ctx.handle, ctx.lib.ebof_timing_enable(ctx.handle, mask))

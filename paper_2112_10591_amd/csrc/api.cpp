@@ -259,41 +259,81 @@ static Scratch* stage_scratch(ebof_ctx* ctx, const Geom& g, hipStream_t st, int*
 // ---------------------------------------------------------------- timing
 // Kernel timing: while timed() runs f for a selected kernel, every launch
 // built (one_launch, batch_launch) takes an event pair recorded right before
-// and right after it on its stream.
+// and right after it on its stream.  In span mode the launches f makes (one
+// stream) are only counted, and one pair recorded around f brackets them all.
 struct TimingScope {
     ebof_ctx* ctx = nullptr;
     int kid = -1;
+    bool span = false;
+    int launches = 0;
 };
 static thread_local TimingScope tl_timing;
 
-static void attach_timing(Launch& L) {
-    ebof_ctx* ctx = tl_timing.ctx;
-    if (!ctx) return;
-    TimedPair tp;
-    tp.launches = 1;
-    std::lock_guard<std::mutex> lk(ctx->timing_mu);
+static bool take_pair(ebof_ctx* ctx, TimedPair& tp) {  // under timing_mu
     for (hipEvent_t* e : {&tp.a, &tp.b}) {
         if (!ctx->event_pool.empty()) {
             *e = ctx->event_pool.back();
             ctx->event_pool.pop_back();
         } else if (hipEventCreate(e) != hipSuccess) {
-            return;  // untimed launch rather than a failed one
+            if (e == &tp.b) ctx->event_pool.push_back(tp.a);
+            return false;  // untimed launches rather than failed ones
         }
     }
+    return true;
+}
+
+static void attach_timing(Launch& L) {
+    ebof_ctx* ctx = tl_timing.ctx;
+    if (!ctx) return;
+    if (tl_timing.span) {
+        ++tl_timing.launches;
+        return;
+    }
+    TimedPair tp;
+    tp.launches = 1;
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
+    if (!take_pair(ctx, tp)) return;
     ctx->timed[tl_timing.kid].push_back(tp);
     L.ev_start = tp.a;
     L.ev_stop = tp.b;
 }
 
 template <class F>
-static void timed(ebof_ctx* ctx, int kid, hipStream_t, F&& f) {
+static void timed(ebof_ctx* ctx, int kid, hipStream_t st, F&& f) {
     if (!(ctx->timing_mask.load(std::memory_order_relaxed) & (1u << kid))) {
         f();
         return;
     }
-    tl_timing = TimingScope{ctx, kid};
+    const bool span = ctx->timing_span.load(std::memory_order_relaxed);
+    TimedPair tp{};
+    if (span) {
+        std::lock_guard<std::mutex> lk(ctx->timing_mu);
+        if (!take_pair(ctx, tp)) {
+            f();
+            return;
+        }
+    }
+    if (span && hipEventRecord(tp.a, st) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(ctx->timing_mu);
+        ctx->event_pool.push_back(tp.a);
+        ctx->event_pool.push_back(tp.b);
+        f();
+        return;
+    }
+    tl_timing = TimingScope{ctx, kid, span, 0};
     f();
+    const int n = tl_timing.launches;
     tl_timing = TimingScope{};
+    if (!span) return;
+    const bool ok = hipEventRecord(tp.b, st) == hipSuccess;
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
+    if (ok && n > 0) {
+        tp.launches = n;
+        ctx->timed[kid].push_back(tp);
+    } else {
+        ctx->event_pool.push_back(tp.a);
+        ctx->event_pool.push_back(tp.b);
+    }
 }
 
 // stage calls launch one block per item with the default tile shapes
@@ -1379,6 +1419,7 @@ int ebof_run_batch(ebof_ctx* ctx, const ebof_window* w, int32_t n, void* hip_str
 int ebof_timing_enable(ebof_ctx* ctx, uint32_t kernel_mask) {
     int rc = ctx_ok(ctx);
     if (rc) return rc;
+    ctx->timing_span = (kernel_mask & EBOF_TIMING_SPAN) != 0;
     ctx->timing_mask = kernel_mask & ((1u << EBOF_K_COUNT) - 1);
     return EBOF_OK;
 }

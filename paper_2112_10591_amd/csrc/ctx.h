@@ -63,8 +63,8 @@ struct Lut {
 };
 
 struct TimedPair {
-    hipEvent_t a, b;  // stamped with one kernel's start and end
-    int launches;
+    hipEvent_t a, b;  // stamped before and after the launches they bracket
+    int launches;     // one, or in span mode those of one call
 };
 
 // Device descriptor table + pinned staging ring + captured graphs of one
@@ -131,6 +131,7 @@ struct ebof_ctx {
 
     // timing
     std::atomic<uint32_t> timing_mask{0};
+    std::atomic<bool> timing_span{false};  // one pair per call, not per launch
     std::mutex timing_mu;  // guards timed[] and event_pool (launches happen outside mu)
     std::vector<ebof::TimedPair> timed[EBOF_K_COUNT];
     std::vector<hipEvent_t> event_pool;

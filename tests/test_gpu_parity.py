@@ -181,6 +181,31 @@ def test_flow_zero_motion_exact(ctx):
     assert np.all(f == 0.0)
 
 
+def test_kernel_timing_per_launch_and_span(ctx):
+    """Kernel timing, with a pair per launch and with one pair around the
+    launches a call makes back to back (the levels of the inverse search),
+    counts every launch, reports positive times, resets on reading, and
+    leaves the flow bit for bit as the untimed call's."""
+    s = synth.c1_stream(0)
+    p = L.ebof_params_default(s.W, s.H)
+    g0 = gpu_window(ctx, p, s.window(0), d2=False)
+    g1 = gpu_window(ctx, p, s.window(1), d2=False)
+    want = gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"])
+    _say("kernel timing: per launch, then spans")
+    try:
+        for span in (False, True):
+            L.ebof_timing_enable(ctx, ["dis_level", "densify"], span=span)
+            for _ in range(3):
+                assert np.array_equal(gpu_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"]), want)
+            ms, cnt = L.ebof_timing_read(ctx, "dis_level")
+            assert cnt == 3 * p.levels and ms > 0.0, (span, ms, cnt)
+            ms, cnt = L.ebof_timing_read(ctx, "densify")
+            assert cnt == 3 and ms > 0.0, (span, ms, cnt)
+            assert L.ebof_timing_read(ctx, "dis_level") == (0.0, 0)
+    finally:
+        L.ebof_timing_enable(ctx, [])
+
+
 def test_flow_empty_windows_exact_zero(ctx):
     """A window with no events has the surface 1.0 everywhere: as the
     reference its template gradient is 0, so b = 0 and no patch moves; the
