@@ -836,7 +836,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // When only the masked flow is wanted, a level-0 item with no pixel
         // on the mask is not needed: a pixel's flow reads only the patches
         // that contain it, and the densification skips pixels off the mask.
-        if (level == 0 && (d->flags & EBOF_MASK_FLOW) && d->mask && !d->flow_keep && !d->ud) {
+        const bool mask_only = level == 0 && (d->flags & EBOF_MASK_FLOW) && d->mask && !d->flow_keep && !d->ud;
+        if (mask_only) {
             const int fx0 = min(kx0 * s, Wl - kPatch), fx1 = min(kx_last * s, Wl - kPatch) + kPatch;
             const int fy0 = min(ky0 * s, Hl - kPatch), fy1 = min(ky_last * s, Hl - kPatch) + kPatch;
             const int fw = fx1 - fx0, fn = fw * (fy1 - fy0);
@@ -850,6 +851,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int kxc = min(kx, kx_last), kyc = min(ky, ky_last);
         const int ox = min(kxc * s, Wl - kPatch), oy = min(kyc * s, Hl - kPatch);
         const int x = ox + cg * CPL;  // the lane's first column
+        // ... and within a needed item, a patch with no pixel on the mask is
+        // not needed either: its mask bytes (this lane's columns) are loaded
+        // here and arrive with the reference strip
+        uint32_t mbits = 1;
+        if (mask_only) {
+            const uint8_t* __restrict__ mp = d->mask + (size_t)oy * Wl + x;
+            mbits = 0;
+#pragma unroll
+            for (int j = 0; j < kPatch; ++j)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) mbits |= mp[(size_t)j * Wl + c];
+        }
 
         // ---- the reference strip: its loads are issued first and complete
         // while the initial displacement is formed
@@ -969,7 +982,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const double ha = hxx + lam, hc = hyy + lam;
         const double det = ha * hc - hxy * hxy;
         const double idet = 1.0 / det;
-        const float fia = (float)(hc * idet), fib = (float)(-hxy * idet), fic = (float)(ha * idet);
+        // a patch that no masked pixel reads keeps its initial displacement:
+        // a zero update, and its cell fixed from the start (below), so it
+        // never makes its wave form corner sums
+        const bool live = redf<LP>(mbits ? 1.f : 0.f) > 0.f;  // any lane of the patch
+        const float fia = live ? (float)(hc * idet) : 0.f, fib = live ? (float)(-hxy * idet) : 0.f,
+                    fic = live ? (float)(ha * idet) : 0.f;
         // c by the same single-precision chain, in the same order, as the
         // corner sum SA: at an integer u where I1 equals the template the
         // residual is exactly 0, so a patch that does not move stays exactly
@@ -1045,7 +1063,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         float S[8] = {};  // SA, SB, SC, SD for the x gradient, then for the y gradient
         float D[4] = {};  // SB - SA, SD - SC (x), then (y): formed with the sums
         int cix = INT32_MIN, ciy = INT32_MIN;
-        for (int it = 0; it < iters; ++it) {
+        if (!live) {
+            cix = (int)floorf(__builtin_amdgcn_fmed3f(ux, -flim, flim));
+            ciy = (int)floorf(__builtin_amdgcn_fmed3f(uy, -flim, flim));
+        }
+        // (a wave whose patches are all kept skips the iterations)
+        for (int it = __ballot(live) ? 0 : iters; it < iters; ++it) {
             // (med3 clamps in one instruction, the same value as min(max()))
             const float sxu = __builtin_amdgcn_fmed3f(ux, -flim, flim), syu = __builtin_amdgcn_fmed3f(uy, -flim, flim);
             const float fx = floorf(sxu), fy = floorf(syu);
