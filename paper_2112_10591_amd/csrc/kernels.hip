@@ -812,6 +812,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                   "reference strip too large");
     __shared__ float sR[kDisRH * kDisRP];
     __shared__ int sBox[kBlock / 64][4];
+    __shared__ int sCnt[kBlock / 64];        // needed patches per wave
+    __shared__ int sList[kBlock / LP];       // the item's needed patches, packed
     const int32_t total = item_total<B>(ba, total_arg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int prow = wave / WPR;                      // patch row within the item
@@ -831,38 +833,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int ky0 = kyi * PR, ky_last = min(ky0 + PR, pny) - 1;
         const int kx0 = seg * kPatchesPerItem;
         const int kx_last = min(kx0 + kPatchesPerItem, pnx) - 1;
-        const int ky = ky0 + prow, kx = kx0 + slot;
-        const bool valid = kx < pnx && ky < pny;
-        // When only the masked flow is wanted, a level-0 item with no pixel
+        int ky = ky0 + prow, kx = kx0 + slot;
+        bool valid = kx < pnx && ky < pny;
+        // When only the masked flow is wanted, a level-0 patch with no pixel
         // on the mask is not needed: a pixel's flow reads only the patches
         // that contain it, and the densification skips pixels off the mask.
+        // An item with no needed patch returns at once; the needed patches of
+        // the others are packed, in item order, into the first waves, and the
+        // waves left over (active false, the same for a whole wave) skip the
+        // initial displacement, the template and the iterations.  A needed
+        // patch runs the same arithmetic wherever it is packed.
         const bool mask_only = level == 0 && (d->flags & EBOF_MASK_FLOW) && d->mask && !d->flow_keep && !d->ud;
+        bool active = true;
         if (mask_only) {
-            const int fx0 = min(kx0 * s, Wl - kPatch), fx1 = min(kx_last * s, Wl - kPatch) + kPatch;
-            const int fy0 = min(ky0 * s, Hl - kPatch), fy1 = min(ky_last * s, Hl - kPatch) + kPatch;
-            const int fw = fx1 - fx0, fn = fw * (fy1 - fy0);
-            int any = 0;
-            for (int i = threadIdx.x; i < fn; i += kBlock) {
-                const int r = i / fw;
-                any |= d->mask[(size_t)(fy0 + r) * Wl + fx0 + (i - r * fw)];
-            }
-            if (!__syncthreads_or(any)) continue;
+            const int ox = min(min(kx, kx_last) * s, Wl - kPatch), oy = min(min(ky, ky_last) * s, Hl - kPatch);
+            const uint8_t* __restrict__ mp = d->mask + (size_t)oy * Wl + ox + cg * CPL;
+            uint32_t mb = 0;
+#pragma unroll
+            for (int j = 0; j < kPatch; ++j)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) mb |= mp[(size_t)j * Wl + c];
+            const bool need = valid && redf<LP>(mb ? 1.f : 0.f) > 0.f;  // any lane of the patch
+            const uint64_t bal = __ballot(need && cg == 0);
+            if (lane == 0) sCnt[wave] = __popcll(bal);
+            const int n = __syncthreads_count(need && cg == 0);
+            if (n == 0) continue;
+            int base = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) base += w < wave ? sCnt[w] : 0;
+            if (need && cg == 0) sList[base + __popcll(bal & ((1ull << lane) - 1ull))] = prow * kPatchesPerItem + slot;
+            __syncthreads();
+            const int ci = wave * PPW + lane / LP;  // this lane's packed patch
+            const int q = sList[ci < n ? ci : 0];
+            ky = ky0 + q / kPatchesPerItem;
+            kx = kx0 + q % kPatchesPerItem;
+            valid = ci < n;
+            active = wave * PPW < n;
         }
         const int kxc = min(kx, kx_last), kyc = min(ky, ky_last);
         const int ox = min(kxc * s, Wl - kPatch), oy = min(kyc * s, Hl - kPatch);
         const int x = ox + cg * CPL;  // the lane's first column
-        // ... and within a needed item, a patch with no pixel on the mask is
-        // not needed either: its mask bytes (this lane's columns) are loaded
-        // here and arrive with the reference strip
-        uint32_t mbits = 1;
-        if (mask_only) {
-            const uint8_t* __restrict__ mp = d->mask + (size_t)oy * Wl + x;
-            mbits = 0;
-#pragma unroll
-            for (int j = 0; j < kPatch; ++j)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) mbits |= mp[(size_t)j * Wl + c];
-        }
 
         // ---- the reference strip: its loads are issued first and complete
         // while the initial displacement is formed
@@ -874,10 +884,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
         // ---- initial displacement: twice the coarser dense flow at the
         // pixel nearest the patch centre, densified there from the coarser
-        // level's patch displacements as in the densification (every lane of
-        // the patch forms the same sums, so the lane count changes no bit)
+        // level's patch displacements as in the densification
         double u0x = 0.0, u0y = 0.0;
-        if (level == d->L - 1 && d->flow_init) {
+        if (!active) {
+            // (a wave with no patch to compute)
+        } else if (level == d->L - 1 && d->flow_init) {
             // warm start: the previous pair's level-0 flow at the pixel under
             // the patch centre, in pixels of this level (a power-of-two
             // scale, exact)
@@ -947,9 +958,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // tree (a lane's two columns first, then the lanes by DPP), so both
         // lane counts give the same bits and the launch shape never changes
         // a result.
-        float fgx[CPL][kPatch], fgy[CPL][kPatch], tf[CPL][kPatch];
-        double hxx, hxy, hyy;
-        {
+        float fgx[CPL][kPatch], fgy[CPL][kPatch];
+        double hxx = 1.0, hxy = 0.0, hyy = 1.0;
+        float fcx = 0.f, fcy = 0.f;
+        if (active) {
+            float tf[CPL][kPatch];
             // gradients in single precision (the difference of two floats
             // rounded once: the value a double difference rounded to float
             // would give), the Hessian's sums too (relative error ~1e-6 of
@@ -978,34 +991,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             hxx = (double)redf<LP>(fxx);
             hxy = (double)redf<LP>(fxy);
             hyy = (double)redf<LP>(fyy);
+            // c by the same single-precision chain, in the same order, as
+            // the corner sum SA: at an integer u where I1 equals the template
+            // the residual is exactly 0, so a patch that does not move stays
+            // exactly in place
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                float cx_ = 0.f, cy_ = 0.f;
+#pragma unroll
+                for (int j = 0; j < kPatch; ++j) {
+                    cx_ += fgx[c][j] * tf[c][j];
+                    cy_ += fgy[c][j] * tf[c][j];
+                }
+                fcx = c ? fcx + cx_ : cx_;
+                fcy = c ? fcy + cy_ : cy_;
+            }
+            fcx = redf<LP>(fcx);
+            fcy = redf<LP>(fcy);
         }
         const double ha = hxx + lam, hc = hyy + lam;
         const double det = ha * hc - hxy * hxy;
         const double idet = 1.0 / det;
-        // a patch that no masked pixel reads keeps its initial displacement:
-        // a zero update, and its cell fixed from the start (below), so it
-        // never makes its wave form corner sums
-        const bool live = redf<LP>(mbits ? 1.f : 0.f) > 0.f;  // any lane of the patch
+        // a lane that holds no needed patch (the tail of the last packed
+        // wave) keeps its initial displacement: a zero update, and its cell
+        // fixed from the start (below), so it never makes its wave form
+        // corner sums
+        const bool live = !mask_only || valid;
         const float fia = live ? (float)(hc * idet) : 0.f, fib = live ? (float)(-hxy * idet) : 0.f,
                     fic = live ? (float)(ha * idet) : 0.f;
-        // c by the same single-precision chain, in the same order, as the
-        // corner sum SA: at an integer u where I1 equals the template the
-        // residual is exactly 0, so a patch that does not move stays exactly
-        // in place
-        float fcx = 0.f, fcy = 0.f;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            float cx_ = 0.f, cy_ = 0.f;
-#pragma unroll
-            for (int j = 0; j < kPatch; ++j) {
-                cx_ += fgx[c][j] * tf[c][j];
-                cy_ += fgy[c][j] * tf[c][j];
-            }
-            fcx = c ? fcx + cx_ : cx_;
-            fcy = c ? fcy + cy_ : cy_;
-        }
-        fcx = redf<LP>(fcx);
-        fcy = redf<LP>(fcy);
 
         // ---- stage the search region of I1: the box of the patches'
         // initial windows, reduced over each wave's lanes, then over the
