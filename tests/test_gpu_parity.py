@@ -206,6 +206,43 @@ def test_kernel_timing_per_launch_and_span(ctx):
         L.ebof_timing_enable(ctx, [])
 
 
+@pytest.mark.parametrize("case", ["c1", "c2", "odd"])
+def test_masked_flow_equals_dense_flow_masked(ctx, case):
+    """With only the masked flow wanted, level 0 computes just the patches
+    that hold a mask pixel (packed into the first waves of each item); the
+    result must equal, bit for bit, the flow computed for every patch (the
+    dense flow kept before masking) with the mask applied afterwards.  C1
+    runs level 0 with 8 lanes per patch, C2 with 4, and the odd size has
+    clamped border patches on both axes."""
+    if case == "c2":
+        W, H = 1280, 720
+        evs = synth.generate("c2", 0, range(2), workers=2)
+    else:
+        s = synth.c1_stream(3)
+        W, H = (s.W, s.H) if case == "c1" else (203, 117)
+        evs = []
+        for k in range(2):
+            w = s.window(k)
+            keep = (w["x"] < W) & (w["y"] < H)
+            evs.append(dict(x=w["x"][keep], y=w["y"][keep], t=w["t"][keep], t0=w["t0"]))
+    p = L.ebof_params_default(W, H, flags=L.EBOF_MASK_FLOW)
+    g0 = gpu_window(ctx, p, evs[0], d2=False)
+    g1 = gpu_window(ctx, p, evs[1], d2=False)
+    _say(f"masked vs dense flow {case} ({W}x{H})")
+    f = torch.full((2 * W * H,), 7.0, dtype=torch.float32, device="cuda")
+    L.ebof_flow(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], f, mask=g0["_edge_dev"])
+    fk = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    dense = torch.empty(2 * W * H, dtype=torch.float32, device="cuda")
+    L.ebof_flow_warm(ctx, p, g0["_pyr_dev"], g1["_pyr_dev"], fk, flow_dense_out=dense, mask=g0["_edge_dev"])
+    torch.cuda.synchronize()
+    m = g0["_edge_dev"].cpu().numpy().reshape(H, W).astype(bool)
+    f, fk, dense = (a.cpu().numpy().reshape(2, H, W) for a in (f, fk, dense))
+    assert 0 < m.mean() < 0.5
+    assert np.array_equal(fk, np.where(m[None], dense, 0.0))
+    assert np.array_equal(f, fk)
+    assert np.abs(dense[:, m]).max() > 0.1  # some motion on the mask
+
+
 def test_flow_empty_windows_exact_zero(ctx):
     """A window with no events has the surface 1.0 everywhere: as the
     reference its template gradient is 0, so b = 0 and no patch moves; the
