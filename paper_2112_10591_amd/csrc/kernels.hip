@@ -798,7 +798,9 @@ __device__ __forceinline__ float redf(float v) {
 // gradient; then the region of I1 covering every patch's search window at
 // its initial displacement (plus a margin) is staged, row-major, and the
 // iterations read it there (a patch whose window leaves the region reads
-// global memory; both give the same clamped samples).
+// global memory; both give the same clamped samples).  At level 0, when only
+// the masked flow is wanted, the item's patches that hold a mask pixel are
+// packed into its first waves and the others are not computed.
 template <bool B, int LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dis_level(const WinDesc one, const BatchArgs ba, int32_t total_arg,
                                                       int level) {
